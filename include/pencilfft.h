@@ -1,0 +1,217 @@
+/*
+ * pencilfft.h -- C ABI of the MI355X (gfx950) pencil 3D real-to-complex /
+ * complex-to-real FFT library.
+ *
+ * The method is the transpose-based 3D FFT of Pekurovsky, "P3DFFT: a
+ * framework for parallel computations of Fourier transforms in three
+ * dimensions" (arXiv:1905.02803): three stages of batched 1D transforms, along
+ * X (real-to-complex), then Y, then Z (complex-to-complex), with the data
+ * re-oriented from X-pencils to Y-pencils to Z-pencils between stages
+ * (Sec. 2, Fig. 2).  The backward transform runs the chain in reverse, ending
+ * in a complex-to-real transform along X (Sec. 3.2).  On one GPU the paper's
+ * pack / all-to-all / unpack steps (Sec. 3.3) become on-device reorders fused
+ * into the transform kernels' loads and stores.
+ *
+ * Conventions (Sec. 3.2, Table 1, Sec. 4.1):
+ *  - Arrays are C order, slowest index first.  The paper's Fortran storage
+ *    order "XYZ" (X fastest) is C [z][y][x].
+ *  - Real X-pencil data: float or double [nz][ny][nx], unpadded.
+ *  - Half spectrum: nxh = nx/2 + 1 complex modes along X (the paper's
+ *    (Nx+2)/2 in integer division; modes above nx/2 follow by conjugate
+ *    symmetry).  Complex values are interleaved (re, im) pairs of the plan's
+ *    precision.
+ *  - Z-pencil complex data: with stride1 = 1 (the paper's "STRIDE1 defined",
+ *    Fortran ZYX) C [nxh][ny][nz] (kz fastest); with stride1 = 0 (Fortran XYZ)
+ *    C [nz][ny][nxh].
+ *  - Forward uses exp(-2 pi i ...), backward exp(+2 pi i ...); neither is
+ *    normalised, so backward(forward(u)) = nx*ny*nz * u (Sec. 4.1: the round
+ *    trip returns the input up to a scale factor).
+ *  - Backward is the staged transform: inverse C2C along Z, then along Y, then
+ *    along X the 1D C2R that uses only the real parts of mode 0 and (even nx)
+ *    mode nx/2, the two modes Sec. 3.2 states are real.  On any output of the
+ *    forward transform this is the inverse 3D DFT.
+ *
+ * Ownership and ordering: the caller owns every data buffer (device memory);
+ * the plan owns its twiddle tables and, unless pf_set_workspace supplied one,
+ * its workspace.  Transform calls only enqueue work on the given stream
+ * (a hipStream_t; NULL means the default stream) and return at once.  A plan
+ * must not be used from two streams concurrently: its workspace is shared.
+ *
+ * Errors: every call returns PF_OK (0) or a negative PF_E* code; nothing is
+ * thrown across the ABI.  pf_strerror names a code.
+ */
+#ifndef PENCILFFT_H
+#define PENCILFFT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PF_OK 0
+#define PF_EINVAL (-1)        /* bad sizes, layout values or arguments        */
+#define PF_EUNSUPPORTED (-2)  /* length with a prime factor above 7, option
+                                 not built, or math/precision combination     */
+#define PF_EALIGN (-3)        /* data pointer not 16-byte aligned             */
+#define PF_EALIAS (-4)        /* in == out but the plan is out-of-place, or
+                                 in != out but the plan is in-place           */
+#define PF_ENOMEM (-5)        /* device allocation failed                     */
+#define PF_EWORKSPACE (-6)    /* workspace missing or too small               */
+#define PF_EHIP (-7)          /* a HIP runtime call or kernel launch failed   */
+
+/* ---- layout option values ---------------------------------------------- */
+#define PF_F32 0 /* single precision (Sec. 3.1: single and double supported) */
+#define PF_F64 1
+
+#define PF_PLAIN 0       /* FP32 / FP64 butterflies on the vector ALUs           */
+#define PF_MFMA_FP16X2 1 /* radix-16 stages as split FP16 (hi+lo) matrix products */
+#define PF_MFMA_BF16X2 2 /* radix-16 stages as split BF16 (hi+lo) matrix products */
+
+#define PF_THIRD_FFT 0   /* Fourier transform along Z (default)                 */
+#define PF_THIRD_EMPTY 1 /* no transform along Z (Sec. 3.1: empty transform)   */
+
+#define PF_PENCIL_X 0
+#define PF_PENCIL_Y 1
+#define PF_PENCIL_Z 2
+
+#define PF_DIR_FORWARD 0
+#define PF_DIR_BACKWARD 1
+
+/*
+ * Layout and options of a plan.  Initialise with pf_layout_init, then change
+ * fields.  m1 x m2 is the virtual processor grid of Sec. 2 (m1 * m2 = P; 1 x P
+ * is the slab decomposition of Sec. 4.3); the default 1 x 1 is one whole grid.
+ * stride1 selects the Table 1 storage orders (Sec. 3.2, 3.3).  useeven pads
+ * exchange blocks to equal size (Sec. 3.4).  inplace: in == out, and the
+ * buffer must hold max(real, complex) bytes; real data sits unpadded at the
+ * start of the buffer (Sec. 3.1 lists in- and out-of-place transforms).
+ */
+typedef struct pf_layout {
+    int m1, m2;     /* processor grid, each >= 1                            */
+    int stride1;    /* 1 (default) = STRIDE1 defined, 0 = undefined         */
+    int useeven;    /* 0 (default) or 1                                     */
+    int precision;  /* PF_F32 (default) or PF_F64                           */
+    int math;       /* PF_PLAIN (default), PF_MFMA_FP16X2, PF_MFMA_BF16X2   */
+    int inplace;    /* 0 (default) = out-of-place, 1 = in-place             */
+    int third;      /* PF_THIRD_FFT (default) or PF_THIRD_EMPTY             */
+    int share_only; /* reserved, must be 0                                   */
+    int r1, r2;     /* reserved, must be 0                                   */
+} pf_layout;
+
+typedef struct pf_plan pf_plan;
+
+/* Fill *l with the defaults above.  l must not be NULL. */
+void pf_layout_init(pf_layout *l);
+
+/*
+ * Host-only validation of a grid and layout; touches no GPU.  Checks sizes >= 1,
+ * the processor-grid bounds of Eq. 2 read as m1 <= min(nx/2+1, ny) and
+ * m2 <= min(ny, nz) (every rank's block in every pencil non-empty), option
+ * values, and that every length factors into 2, 3, 5 and 7.
+ * Returns PF_OK, PF_EINVAL or PF_EUNSUPPORTED.
+ */
+int pf_check(int nx, int ny, int nz, const pf_layout *l);
+
+/*
+ * Host-only: the block of rank (r1, r2) in the given pencil (Table 1), for a
+ * grid and layout that pf_check accepts.  start[3] and size[3] are the global
+ * offsets and extents of the block along (X, Y, Z) -- along X in modes for Y-
+ * and Z-pencils; order[3] lists the axes (0 = X, 1 = Y, 2 = Z) from fastest to
+ * slowest in memory.  An axis of length n split over M ranks gives rank r
+ * floor(n/M) + (r < n mod M) elements starting at r floor(n/M) + min(r, n mod M)
+ * (blocks differ by at most one, Sec. 3.4).
+ */
+int pf_query_dims(int nx, int ny, int nz, const pf_layout *l, int pencil, int r1, int r2, int start[3],
+                  int size[3], int order[3]);
+
+/*
+ * Create a plan: validates (as pf_check), factors the three lengths, builds
+ * the twiddle tables in FP64 on the host (rounded once to the plan's
+ * precision), uploads them, and allocates the workspace on the current HIP
+ * device.  On success *out holds the plan; on failure *out is NULL.
+ */
+int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out);
+
+/* pf_query_dims for the plan's grid and layout. */
+int pf_get_dims(const pf_plan *p, int pencil, int r1, int r2, int start[3], int size[3], int order[3]);
+
+/* Bytes of device workspace the plan needs (0 for a NULL plan). */
+size_t pf_workspace_bytes(const pf_plan *p);
+
+/*
+ * Use caller-owned device memory as the workspace instead of the plan's own
+ * (which is freed).  ws must be 256-byte aligned and hold at least
+ * pf_workspace_bytes(p) bytes; it must outlive the plan's use.
+ */
+int pf_set_workspace(pf_plan *p, void *ws, size_t bytes);
+
+/*
+ * Forward transform (R2C): real X-pencil `in` -> complex Z-pencil `out`
+ * (layouts above).  Out-of-place plans leave `in` unchanged.  Asynchronous on
+ * `stream`.
+ */
+int pf_ftran_r2c(pf_plan *p, const void *in, void *out, void *stream);
+
+/*
+ * Backward transform (C2R): complex Z-pencil `in` -> real X-pencil `out`,
+ * unnormalised.  Out-of-place plans leave `in` unchanged.  Asynchronous.
+ */
+int pf_btran_c2r(pf_plan *p, const void *in, void *out, void *stream);
+
+/* Free the plan's device tables and owned workspace.  NULL is accepted. */
+int pf_destroy(pf_plan *p);
+
+/* Static description of a status code. */
+const char *pf_strerror(int code);
+
+/* ---- single passes, for stage-level testing ----------------------------- */
+
+/*
+ * Number of HBM passes (kernel launches) one transform makes in direction dir
+ * (PF_DIR_FORWARD or PF_DIR_BACKWARD).
+ */
+int pf_num_passes(const pf_plan *p, int dir);
+
+/*
+ * Run pass `pass` of direction `dir` alone.  Between passes the data lives in
+ * the workspace layout: complex [nz][nkb][ny][B] where B = 128 bytes / complex
+ * size (16 for F32, 8 for F64), nkb = ceil(nxh / B), and mode kx of line
+ * (y, z) sits at [z][kx / B][y][kx % B]; slots with kx >= nxh are unused.
+ * Forward: pass 0 X stage (user real -> workspace), pass 1 Y stage (workspace
+ * in place), pass 2 Z stage (workspace -> user complex).  Backward: pass 0 Z
+ * stage (user complex -> workspace), pass 1 Y stage (in place), pass 2 X stage
+ * (workspace -> user real).  `in`/`out` that name the workspace may be any
+ * buffer of pf_workspace_bytes bytes.  pass_name writes a short static name.
+ */
+int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *stream);
+const char *pf_pass_name(const pf_plan *p, int dir, int pass);
+
+/*
+ * Algorithmic HBM bytes of one pass: every element read once and written once
+ * (real side N * s, complex side nx/2+1 modes * ny * nz * 2s).
+ */
+double pf_pass_bytes(const pf_plan *p, int dir, int pass);
+
+/* ---- per-pass timing with HIP events ------------------------------------ */
+
+/*
+ * enable != 0: every later transform call records a HIP event pair around
+ * each of its passes on the call's stream.  enable == 0 stops recording.
+ * Either way the accumulated totals are cleared.
+ */
+int pf_set_timing(pf_plan *p, int enable);
+
+/*
+ * Waits for the recorded events, then returns the summed elapsed time in
+ * milliseconds and the number of recorded launches of pass `pass` of
+ * direction `dir` since timing was enabled.
+ */
+int pf_get_timing(pf_plan *p, int dir, int pass, double *total_ms, long long *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PENCILFFT_H */

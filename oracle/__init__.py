@@ -74,6 +74,12 @@ def bind(lib):
     lib.oracle_c2r_line.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                                         ctypes.c_int, _dp]
     lib.oracle_c2r_line.restype = ctypes.c_int
+    for name in ("oracle_stage_x_r2c", "oracle_stage_x_c2r"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p, ctypes.c_int, _dp]
+        f.restype = ctypes.c_int
+    lib.oracle_stage_c2c.argtypes = [ctypes.c_int] * 3 + [_dp, ctypes.c_int, ctypes.c_int]
+    lib.oracle_stage_c2c.restype = ctypes.c_int
     return lib
 
 
@@ -150,6 +156,35 @@ def c2r3d(U: np.ndarray, nx: int, engine: str = "fft") -> np.ndarray:
     eng = {"direct": 0, "fft": 1}[engine]
     _check(_load().oracle_c2r3d_ex(eng, nx, ny, nz, U.ctypes.data, is32,
                                    u.ctypes.data_as(_dp)), "c2r3d")
+    return u
+
+
+def stage_x_r2c(u: np.ndarray) -> np.ndarray:
+    """The X stage alone: 1D R2C of every line of u[nz][ny][nx] -> [nz][ny][nxh]."""
+    u, is32 = _real_in(u)
+    nz, ny, nx = u.shape
+    U = np.empty((nz, ny, nx // 2 + 1), dtype=np.complex128)
+    _check(_load().oracle_stage_x_r2c(nx, ny, nz, u.ctypes.data, is32, U.view(np.float64).ctypes.data_as(_dp)),
+           "stage_x_r2c")
+    return U
+
+
+def stage_c2c(U: np.ndarray, nx: int, axis: str, sign: int) -> np.ndarray:
+    """One C2C stage along "y" or "z" of a copy of U[nz][ny][nxh] (sign -1 forward, +1 backward)."""
+    V = _c128(U).copy()
+    nz, ny, _ = V.shape
+    ax = {"y": 1, "z": 2}[axis]
+    _check(_load().oracle_stage_c2c(nx, ny, nz, V.view(np.float64).ctypes.data_as(_dp), ax, int(sign)),
+           "stage_c2c")
+    return V
+
+
+def stage_x_c2r(U: np.ndarray, nx: int) -> np.ndarray:
+    """The X stage of the backward transform alone: 1D C2R of every line of U[nz][ny][nxh]."""
+    U, is32 = _cplx_in(U)
+    nz, ny, _ = U.shape
+    u = np.empty((nz, ny, nx), dtype=np.float64)
+    _check(_load().oracle_stage_x_c2r(nx, ny, nz, U.ctypes.data, is32, u.ctypes.data_as(_dp)), "stage_x_c2r")
     return u
 
 

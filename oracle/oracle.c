@@ -243,17 +243,10 @@ static inline cplx cget(const void *p, int is_f32, long i) {
 
 /* ---- 3D forward: real [nz][ny][nx] -> half spectrum [nz][ny][nxh] ------ */
 
-/*
- * X stage: 1D real-to-complex transform of every (z, y) line, keeping modes
- * kx = 0 .. nx/2 (Sec. 3.2: the other modes follow from conjugate symmetry);
- * then the Y stage and the Z stage, complex-to-complex (Sec. 2, Fig. 2).
- * engine: 0 = direct DFT per axis, 1 = recursive FFT.  u is float when
- * u_is_f32, else double; U is always double.
- */
-int oracle_r2c3d_ex(int engine, int nx, int ny, int nz, const void *u, int u_is_f32, double *Uout) {
-    if (nx < 1 || ny < 1 || nz < 1 || (engine != 0 && engine != 1)) return -1;
+/* X stage: 1D real-to-complex transform of `lines` contiguous real lines of
+ * length nx, keeping modes 0 .. nx/2 of each (Sec. 3.2) */
+static int stage_x_r2c(int engine, int nx, long lines, const void *u, int u_is_f32, cplx *U) {
     int nxh = nx / 2 + 1;
-    cplx *U = (cplx *)Uout;
     cplx *w = roots_table(nx, -1);
     if (!w) return -2;
     int err = 0;
@@ -261,23 +254,36 @@ int oracle_r2c3d_ex(int engine, int nx, int ny, int nz, const void *u, int u_is_
     if (!pool) err = -2;
     if (!err) {
 #pragma omp parallel
-    {
-        cplx *a = pool + (size_t)nx * 3 * (size_t)omp_thread_id();
-        cplx *b = a + nx;
-        cplx *s = b + nx;
+        {
+            cplx *a = pool + (size_t)nx * 3 * (size_t)omp_thread_id();
+            cplx *b = a + nx;
+            cplx *s = b + nx;
 #pragma omp for schedule(static)
-        for (long L = 0; L < (long)ny * nz; ++L) {
-            for (int x = 0; x < nx; ++x) {
-                a[x].re = rget(u, u_is_f32, L * nx + x);
-                a[x].im = 0.0;
+            for (long L = 0; L < lines; ++L) {
+                for (int x = 0; x < nx; ++x) {
+                    a[x].re = rget(u, u_is_f32, L * nx + x);
+                    a[x].im = 0.0;
+                }
+                line_transform(engine, nx, a, 1, b, w, s);
+                memcpy(U + L * nxh, b, sizeof(cplx) * (size_t)nxh);
             }
-            line_transform(engine, nx, a, 1, b, w, s);
-            memcpy(U + L * nxh, b, sizeof(cplx) * (size_t)nxh);
         }
-    }
     }
     free(pool);
     free(w);
+    return err;
+}
+
+/*
+ * Forward: the X stage, then the Y stage and the Z stage, complex-to-complex
+ * (Sec. 2, Fig. 2).  engine: 0 = direct DFT per axis, 1 = recursive FFT.
+ * u is float when u_is_f32, else double; U is always double.
+ */
+int oracle_r2c3d_ex(int engine, int nx, int ny, int nz, const void *u, int u_is_f32, double *Uout) {
+    if (nx < 1 || ny < 1 || nz < 1 || (engine != 0 && engine != 1)) return -1;
+    int nxh = nx / 2 + 1;
+    cplx *U = (cplx *)Uout;
+    int err = stage_x_r2c(engine, nx, (long)ny * nz, u, u_is_f32, U);
     if (err) return err;
     if ((err = pass_y(engine, nxh, ny, nz, U, -1))) return err;
     return pass_z(engine, nxh, ny, nz, U, -1);
@@ -285,6 +291,24 @@ int oracle_r2c3d_ex(int engine, int nx, int ny, int nz, const void *u, int u_is_
 
 int oracle_r2c3d(int nx, int ny, int nz, const double *u, double *U) {
     return oracle_r2c3d_ex(1, nx, ny, nz, u, 0, U);
+}
+
+/*
+ * The stages on their own, for stage-level checks: the X stage of the forward
+ * transform (real [nz][ny][nx] -> [nz][ny][nxh], nothing else), and one C2C
+ * stage along Y (axis 1) or Z (axis 2) of a [nz][ny][nxh] array in place.
+ */
+int oracle_stage_x_r2c(int nx, int ny, int nz, const void *u, int u_is_f32, double *Uout) {
+    if (nx < 1 || ny < 1 || nz < 1) return -1;
+    return stage_x_r2c(1, nx, (long)ny * nz, u, u_is_f32, (cplx *)Uout);
+}
+
+int oracle_stage_c2c(int nx, int ny, int nz, double *U, int axis, int sign) {
+    if (nx < 1 || ny < 1 || nz < 1 || (sign != 1 && sign != -1)) return -1;
+    int nxh = nx / 2 + 1;
+    if (axis == 1) return pass_y(1, nxh, ny, nz, (cplx *)U, sign);
+    if (axis == 2) return pass_z(1, nxh, ny, nz, (cplx *)U, sign);
+    return -1;
 }
 
 /*
@@ -309,45 +333,63 @@ static void c2r_line(int engine, int nx, const cplx *c, double *out, const cplx 
     for (int x = 0; x < nx; ++x) out[x] = G[x].re;
 }
 
+/* X stage of the backward transform: 1D C2R of `lines` lines of nxh modes */
+static int stage_x_c2r(int engine, int nx, long lines, const cplx *T, double *u) {
+    int nxh = nx / 2 + 1;
+    cplx *w = roots_table(nx, +1);
+    if (!w) return -2;
+    int err = 0;
+    cplx *pool = (cplx *)malloc(sizeof(cplx) * (size_t)nx * 3 * (size_t)oracle_num_threads());
+    if (!pool) err = -2;
+    if (!err) {
+#pragma omp parallel
+        {
+            cplx *F = pool + (size_t)nx * 3 * (size_t)omp_thread_id();
+            cplx *G = F + nx;
+            cplx *s = G + nx;
+#pragma omp for schedule(static)
+            for (long L = 0; L < lines; ++L) c2r_line(engine, nx, T + L * nxh, u + L * nx, w, F, G, s);
+        }
+    }
+    free(pool);
+    free(w);
+    return err;
+}
+
+static cplx *promote_complex(const void *U, int U_is_f32, long M) {
+    cplx *T = (cplx *)malloc(sizeof(cplx) * (size_t)M);
+    if (!T) return NULL;
+    for (long i = 0; i < M; ++i) T[i] = cget(U, U_is_f32, i);
+    return T;
+}
+
 /* ---- 3D backward (staged): [nz][ny][nxh] -> real [nz][ny][nx] ---------- */
 int oracle_c2r3d_ex(int engine, int nx, int ny, int nz, const void *Uin, int U_is_f32, double *u) {
     if (nx < 1 || ny < 1 || nz < 1 || (engine != 0 && engine != 1)) return -1;
     int nxh = nx / 2 + 1;
     long M = (long)nxh * ny * nz;
-    cplx *T = (cplx *)malloc(sizeof(cplx) * (size_t)M);
+    cplx *T = promote_complex(Uin, U_is_f32, M);
     if (!T) return -2;
-    for (long i = 0; i < M; ++i) T[i] = cget(Uin, U_is_f32, i);
     int err = pass_z(engine, nxh, ny, nz, T, +1);
     if (!err) err = pass_y(engine, nxh, ny, nz, T, +1);
-    if (err) {
-        free(T);
-        return err;
-    }
-    cplx *w = roots_table(nx, +1);
-    if (!w) {
-        free(T);
-        return -2;
-    }
-    cplx *pool = (cplx *)malloc(sizeof(cplx) * (size_t)nx * 3 * (size_t)oracle_num_threads());
-    if (!pool) err = -2;
-    if (!err) {
-#pragma omp parallel
-    {
-        cplx *F = pool + (size_t)nx * 3 * (size_t)omp_thread_id();
-        cplx *G = F + nx;
-        cplx *s = G + nx;
-#pragma omp for schedule(static)
-        for (long L = 0; L < (long)ny * nz; ++L) c2r_line(engine, nx, T + L * nxh, u + L * nx, w, F, G, s);
-    }
-    }
-    free(pool);
-    free(w);
+    if (!err) err = stage_x_c2r(engine, nx, (long)ny * nz, T, u);
     free(T);
     return err;
 }
 
 int oracle_c2r3d(int nx, int ny, int nz, const double *U, double *u) {
     return oracle_c2r3d_ex(1, nx, ny, nz, U, 0, u);
+}
+
+/* the X stage of the backward transform alone: 1D C2R of every line */
+int oracle_stage_x_c2r(int nx, int ny, int nz, const void *U, int U_is_f32, double *u) {
+    if (nx < 1 || ny < 1 || nz < 1) return -1;
+    long lines = (long)ny * nz;
+    cplx *T = promote_complex(U, U_is_f32, lines * (nx / 2 + 1));
+    if (!T) return -2;
+    int err = stage_x_c2r(1, nx, lines, T, u);
+    free(T);
+    return err;
 }
 
 /* ---- sampled exact values, for grids too large for a whole transform ---- */

@@ -1,0 +1,358 @@
+"""Python binding of the MI355X pencil 3D R2C / C2R FFT library (libpencilfft.so).
+
+Argument marshalling only: every step of a transform runs in the library's
+HIP kernels; PyTorch supplies device memory and streams.  The functions named
+``pf_*`` mirror the C ABI in include/pencilfft.h one to one; ``Plan`` wraps a
+plan handle for convenience.  There is no fallback: if the library is not
+built, importing the binding's functions raises.
+
+Layouts (C order, slowest index first; Table 1 of the paper):
+  real X-pencil            [nz][ny][nx]
+  Z-pencil, stride1 = 1    [nxh][ny][nz]  complex, nxh = nx // 2 + 1
+  Z-pencil, stride1 = 0    [nz][ny][nxh]  complex
+Forward and backward are unnormalised: btran(ftran(u)) = nx*ny*nz * u.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpencilfft.so")
+
+PF_OK = 0
+PF_EINVAL = -1
+PF_EUNSUPPORTED = -2
+PF_EALIGN = -3
+PF_EALIAS = -4
+PF_ENOMEM = -5
+PF_EWORKSPACE = -6
+PF_EHIP = -7
+
+PF_F32, PF_F64 = 0, 1
+PF_PLAIN, PF_MFMA_FP16X2, PF_MFMA_BF16X2 = 0, 1, 2
+PF_THIRD_FFT, PF_THIRD_EMPTY = 0, 1
+PF_PENCIL_X, PF_PENCIL_Y, PF_PENCIL_Z = 0, 1, 2
+PF_DIR_FORWARD, PF_DIR_BACKWARD = 0, 1
+
+EXPORTED = (
+    "pf_layout_init", "pf_check", "pf_query_dims", "pf_setup", "pf_get_dims", "pf_workspace_bytes",
+    "pf_set_workspace", "pf_ftran_r2c", "pf_btran_c2r", "pf_destroy", "pf_strerror", "pf_num_passes",
+    "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing",
+)
+
+
+class PfError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {pf_strerror(code)} (code {code})")
+        self.code = code
+
+
+class pf_layout(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int) for name in (
+        "m1", "m2", "stride1", "useeven", "precision", "math", "inplace", "third", "share_only", "r1", "r2")]
+
+
+@dataclass
+class Layout:
+    """Plan options; field meanings as in include/pencilfft.h."""
+    m1: int = 1
+    m2: int = 1
+    stride1: int = 1
+    useeven: int = 0
+    precision: int = PF_F32
+    math: int = PF_PLAIN
+    inplace: int = 0
+    third: int = PF_THIRD_FFT
+    share_only: int = 0
+    r1: int = 0
+    r2: int = 0
+
+    def c(self) -> pf_layout:
+        return pf_layout(*[int(getattr(self, f[0])) for f in pf_layout._fields_])
+
+
+_lib = None
+_ip3 = ctypes.c_int * 3
+
+
+def lib():
+    """Load libpencilfft.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1905_02803_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        lp = ctypes.POINTER(pf_layout)
+        ip = ctypes.POINTER(ctypes.c_int)
+        sig = {
+            "pf_layout_init": (None, [lp]),
+            "pf_check": (i, [i, i, i, lp]),
+            "pf_query_dims": (i, [i, i, i, lp, i, i, i, ip, ip, ip]),
+            "pf_setup": (i, [i, i, i, lp, ctypes.POINTER(vp)]),
+            "pf_get_dims": (i, [vp, i, i, i, ip, ip, ip]),
+            "pf_workspace_bytes": (sz, [vp]),
+            "pf_set_workspace": (i, [vp, vp, sz]),
+            "pf_ftran_r2c": (i, [vp, vp, vp, vp]),
+            "pf_btran_c2r": (i, [vp, vp, vp, vp]),
+            "pf_destroy": (i, [vp]),
+            "pf_strerror": (ctypes.c_char_p, [i]),
+            "pf_num_passes": (i, [vp, i]),
+            "pf_run_pass": (i, [vp, i, i, vp, vp, vp]),
+            "pf_pass_name": (ctypes.c_char_p, [vp, i, i]),
+            "pf_pass_bytes": (ctypes.c_double, [vp, i, i]),
+            "pf_set_timing": (i, [vp, i]),
+            "pf_get_timing": (i, [vp, i, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _raise(code: int, what: str) -> None:
+    if code != PF_OK:
+        raise PfError(code, what)
+
+
+# ---- one-to-one wrappers of the C ABI -------------------------------------
+
+def pf_strerror(code: int) -> str:
+    return lib().pf_strerror(int(code)).decode()
+
+
+def pf_layout_init() -> Layout:
+    c = pf_layout()
+    lib().pf_layout_init(ctypes.byref(c))
+    return Layout(*[getattr(c, f[0]) for f in pf_layout._fields_])
+
+
+def pf_check(nx: int, ny: int, nz: int, layout: Layout | None = None) -> int:
+    """Host-only validation; returns the status code (0 = accepted)."""
+    c = (layout or Layout()).c()
+    return int(lib().pf_check(nx, ny, nz, ctypes.byref(c)))
+
+
+def pf_query_dims(nx, ny, nz, layout, pencil, r1=0, r2=0):
+    """Host-only Table 1 block of rank (r1, r2): (start, size, order) along (X, Y, Z)."""
+    c = (layout or Layout()).c()
+    st, sz, od = _ip3(), _ip3(), _ip3()
+    _raise(lib().pf_query_dims(nx, ny, nz, ctypes.byref(c), pencil, r1, r2, st, sz, od), "pf_query_dims")
+    return tuple(st), tuple(sz), tuple(od)
+
+
+def pf_setup(nx: int, ny: int, nz: int, layout: Layout | None = None) -> int:
+    c = (layout or Layout()).c()
+    h = ctypes.c_void_p()
+    _raise(lib().pf_setup(nx, ny, nz, ctypes.byref(c), ctypes.byref(h)), "pf_setup")
+    return h.value
+
+
+def pf_destroy(h) -> None:
+    _raise(lib().pf_destroy(h), "pf_destroy")
+
+
+def pf_ftran_r2c(h, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _raise(lib().pf_ftran_r2c(h, in_ptr, out_ptr, stream), "pf_ftran_r2c")
+
+
+def pf_btran_c2r(h, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _raise(lib().pf_btran_c2r(h, in_ptr, out_ptr, stream), "pf_btran_c2r")
+
+
+def pf_run_pass(h, direction: int, pass_index: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _raise(lib().pf_run_pass(h, direction, pass_index, in_ptr, out_ptr, stream), "pf_run_pass")
+
+
+def pf_workspace_bytes(h) -> int:
+    return int(lib().pf_workspace_bytes(h))
+
+
+def pf_set_workspace(h, ptr: int, nbytes: int) -> None:
+    _raise(lib().pf_set_workspace(h, ptr, nbytes), "pf_set_workspace")
+
+
+def pf_num_passes(h, direction: int) -> int:
+    return int(lib().pf_num_passes(h, direction))
+
+
+def pf_pass_name(h, direction: int, pass_index: int) -> str:
+    return lib().pf_pass_name(h, direction, pass_index).decode()
+
+
+def pf_pass_bytes(h, direction: int, pass_index: int) -> float:
+    return float(lib().pf_pass_bytes(h, direction, pass_index))
+
+
+def pf_set_timing(h, enable: bool) -> None:
+    _raise(lib().pf_set_timing(h, int(bool(enable))), "pf_set_timing")
+
+
+def pf_get_timing(h, direction: int, pass_index: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _raise(lib().pf_get_timing(h, direction, pass_index, ctypes.byref(ms), ctypes.byref(n)), "pf_get_timing")
+    return ms.value, n.value
+
+
+def pf_get_dims(h, pencil, r1=0, r2=0):
+    st, sz, od = _ip3(), _ip3(), _ip3()
+    _raise(lib().pf_get_dims(h, pencil, r1, r2, st, sz, od), "pf_get_dims")
+    return tuple(st), tuple(sz), tuple(od)
+
+
+# ---- convenience wrapper ----------------------------------------------------
+
+def _stream_handle(stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Plan:
+    """A plan for one grid; tensors in, tensors out, on torch's current stream."""
+
+    def __init__(self, nx: int, ny: int, nz: int, layout: Layout | None = None, **opts):
+        self.layout = layout or Layout(**opts)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.nxh = self.nx // 2 + 1
+        self.handle = pf_setup(self.nx, self.ny, self.nz, self.layout)
+
+    # shapes and dtypes
+    @property
+    def real_dtype(self):
+        import torch
+
+        return torch.float64 if self.layout.precision == PF_F64 else torch.float32
+
+    @property
+    def complex_dtype(self):
+        import torch
+
+        return torch.complex128 if self.layout.precision == PF_F64 else torch.complex64
+
+    @property
+    def real_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def complex_shape(self):
+        if self.layout.stride1:
+            return (self.nxh, self.ny, self.nz)
+        return (self.nz, self.ny, self.nxh)
+
+    def empty_real(self, device="cuda"):
+        import torch
+
+        return torch.empty(self.real_shape, dtype=self.real_dtype, device=device)
+
+    def empty_complex(self, device="cuda"):
+        import torch
+
+        return torch.empty(self.complex_shape, dtype=self.complex_dtype, device=device)
+
+    def _check_tensor(self, t, shape, dtype, what):
+        if not t.is_cuda or t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{what} must be a contiguous {dtype} CUDA tensor of shape {shape}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+    def ftran(self, u, out=None, stream=None):
+        """Forward R2C: real [nz][ny][nx] -> complex Z-pencil (returned)."""
+        self._check_tensor(u, self.real_shape, self.real_dtype, "input")
+        if out is None:
+            out = self.empty_complex(u.device)
+        self._check_tensor(out, self.complex_shape, self.complex_dtype, "output")
+        pf_ftran_r2c(self.handle, u.data_ptr(), out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def btran(self, U, out=None, stream=None):
+        """Backward C2R: complex Z-pencil -> real [nz][ny][nx] (unnormalised)."""
+        self._check_tensor(U, self.complex_shape, self.complex_dtype, "input")
+        if out is None:
+            out = self.empty_real(U.device)
+        self._check_tensor(out, self.real_shape, self.real_dtype, "output")
+        pf_btran_c2r(self.handle, U.data_ptr(), out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def ftran_inplace(self, buf, stream=None):
+        """In-place forward on a buffer tensor holding max(real, complex) bytes."""
+        pf_ftran_r2c(self.handle, buf.data_ptr(), buf.data_ptr(), _stream_handle(stream))
+        return buf
+
+    def btran_inplace(self, buf, stream=None):
+        pf_btran_c2r(self.handle, buf.data_ptr(), buf.data_ptr(), _stream_handle(stream))
+        return buf
+
+    def run_pass(self, direction, index, src, dst, stream=None):
+        pf_run_pass(self.handle, direction, index, src.data_ptr(), dst.data_ptr(), _stream_handle(stream))
+        return dst
+
+    @property
+    def workspace_bytes(self) -> int:
+        return pf_workspace_bytes(self.handle)
+
+    def num_passes(self, direction: int) -> int:
+        return pf_num_passes(self.handle, direction)
+
+    def pass_name(self, direction: int, index: int) -> str:
+        return pf_pass_name(self.handle, direction, index)
+
+    def pass_bytes(self, direction: int, index: int) -> float:
+        return pf_pass_bytes(self.handle, direction, index)
+
+    def set_timing(self, enable: bool) -> None:
+        pf_set_timing(self.handle, enable)
+
+    def get_timing(self, direction: int, index: int):
+        return pf_get_timing(self.handle, direction, index)
+
+    def dims(self, pencil, r1=0, r2=0):
+        return pf_get_dims(self.handle, pencil, r1, r2)
+
+    def destroy(self) -> None:
+        if getattr(self, "handle", None):
+            pf_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def workspace_to_half_spectrum(ws, nx: int, ny: int, nz: int):
+    """View a workspace buffer (the layout between passes, see pf_run_pass) as [nz][ny][nxh].
+
+    Pure index permutation for tests; ws is a tensor of the plan's complex dtype
+    with nz * nkb * ny * B elements.
+    """
+    nxh = nx // 2 + 1
+    B = 128 // ws.element_size()
+    nkb = (nxh + B - 1) // B
+    w = ws.reshape(nz, nkb, ny, B).permute(0, 2, 1, 3).reshape(nz, ny, nkb * B)
+    return w[:, :, :nxh]
+
+
+def half_spectrum_to_workspace(U, ws):
+    """Inverse of workspace_to_half_spectrum: scatter U[nz][ny][nxh] into the workspace layout."""
+    nz, ny, nxh = U.shape
+    B = 128 // ws.element_size()
+    nkb = (nxh + B - 1) // B
+    w = ws.reshape(nz, nkb, ny, B)
+    full = U.new_zeros((nz, ny, nkb * B))
+    full[:, :, :nxh] = U
+    w.copy_(full.reshape(nz, ny, nkb, B).permute(0, 2, 1, 3))
+    return ws

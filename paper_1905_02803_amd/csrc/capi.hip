@@ -1,0 +1,564 @@
+// capi.hip -- host side of the pencil 3D FFT library: validation, Table 1
+// layout arithmetic, radix plans, twiddle tables, workspace and the pass
+// chain behind the C ABI of include/pencilfft.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pencilfft.h"
+#include "pf_internal.h"
+
+using pf::FftSpec;
+using pf::PassArgs;
+using pf::PassDesc;
+using pf::Side;
+
+namespace {
+
+constexpr int kPasses = 3;
+constexpr size_t kLdsBudget = 80 * 1024;  // two workgroups per CU fit in 160 KB
+
+struct EventPair {
+    hipEvent_t start, stop;
+};
+
+struct PassTiming {
+    std::vector<EventPair> used;
+};
+
+}  // namespace
+
+struct pf_plan {
+    int nx, ny, nz, nxh;
+    pf_layout lay;
+    int csize;  // bytes per complex value
+    int B, b_log2, nkb;
+    FftSpec fx, fy, fz;
+    void *tw_dev;  // one allocation holding the x, y, z tables
+    size_t tw_off[3];
+    void *ws;
+    size_t ws_bytes;
+    bool own_ws;
+    int npass[2];
+    PassDesc pass[2][kPasses];
+    const char *pass_names[2][kPasses];
+    double pass_bytes[2][kPasses];
+    bool timing;
+    PassTiming tim[2][kPasses];
+    std::vector<EventPair> pool;
+};
+
+namespace {
+
+int ilog2(long long v) {
+    int r = 0;
+    while ((1LL << r) < v) ++r;
+    return r;
+}
+
+bool valid_layout_values(const pf_layout *l) {
+    if (l->m1 < 1 || l->m2 < 1) return false;
+    if (l->stride1 != 0 && l->stride1 != 1) return false;
+    if (l->useeven != 0 && l->useeven != 1) return false;
+    if (l->precision != PF_F32 && l->precision != PF_F64) return false;
+    if (l->math != PF_PLAIN && l->math != PF_MFMA_FP16X2 && l->math != PF_MFMA_BF16X2) return false;
+    if (l->inplace != 0 && l->inplace != 1) return false;
+    if (l->third != PF_THIRD_FFT && l->third != PF_THIRD_EMPTY) return false;
+    if (l->share_only != 0 || l->r1 != 0 || l->r2 != 0) return false;
+    return true;
+}
+
+// Radix plan: 16s first, then 8, 4, 2, then 3, 5, 7 (returns false for other primes).
+bool factor_length(int n, FftSpec *fs) {
+    std::memset(fs, 0, sizeof(*fs));
+    fs->n = n;
+    int m = n, s = 0;
+    const int order[] = {16, 8, 4, 2, 3, 5, 7};
+    for (int r : order) {
+        while (m % r == 0 && m > 1) {
+            if (s >= pf::kMaxStages) return false;
+            fs->radix[s++] = r;
+            m /= r;
+        }
+    }
+    if (m != 1) return false;
+    fs->nstages = s;
+    int off = 0, Ns = 1;
+    for (int i = 0; i < s; ++i) {
+        fs->twoff[i] = off;
+        off += Ns * (fs->radix[i] - 1);
+        Ns *= fs->radix[i];
+    }
+    return true;
+}
+
+// Stage twiddles W_{Ns R}^{r k} = exp(-2 pi i ((r k) mod L) / L), L = Ns R,
+// computed in FP64 from the reduced integer phase, rounded once.
+template <typename T>
+void build_twiddles(const FftSpec &fs, std::vector<T> &out) {
+    int total = 0, Ns = 1;
+    for (int s = 0; s < fs.nstages; ++s) {
+        total += Ns * (fs.radix[s] - 1);
+        Ns *= fs.radix[s];
+    }
+    out.assign(2 * (size_t)(total > 0 ? total : 1), T(0));
+    Ns = 1;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int s = 0; s < fs.nstages; ++s) {
+        const int R = fs.radix[s];
+        const long long L = (long long)Ns * R;
+        for (int k = 0; k < Ns; ++k)
+            for (int r = 1; r < R; ++r) {
+                const long long m = ((long long)r * k) % L;
+                const double ang = two_pi * (double)m / (double)L;
+                const size_t i = (size_t)fs.twoff[s] + (size_t)k * (R - 1) + (r - 1);
+                out[2 * i] = (T)std::cos(ang);
+                out[2 * i + 1] = (T)(-std::sin(ang));
+            }
+        Ns *= R;
+    }
+}
+
+void block_split(int n, int M, int r, int *start, int *size) {
+    const int q = n / M, rem = n % M;
+    *size = q + (r < rem ? 1 : 0);
+    *start = r * q + (r < rem ? r : rem);
+}
+
+// Threads per column (power of two, >= n / kEMax) and columns per tile.
+void choose_tile(int n, int csize, int max_tc, int *tc_log2, int *wpc_log2, int *pitch, size_t *lds) {
+    const int emax = csize == 16 ? pf::kEMax / 2 : pf::kEMax;  // elements per thread (F64 halves it)
+    int wpc = 1;
+    while (wpc * emax < n) wpc <<= 1;
+    if (wpc > 1024) wpc = 1024;
+    const int p = pf::pidx(n - 1) + 1;
+    int tc = 1;
+    while (tc * 2 <= max_tc && tc * 2 * wpc <= 512 && (size_t)(tc * 2) * p * csize <= kLdsBudget) tc <<= 1;
+    *tc_log2 = ilog2(tc);
+    *wpc_log2 = ilog2(wpc);
+    *pitch = p;
+    *lds = (size_t)tc * p * csize;
+}
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return PF_OK;
+    if (e == hipErrorOutOfMemory) return PF_ENOMEM;
+    return PF_EHIP;
+}
+
+int check_impl(int nx, int ny, int nz, const pf_layout *l) {
+    if (!l) return PF_EINVAL;
+    if (nx < 1 || ny < 1 || nz < 1) return PF_EINVAL;
+    if (!valid_layout_values(l)) return PF_EINVAL;
+    const int nxh = nx / 2 + 1;
+    // Eq. 2 read as: every rank's block of every pencil is non-empty.
+    if (l->m1 > nxh || l->m1 > ny || l->m2 > ny || l->m2 > nz) return PF_EINVAL;
+    FftSpec f;
+    if (!factor_length(nx, &f) || !factor_length(ny, &f) || !factor_length(nz, &f)) return PF_EUNSUPPORTED;
+    const int maxn = l->precision == PF_F64 ? 4096 : 8192;
+    if (nx > maxn || ny > maxn || nz > maxn) return PF_EUNSUPPORTED;
+    return PF_OK;
+}
+
+// Options accepted by pf_check but not built into the transform yet.
+int built_options(const pf_layout *l) {
+    if (l->m1 != 1 || l->m2 != 1) return PF_EUNSUPPORTED;
+    if (l->math != PF_PLAIN) return PF_EUNSUPPORTED;
+    if (l->third != PF_THIRD_FFT) return PF_EUNSUPPORTED;
+    if (l->useeven) return PF_EUNSUPPORTED;
+    return PF_OK;
+}
+
+void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc) {
+    d.kind = pf::PASS_C2C;
+    d.dir = dir;
+    d.prec = p->lay.precision;
+    PassArgs &a = d.a;
+    std::memset(&a, 0, sizeof(a));
+    a.fft = fs;
+    a.tw = (const char *)p->tw_dev + twoff;
+    choose_tile(fs.n, p->csize, max_tc, &a.tc_log2, &a.wpc_log2, &a.pitch, &d.lds);
+    d.threads = 1u << (a.tc_log2 + a.wpc_log2);
+    a.C = p->nxh;
+}
+
+// Blocked workspace side seen by a C2C pass whose tile rows run along
+// `axis_stride` (B for Y, nkb ny B for Z) and whose outer index moves by sa.
+Side ws_side(const pf_plan *p, long long sa, long long sp, int tc_log2) {
+    Side s;
+    s.sa = sa;
+    s.sblk = (long long)p->ny * p->B;
+    s.sc = 1;
+    s.sp = sp;
+    s.cpb = p->B >> tc_log2;
+    return s;
+}
+
+// User Z-pencil side: STRIDE1 [nxh][ny][nz] or [nz][ny][nxh]; outer index y.
+Side user_side(const pf_plan *p, long long CB) {
+    Side s;
+    if (p->lay.stride1) {
+        s.sa = p->nz;
+        s.sc = (long long)p->ny * p->nz;
+        s.sp = 1;
+    } else {
+        s.sa = p->nxh;
+        s.sc = 1;
+        s.sp = (long long)p->ny * p->nxh;
+    }
+    s.sblk = 0;
+    s.cpb = CB;
+    return s;
+}
+
+void build_passes(pf_plan *p) {
+    const long long nyB = (long long)p->ny * p->B;
+    const long long zstride = (long long)p->nkb * nyB;
+    const double rs = p->lay.precision == PF_F64 ? 8.0 : 4.0;
+    const double N = (double)p->nx * p->ny * p->nz;
+    const double M = (double)p->nxh * p->ny * p->nz;
+    for (int dir = 0; dir < 2; ++dir) {
+        const int sgn = dir == 0 ? -1 : 1;
+        // X stage
+        PassDesc x;
+        std::memset(&x, 0, sizeof(x));
+        x.kind = dir == 0 ? pf::PASS_R2C_X : pf::PASS_C2R_X;
+        x.dir = sgn;
+        x.prec = p->lay.precision;
+        x.a.fft = p->fx;
+        x.a.tw = (const char *)p->tw_dev + p->tw_off[0];
+        choose_tile(p->nx, p->csize, 64, &x.a.tc_log2, &x.a.wpc_log2, &x.a.pitch, &x.lds);
+        x.threads = 1u << (x.a.tc_log2 + x.a.wpc_log2);
+        x.a.lines = (long long)p->ny * p->nz;
+        x.a.ld_real = p->nx;
+        x.a.ny = p->ny;
+        x.a.nkb = p->nkb;
+        x.a.b_log2 = p->b_log2;
+        x.a.nxh = p->nxh;
+        const long long pairs = (x.a.lines + 1) / 2;
+        const long long tcx = 1LL << x.a.tc_log2;
+        x.blocks = (unsigned)((pairs + tcx - 1) / tcx);
+        // Y stage: in place on the workspace, tile (z, column block)
+        PassDesc y;
+        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B);
+        y.a.in_s = ws_side(p, zstride, p->B, y.a.tc_log2);
+        y.a.out_s = y.a.in_s;
+        y.a.A = p->nz;
+        y.a.CB = (long long)p->nkb * (p->B >> y.a.tc_log2);
+        y.blocks = (unsigned)(y.a.A * y.a.CB);
+        // Z stage: tile (y, column block)
+        PassDesc z;
+        set_c2c_common(z, p, p->fz, p->tw_off[2], sgn, p->B);
+        z.a.A = p->ny;
+        z.a.CB = (long long)p->nkb * (p->B >> z.a.tc_log2);
+        const Side wsz = ws_side(p, p->B, zstride, z.a.tc_log2);
+        const Side usr = user_side(p, z.a.CB);
+        z.a.in_s = dir == 0 ? wsz : usr;
+        z.a.out_s = dir == 0 ? usr : wsz;
+        z.blocks = (unsigned)(z.a.A * z.a.CB);
+
+        const double cbytes = M * 2 * rs;
+        if (dir == 0) {
+            p->pass[0][0] = x;
+            p->pass[0][1] = y;
+            p->pass[0][2] = z;
+            p->pass_names[0][0] = "fwd_x_r2c";
+            p->pass_names[0][1] = "fwd_y_c2c";
+            p->pass_names[0][2] = "fwd_z_c2c";
+            p->pass_bytes[0][0] = N * rs + cbytes;
+            p->pass_bytes[0][1] = 2 * cbytes;
+            p->pass_bytes[0][2] = 2 * cbytes;
+        } else {
+            p->pass[1][0] = z;
+            p->pass[1][1] = y;
+            p->pass[1][2] = x;
+            p->pass_names[1][0] = "bwd_z_c2c";
+            p->pass_names[1][1] = "bwd_y_c2c";
+            p->pass_names[1][2] = "bwd_x_c2r";
+            p->pass_bytes[1][0] = 2 * cbytes;
+            p->pass_bytes[1][1] = 2 * cbytes;
+            p->pass_bytes[1][2] = N * rs + cbytes;
+        }
+        p->npass[dir] = kPasses;
+    }
+}
+
+EventPair take_events(pf_plan *p) {
+    if (!p->pool.empty()) {
+        EventPair e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    EventPair e{nullptr, nullptr};
+    if (hipEventCreate(&e.start) != hipSuccess) e.start = nullptr;
+    if (hipEventCreate(&e.stop) != hipSuccess) e.stop = nullptr;
+    return e;
+}
+
+void release_timing(pf_plan *p) {
+    for (int d = 0; d < 2; ++d)
+        for (int i = 0; i < kPasses; ++i) {
+            for (auto &e : p->tim[d][i].used) p->pool.push_back(e);
+            p->tim[d][i].used.clear();
+        }
+}
+
+// Set the buffers of pass i of direction dir and enqueue it.
+int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s) {
+    PassDesc d = p->pass[dir][i];
+    d.a.in = in;
+    d.a.out = out;
+    EventPair ev{nullptr, nullptr};
+    if (p->timing) {
+        ev = take_events(p);
+        if (ev.start && ev.stop) hipEventRecord(ev.start, s);
+    }
+    hipError_t e = pf::launch_pass(d, s);
+    if (p->timing && ev.start && ev.stop) {
+        hipEventRecord(ev.stop, s);
+        p->tim[dir][i].used.push_back(ev);
+    }
+    return hip_status(e);
+}
+
+bool aligned16(const void *ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
+int check_call(const pf_plan *p, const void *in, const void *out) {
+    if (!p || !in || !out) return PF_EINVAL;
+    if (!aligned16(in) || !aligned16(out)) return PF_EALIGN;
+    if (p->lay.inplace && in != out) return PF_EALIAS;
+    if (!p->lay.inplace && in == out) return PF_EALIAS;
+    if (!p->ws) return PF_EWORKSPACE;
+    return PF_OK;
+}
+
+int run_chain(pf_plan *p, int dir, const void *in, void *out, void *stream) {
+    const int rc = check_call(p, in, out);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // pass 0: user -> workspace; pass 1: workspace in place; pass 2: workspace -> user
+    int r = run_one(p, dir, 0, in, p->ws, s);
+    if (!r) r = run_one(p, dir, 1, p->ws, p->ws, s);
+    if (!r) r = run_one(p, dir, 2, p->ws, out, s);
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pf_layout_init(pf_layout *l) {
+    if (!l) return;
+    std::memset(l, 0, sizeof(*l));
+    l->m1 = 1;
+    l->m2 = 1;
+    l->stride1 = 1;
+    l->precision = PF_F32;
+    l->math = PF_PLAIN;
+    l->third = PF_THIRD_FFT;
+}
+
+int pf_check(int nx, int ny, int nz, const pf_layout *l) { return check_impl(nx, ny, nz, l); }
+
+int pf_query_dims(int nx, int ny, int nz, const pf_layout *l, int pencil, int r1, int r2, int start[3],
+                  int size[3], int order[3]) {
+    const int rc = check_impl(nx, ny, nz, l);
+    if (rc) return rc;
+    if (!start || !size || !order) return PF_EINVAL;
+    if (r1 < 0 || r1 >= l->m1 || r2 < 0 || r2 >= l->m2) return PF_EINVAL;
+    const int nxh = nx / 2 + 1;
+    int s0, n0, s1, n1, s2, n2;
+    switch (pencil) {
+        case PF_PENCIL_X:  // X whole, Y over M1, Z over M2; order XYZ
+            s0 = 0, n0 = nx;
+            block_split(ny, l->m1, r1, &s1, &n1);
+            block_split(nz, l->m2, r2, &s2, &n2);
+            order[0] = 0, order[1] = 1, order[2] = 2;
+            break;
+        case PF_PENCIL_Y:  // X modes over M1, Y whole, Z over M2; YXZ or XYZ
+            block_split(nxh, l->m1, r1, &s0, &n0);
+            s1 = 0, n1 = ny;
+            block_split(nz, l->m2, r2, &s2, &n2);
+            if (l->stride1)
+                order[0] = 1, order[1] = 0, order[2] = 2;
+            else
+                order[0] = 0, order[1] = 1, order[2] = 2;
+            break;
+        case PF_PENCIL_Z:  // X modes over M1, Y over M2, Z whole; ZYX or XYZ
+            block_split(nxh, l->m1, r1, &s0, &n0);
+            block_split(ny, l->m2, r2, &s1, &n1);
+            s2 = 0, n2 = nz;
+            if (l->stride1)
+                order[0] = 2, order[1] = 1, order[2] = 0;
+            else
+                order[0] = 0, order[1] = 1, order[2] = 2;
+            break;
+        default:
+            return PF_EINVAL;
+    }
+    start[0] = s0, start[1] = s1, start[2] = s2;
+    size[0] = n0, size[1] = n1, size[2] = n2;
+    return PF_OK;
+}
+
+int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
+    if (!out) return PF_EINVAL;
+    *out = nullptr;
+    int rc = check_impl(nx, ny, nz, l);
+    if (rc) return rc;
+    rc = built_options(l);
+    if (rc) return rc;
+    pf_plan *p = new (std::nothrow) pf_plan();
+    if (!p) return PF_ENOMEM;
+    p->nx = nx, p->ny = ny, p->nz = nz, p->nxh = nx / 2 + 1;
+    p->lay = *l;
+    p->csize = l->precision == PF_F64 ? 16 : 8;
+    p->B = 128 / p->csize;
+    p->b_log2 = ilog2(p->B);
+    p->nkb = (p->nxh + p->B - 1) / p->B;
+    factor_length(nx, &p->fx);
+    factor_length(ny, &p->fy);
+    factor_length(nz, &p->fz);
+
+    // twiddle tables, one allocation, each table 256-byte aligned
+    std::vector<unsigned char> host;
+    const FftSpec *specs[3] = {&p->fx, &p->fy, &p->fz};
+    for (int i = 0; i < 3; ++i) {
+        p->tw_off[i] = host.size();
+        if (l->precision == PF_F64) {
+            std::vector<double> t;
+            build_twiddles<double>(*specs[i], t);
+            const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
+            host.insert(host.end(), b, b + t.size() * sizeof(double));
+        } else {
+            std::vector<float> t;
+            build_twiddles<float>(*specs[i], t);
+            const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
+            host.insert(host.end(), b, b + t.size() * sizeof(float));
+        }
+        host.resize((host.size() + 255) & ~(size_t)255, 0);
+    }
+    hipError_t e = hipMalloc(&p->tw_dev, host.size());
+    if (e != hipSuccess) {
+        delete p;
+        return hip_status(e);
+    }
+    e = hipMemcpy(p->tw_dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = pf::prepare_kernels(pf::kMaxLds);
+    if (e != hipSuccess) {
+        hipFree(p->tw_dev);
+        delete p;
+        return hip_status(e);
+    }
+    p->ws_bytes = (size_t)p->nz * p->nkb * p->ny * p->B * p->csize;
+    e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+        hipFree(p->tw_dev);
+        delete p;
+        return hip_status(e);
+    }
+    p->own_ws = true;
+    build_passes(p);
+    *out = p;
+    return PF_OK;
+}
+
+int pf_get_dims(const pf_plan *p, int pencil, int r1, int r2, int start[3], int size[3], int order[3]) {
+    if (!p) return PF_EINVAL;
+    return pf_query_dims(p->nx, p->ny, p->nz, &p->lay, pencil, r1, r2, start, size, order);
+}
+
+size_t pf_workspace_bytes(const pf_plan *p) { return p ? p->ws_bytes : 0; }
+
+int pf_set_workspace(pf_plan *p, void *ws, size_t bytes) {
+    if (!p || !ws) return PF_EINVAL;
+    if (((uintptr_t)ws & 255u) != 0) return PF_EALIGN;
+    if (bytes < p->ws_bytes) return PF_EWORKSPACE;
+    if (p->own_ws && p->ws) hipFree(p->ws);
+    p->ws = ws;
+    p->own_ws = false;
+    return PF_OK;
+}
+
+int pf_ftran_r2c(pf_plan *p, const void *in, void *out, void *stream) { return run_chain(p, 0, in, out, stream); }
+
+int pf_btran_c2r(pf_plan *p, const void *in, void *out, void *stream) { return run_chain(p, 1, in, out, stream); }
+
+int pf_destroy(pf_plan *p) {
+    if (!p) return PF_OK;
+    release_timing(p);
+    for (auto &e : p->pool) {
+        if (e.start) hipEventDestroy(e.start);
+        if (e.stop) hipEventDestroy(e.stop);
+    }
+    if (p->own_ws && p->ws) hipFree(p->ws);
+    if (p->tw_dev) hipFree(p->tw_dev);
+    delete p;
+    return PF_OK;
+}
+
+const char *pf_strerror(int code) {
+    switch (code) {
+        case PF_OK: return "ok";
+        case PF_EINVAL: return "invalid argument";
+        case PF_EUNSUPPORTED: return "unsupported size or option";
+        case PF_EALIGN: return "pointer not aligned";
+        case PF_EALIAS: return "in/out aliasing does not match the plan's in-place setting";
+        case PF_ENOMEM: return "device allocation failed";
+        case PF_EWORKSPACE: return "workspace missing or too small";
+        case PF_EHIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+int pf_num_passes(const pf_plan *p, int dir) {
+    if (!p || (dir != PF_DIR_FORWARD && dir != PF_DIR_BACKWARD)) return PF_EINVAL;
+    return p->npass[dir];
+}
+
+int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *stream) {
+    if (!p || (dir != PF_DIR_FORWARD && dir != PF_DIR_BACKWARD)) return PF_EINVAL;
+    if (pass < 0 || pass >= p->npass[dir]) return PF_EINVAL;
+    if (!in || !out) return PF_EINVAL;
+    if (!aligned16(in) || !aligned16(out)) return PF_EALIGN;
+    return run_one(p, dir, pass, in, out, (hipStream_t)stream);
+}
+
+const char *pf_pass_name(const pf_plan *p, int dir, int pass) {
+    if (!p || dir < 0 || dir > 1 || pass < 0 || pass >= p->npass[dir]) return "";
+    return p->pass_names[dir][pass];
+}
+
+double pf_pass_bytes(const pf_plan *p, int dir, int pass) {
+    if (!p || dir < 0 || dir > 1 || pass < 0 || pass >= p->npass[dir]) return 0.0;
+    return p->pass_bytes[dir][pass];
+}
+
+int pf_set_timing(pf_plan *p, int enable) {
+    if (!p) return PF_EINVAL;
+    release_timing(p);
+    p->timing = enable != 0;
+    return PF_OK;
+}
+
+int pf_get_timing(pf_plan *p, int dir, int pass, double *total_ms, long long *count) {
+    if (!p || !total_ms || !count || dir < 0 || dir > 1 || pass < 0 || pass >= kPasses) return PF_EINVAL;
+    double tot = 0.0;
+    long long n = 0;
+    for (auto &e : p->tim[dir][pass].used) {
+        if (hipEventSynchronize(e.stop) != hipSuccess) return PF_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.start, e.stop) != hipSuccess) return PF_EHIP;
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *count = n;
+    return PF_OK;
+}
+
+}  // extern "C"

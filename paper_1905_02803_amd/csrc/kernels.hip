@@ -1,0 +1,545 @@
+// kernels.hip -- transform kernels of the pencil 3D R2C / C2R FFT for gfx950.
+//
+// Each kernel is one HBM pass of the transpose-based 3D FFT (Sec. 2, Fig. 2):
+// a workgroup loads a tile of whole lines of the axis being transformed into
+// LDS, runs a mixed-radix Stockham FFT on every line of the tile, and writes
+// the tile back.  The re-orientation between pencils (the paper's pack,
+// all-to-all and unpack, Sec. 3.3) is folded into the address maps of these
+// loads and stores, so each stage reads and writes the array exactly once.
+//
+//  k_r2c_x  : X stage of the forward transform.  Two real lines a, b are
+//             packed as one complex line z = a + i b, transformed together,
+//             and separated with A[k] = (Z[k] + conj Z[n-k]) / 2,
+//             B[k] = (Z[k] - conj Z[n-k]) / (2 i), keeping k <= n/2 (the
+//             (Nx+2)/2 modes of Sec. 3.2).
+//  k_c2r_x  : X stage of the backward transform: the inverse of the above,
+//             using only Re of modes 0 and n/2 (the modes Sec. 3.2 states are
+//             real) and the conjugate-symmetric extension for the rest.
+//  k_c2c_tile: C2C along Y or Z for a tile of TC adjacent columns; columns
+//             are contiguous in memory so every row of the tile is one
+//             coalesced segment, and the output may be laid out differently
+//             from the input (the fused transpose).
+#include "pf_internal.h"
+
+namespace pf {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<float> {
+    typedef float2 t;
+};
+template <>
+struct V2<double> {
+    typedef double2 t;
+};
+template <typename T>
+using cx = typename V2<T>::t;
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmk(T a, T b) {
+    cx<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+template <typename V>
+__device__ __forceinline__ V cadd(V a, V b) {
+    V r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename V>
+__device__ __forceinline__ V csub(V a, V b) {
+    V r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename V, typename S>
+__device__ __forceinline__ V cscale(V a, S s) {
+    V r;
+    r.x = a.x * s;
+    r.y = a.y * s;
+    return r;
+}
+// a * (DIR i)
+template <int DIR, typename V>
+__device__ __forceinline__ V cmuli(V a) {
+    V r;
+    if (DIR > 0) {
+        r.x = -a.y;
+        r.y = a.x;
+    } else {
+        r.x = a.y;
+        r.y = -a.x;
+    }
+    return r;
+}
+// a * (c + DIR i s)
+template <int DIR, typename V, typename S>
+__device__ __forceinline__ V crot(V a, S c, S s) {
+    const S sd = DIR > 0 ? s : -s;
+    V r;
+    r.x = a.x * c - a.y * sd;
+    r.y = a.x * sd + a.y * c;
+    return r;
+}
+
+// cos and sin of 2 pi m / R for the odd radices, m in [0, R).  Values of the
+// closed forms (e.g. cos(2 pi/5) = (sqrt 5 - 1)/4), to 25 digits.
+__device__ constexpr double odd_cos(int R, int m) {
+    return R == 3 ? (m == 0 ? 1.0 : -0.5)
+         : R == 5 ? (m == 0 ? 1.0 : (m == 1 || m == 4) ? 0.3090169943749474241022934 : -0.8090169943749474241022934)
+         : (m == 0 ? 1.0
+                   : (m == 1 || m == 6) ? 0.6234898018587335305250049
+                   : (m == 2 || m == 5) ? -0.2225209339563144042889026
+                                        : -0.9009688679024191262361023);
+}
+__device__ constexpr double odd_sin(int R, int m) {
+    return R == 3 ? (m == 0 ? 0.0 : m == 1 ? 0.8660254037844386467637232 : -0.8660254037844386467637232)
+         : R == 5 ? (m == 0 ? 0.0
+                     : m == 1 ? 0.9510565162951535721164393
+                     : m == 2 ? 0.5877852522924731291687060
+                     : m == 3 ? -0.5877852522924731291687060
+                              : -0.9510565162951535721164393)
+         : (m == 0 ? 0.0
+                   : m == 1 ? 0.7818314824680298087084445
+                   : m == 2 ? 0.9749279121818236070181317
+                   : m == 3 ? 0.4338837391175581204757683
+                   : m == 4 ? -0.4338837391175581204757683
+                   : m == 5 ? -0.9749279121818236070181317
+                            : -0.7818314824680298087084445);
+}
+
+constexpr double kSqrtHalf = 0.7071067811865475244008444;   // cos(pi/4)
+constexpr double kCosPi8 = 0.9238795325112867561281832;     // cos(pi/8)
+constexpr double kSinPi8 = 0.3826834323650897717284600;     // sin(pi/8)
+
+// ---- in-register DFTs of size R with sign DIR:  X[k] = sum_r x[r] e^{DIR 2 pi i r k / R}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft4(cx<T> &x0, cx<T> &x1, cx<T> &x2, cx<T> &x3) {
+    const cx<T> t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3);
+    const cx<T> t3 = cmuli<DIR>(csub(x1, x3));
+    x0 = cadd(t0, t2);
+    x2 = csub(t0, t2);
+    x1 = cadd(t1, t3);
+    x3 = csub(t1, t3);
+}
+
+template <typename T, int R, int DIR>
+struct Dft;
+
+template <typename T, int DIR>
+struct Dft<T, 2, DIR> {
+    __device__ __forceinline__ static void run(cx<T> *v) {
+        const cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <typename T, int DIR>
+struct Dft<T, 4, DIR> {
+    __device__ __forceinline__ static void run(cx<T> *v) { dft4<T, DIR>(v[0], v[1], v[2], v[3]); }
+};
+
+// radix 8: two radix-4 DFTs on the even and odd samples, combined with W8^k.
+template <typename T, int DIR>
+struct Dft<T, 8, DIR> {
+    __device__ __forceinline__ static void run(cx<T> *v) {
+        cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<T, DIR>(e0, e1, e2, e3);
+        dft4<T, DIR>(o0, o1, o2, o3);
+        const T c = T(kSqrtHalf);
+        o1 = crot<DIR>(o1, c, c);
+        o2 = cmuli<DIR>(o2);
+        o3 = crot<DIR>(o3, -c, c);
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, o1);
+        v[5] = csub(e1, o1);
+        v[2] = cadd(e2, o2);
+        v[6] = csub(e2, o2);
+        v[3] = cadd(e3, o3);
+        v[7] = csub(e3, o3);
+    }
+};
+
+// radix 16 as 4 x 4: DFT4 over n2 of x[4 n2 + n1], twiddle W16^{n1 k1},
+// DFT4 over n1; output k1 + 4 k2.
+template <typename T, int DIR>
+struct Dft<T, 16, DIR> {
+    __device__ __forceinline__ static void run(cx<T> *v) {
+        cx<T> a[4][4];
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) {
+            a[n1][0] = v[n1];
+            a[n1][1] = v[n1 + 4];
+            a[n1][2] = v[n1 + 8];
+            a[n1][3] = v[n1 + 12];
+            dft4<T, DIR>(a[n1][0], a[n1][1], a[n1][2], a[n1][3]);
+        }
+        const T c1 = T(kCosPi8), s1 = T(kSinPi8), h = T(kSqrtHalf);
+        a[1][1] = crot<DIR>(a[1][1], c1, s1);   // W^1
+        a[1][2] = crot<DIR>(a[1][2], h, h);     // W^2
+        a[1][3] = crot<DIR>(a[1][3], s1, c1);   // W^3
+        a[2][1] = crot<DIR>(a[2][1], h, h);     // W^2
+        a[2][2] = cmuli<DIR>(a[2][2]);          // W^4
+        a[2][3] = crot<DIR>(a[2][3], -h, h);    // W^6
+        a[3][1] = crot<DIR>(a[3][1], s1, c1);   // W^3
+        a[3][2] = crot<DIR>(a[3][2], -h, h);    // W^6
+        a[3][3] = crot<DIR>(a[3][3], -c1, -s1); // W^9
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            dft4<T, DIR>(a[0][k1], a[1][k1], a[2][k1], a[3][k1]);
+            v[k1] = a[0][k1];
+            v[k1 + 4] = a[1][k1];
+            v[k1 + 8] = a[2][k1];
+            v[k1 + 12] = a[3][k1];
+        }
+    }
+};
+
+// odd prime radix: pair x[r] with x[R-r]; X[k] = x0 + sum s_r cos + DIR i sum d_r sin.
+template <typename T, int R, int DIR>
+struct DftOdd {
+    __device__ __forceinline__ static void run(cx<T> *v) {
+        constexpr int H = (R - 1) / 2;
+        cx<T> s[H], d[H];
+        cx<T> x0 = v[0], sum = v[0];
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            s[r - 1] = cadd(v[r], v[R - r]);
+            d[r - 1] = csub(v[r], v[R - r]);
+            sum = cadd(sum, s[r - 1]);
+        }
+        v[0] = sum;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            cx<T> A = x0, Bv = cmk<T>(T(0), T(0));
+#pragma unroll
+            for (int r = 1; r <= H; ++r) {
+                const int m = (r * k) % R;
+                A = cadd(A, cscale(s[r - 1], T(odd_cos(R, m))));
+                Bv = cadd(Bv, cscale(d[r - 1], T(odd_sin(R, m))));
+            }
+            const cx<T> iB = cmuli<DIR>(Bv);
+            v[k] = cadd(A, iB);
+            v[R - k] = csub(A, iB);
+        }
+    }
+};
+template <typename T, int DIR>
+struct Dft<T, 3, DIR> : DftOdd<T, 3, DIR> {};
+template <typename T, int DIR>
+struct Dft<T, 5, DIR> : DftOdd<T, 5, DIR> {};
+template <typename T, int DIR>
+struct Dft<T, 7, DIR> : DftOdd<T, 7, DIR> {};
+
+// ---- one Stockham stage on one LDS column ------------------------------
+// Butterfly j (j < n/R) reads x[j + r n/R], applies W_{Ns R}^{r k} with
+// k = j mod Ns, runs the radix-R DFT and writes (j - k) R + k + r Ns.
+// Every thread of the workgroup must call this (it holds two barriers).
+// Kept out of line: inlining all radices into the runtime stage loop makes
+// the register allocator keep their live ranges together.
+template <typename T>
+struct EMax {
+    static constexpr int value = sizeof(T) == 4 ? kEMax : kEMax / 2;
+};
+
+template <typename T, int R, int DIR>
+__device__ __attribute__((noinline)) void fft_stage(cx<T> *col, int n, int Ns, const cx<T> *__restrict__ tw, int lane,
+                                          int wpc) {
+    constexpr int BM = (EMax<T>::value + R - 1) / R;
+    const int nb = n / R;
+    cx<T> v[BM][R];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const int j = lane + i * wpc;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = col[pidx(j + r * nb)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+        const int j = lane + i * wpc;
+        if (j < nb) {
+            const int k = j % Ns;
+            if (Ns > 1) {
+                const cx<T> *t = tw + k * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = t[r - 1];
+                    if (DIR > 0) w.y = -w.y;
+                    v[i][r] = cmul(v[i][r], w);
+                }
+            }
+            Dft<T, R, DIR>::run(v[i]);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) col[pidx(base + r * Ns)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Whole 1D FFT of length fs.n on one LDS column, in natural order.
+template <typename T, int DIR>
+__device__ __forceinline__ void fft_lds(cx<T> *col, const FftSpec &fs, const cx<T> *__restrict__ tw, int lane,
+                                        int wpc) {
+    int Ns = 1;
+    for (int s = 0; s < fs.nstages; ++s) {
+        const int R = fs.radix[s];
+        const cx<T> *t = tw + fs.twoff[s];
+        switch (R) {
+            case 16: fft_stage<T, 16, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+            case 8: fft_stage<T, 8, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+            case 4: fft_stage<T, 4, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+            case 2: fft_stage<T, 2, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+            case 3: fft_stage<T, 3, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+            case 5: fft_stage<T, 5, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+            default: fft_stage<T, 7, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+        }
+        Ns *= R;
+    }
+}
+
+extern __shared__ __align__(16) unsigned char pf_smem[];
+
+__device__ __forceinline__ long long side_base(const Side &s, long long a, long long cb, int tc) {
+    return a * s.sa + (cb / s.cpb) * s.sblk + (cb % s.cpb) * (long long)tc * s.sc;
+}
+
+// ---- C2C along a strided axis, TC columns per workgroup -------------------
+template <typename T, int DIR>
+__global__ __launch_bounds__(1024) void k_c2c_tile(PassArgs a) {
+    cx<T> *lds = reinterpret_cast<cx<T> *>(pf_smem);
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int TC = 1 << a.tc_log2;
+    const int wpc = 1 << a.wpc_log2;
+    const long long tile = blockIdx.x;
+    const long long ta = tile / a.CB;
+    const long long cb = tile - ta * a.CB;
+    const long long ib = side_base(a.in_s, ta, cb, TC);
+    const long long ob = side_base(a.out_s, ta, cb, TC);
+    const long long left = (long long)a.C - cb * TC;
+    const int ncol = left < TC ? (int)left : TC;
+    const int n = a.fft.n;
+    const int pitch = a.pitch;
+    const cx<T> *__restrict__ in = reinterpret_cast<const cx<T> *>(a.in);
+    cx<T> *__restrict__ out = reinterpret_cast<cx<T> *>(a.out);
+
+    if (a.in_s.sc == 1) {  // rows of the tile are contiguous: column fastest
+        const int c = tid & (TC - 1);
+        if (c < ncol)
+            for (int p = tid >> a.tc_log2; p < n; p += nthr >> a.tc_log2)
+                lds[c * pitch + pidx(p)] = in[ib + c + (long long)p * a.in_s.sp];
+    } else {  // columns are contiguous lines: point fastest
+        const int c = tid >> a.wpc_log2;
+        if (c < ncol)
+            for (int p = tid & (wpc - 1); p < n; p += wpc)
+                lds[c * pitch + pidx(p)] = in[ib + (long long)c * a.in_s.sc + (long long)p * a.in_s.sp];
+    }
+    __syncthreads();
+    fft_lds<T, DIR>(lds + (tid >> a.wpc_log2) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+                    tid & (wpc - 1), wpc);
+    if (a.out_s.sc == 1) {
+        const int c = tid & (TC - 1);
+        if (c < ncol)
+            for (int p = tid >> a.tc_log2; p < n; p += nthr >> a.tc_log2)
+                out[ob + c + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
+    } else {
+        const int c = tid >> a.wpc_log2;
+        if (c < ncol)
+            for (int p = tid & (wpc - 1); p < n; p += wpc)
+                out[ob + (long long)c * a.out_s.sc + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
+    }
+}
+
+// Row offsets in the blocked workspace of the 2 TC real lines of an X tile:
+// line g = z ny + y starts at (z nkb ny + y) B.
+__device__ __forceinline__ void x_row_offsets(const PassArgs &a, long long g0, int nl, long long *rowoff) {
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
+        const long long g = g0 + l;
+        const long long z = g / a.ny;
+        const long long y = g - z * a.ny;
+        rowoff[l] = ((z * a.nkb) * a.ny + y) << a.b_log2;
+    }
+}
+
+// ---- X stage, forward: real lines -> half spectra in the blocked workspace
+template <typename T>
+__global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
+    __shared__ long long rowoff[128];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(pf_smem);
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int TC = 1 << a.tc_log2;
+    const int wpc = 1 << a.wpc_log2;
+    const int n = a.fft.n;
+    const int pitch = a.pitch;
+    const long long g0 = (long long)blockIdx.x * (2 * TC);
+    const T *__restrict__ in = reinterpret_cast<const T *>(a.in);
+    cx<T> *__restrict__ out = reinterpret_cast<cx<T> *>(a.out);
+    x_row_offsets(a, g0, 2 * TC, rowoff);
+    {
+        const int c = tid >> a.wpc_log2;
+        const long long ga = g0 + 2 * c, gb = ga + 1;
+        const bool va = ga < a.lines, vb = gb < a.lines;
+        const T *pa = in + ga * a.ld_real;
+        const T *pb = in + gb * a.ld_real;
+        for (int p = tid & (wpc - 1); p < n; p += wpc) {
+            const T xa = va ? pa[p] : T(0);
+            const T xb = vb ? pb[p] : T(0);
+            lds[c * pitch + pidx(p)] = cmk<T>(xa, xb);
+        }
+    }
+    __syncthreads();
+    fft_lds<T, -1>(lds + (tid >> a.wpc_log2) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+                   tid & (wpc - 1), wpc);
+    const int B = 1 << a.b_log2;
+    const int total = a.nkb * TC * B;
+    const long long kbstride = (long long)a.ny << a.b_log2;
+    const T h = T(0.5);
+    for (int f = tid; f < total; f += nthr) {
+        const int kk = f & (B - 1);
+        const int cc = (f >> a.b_log2) & (TC - 1);
+        const int kb = f >> (a.b_log2 + a.tc_log2);
+        const int k = kb * B + kk;
+        const long long ga = g0 + 2 * cc;
+        if (k >= a.nxh || ga >= a.lines) continue;
+        const cx<T> *col = lds + cc * pitch;
+        const cx<T> z = col[pidx(k)];
+        const cx<T> w = col[pidx(k == 0 ? 0 : n - k)];
+        out[rowoff[2 * cc] + kb * kbstride + kk] = cmk<T>((z.x + w.x) * h, (z.y - w.y) * h);
+        if (ga + 1 < a.lines) out[rowoff[2 * cc + 1] + kb * kbstride + kk] = cmk<T>((z.y + w.y) * h, (w.x - z.x) * h);
+    }
+}
+
+// ---- X stage, backward: blocked half spectra -> real lines ---------------
+template <typename T>
+__global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
+    __shared__ long long rowoff[128];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(pf_smem);
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int TC = 1 << a.tc_log2;
+    const int wpc = 1 << a.wpc_log2;
+    const int n = a.fft.n;
+    const int pitch = a.pitch;
+    const long long g0 = (long long)blockIdx.x * (2 * TC);
+    const cx<T> *__restrict__ in = reinterpret_cast<const cx<T> *>(a.in);
+    T *__restrict__ out = reinterpret_cast<T *>(a.out);
+    x_row_offsets(a, g0, 2 * TC, rowoff);
+    __syncthreads();
+    const int B = 1 << a.b_log2;
+    const int total = a.nkb * TC * B;
+    const long long kbstride = (long long)a.ny << a.b_log2;
+    for (int f = tid; f < total; f += nthr) {
+        const int kk = f & (B - 1);
+        const int cc = (f >> a.b_log2) & (TC - 1);
+        const int kb = f >> (a.b_log2 + a.tc_log2);
+        const int k = kb * B + kk;
+        const long long ga = g0 + 2 * cc;
+        if (k >= a.nxh || ga >= a.lines) continue;
+        const cx<T> xa = in[rowoff[2 * cc] + kb * kbstride + kk];
+        const cx<T> xb = (ga + 1 < a.lines) ? in[rowoff[2 * cc + 1] + kb * kbstride + kk] : cmk<T>(T(0), T(0));
+        cx<T> *col = lds + cc * pitch;
+        if (k == 0 || 2 * k == n) {
+            col[pidx(k)] = cmk<T>(xa.x, xb.x);
+        } else {
+            col[pidx(k)] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
+            col[pidx(n - k)] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+        }
+    }
+    __syncthreads();
+    fft_lds<T, 1>(lds + (tid >> a.wpc_log2) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+                  tid & (wpc - 1), wpc);
+    {
+        const int c = tid >> a.wpc_log2;
+        const long long ga = g0 + 2 * c, gb = ga + 1;
+        const bool va = ga < a.lines, vb = gb < a.lines;
+        T *pa = out + ga * a.ld_real;
+        T *pb = out + gb * a.ld_real;
+        const cx<T> *col = lds + c * pitch;
+        for (int p = tid & (wpc - 1); p < n; p += wpc) {
+            const cx<T> z = col[pidx(p)];
+            if (va) pa[p] = z.x;
+            if (vb) pb[p] = z.y;
+        }
+    }
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+hipError_t prepare_kernels(size_t max_lds) {
+    hipError_t e = hipSuccess;
+#define PF_ALLOW(k)                                      \
+    do {                                                 \
+        hipError_t r = allow_lds(k, max_lds);            \
+        if (r != hipSuccess && e == hipSuccess) e = r;   \
+    } while (0)
+    PF_ALLOW((k_c2c_tile<float, -1>));
+    PF_ALLOW((k_c2c_tile<float, 1>));
+    PF_ALLOW((k_c2c_tile<double, -1>));
+    PF_ALLOW((k_c2c_tile<double, 1>));
+    PF_ALLOW(k_r2c_x<float>);
+    PF_ALLOW(k_r2c_x<double>);
+    PF_ALLOW(k_c2r_x<float>);
+    PF_ALLOW(k_c2r_x<double>);
+#undef PF_ALLOW
+    return e;
+}
+
+hipError_t launch_pass(const PassDesc &d, hipStream_t s) {
+    const dim3 g(d.blocks), b(d.threads);
+    const bool f64 = d.prec != 0;
+    switch (d.kind) {
+        case PASS_C2C:
+            if (f64) {
+                if (d.dir < 0)
+                    hipLaunchKernelGGL((k_c2c_tile<double, -1>), g, b, d.lds, s, d.a);
+                else
+                    hipLaunchKernelGGL((k_c2c_tile<double, 1>), g, b, d.lds, s, d.a);
+            } else {
+                if (d.dir < 0)
+                    hipLaunchKernelGGL((k_c2c_tile<float, -1>), g, b, d.lds, s, d.a);
+                else
+                    hipLaunchKernelGGL((k_c2c_tile<float, 1>), g, b, d.lds, s, d.a);
+            }
+            break;
+        case PASS_R2C_X:
+            if (f64)
+                hipLaunchKernelGGL(k_r2c_x<double>, g, b, d.lds, s, d.a);
+            else
+                hipLaunchKernelGGL(k_r2c_x<float>, g, b, d.lds, s, d.a);
+            break;
+        case PASS_C2R_X:
+            if (f64)
+                hipLaunchKernelGGL(k_c2r_x<double>, g, b, d.lds, s, d.a);
+            else
+                hipLaunchKernelGGL(k_c2r_x<float>, g, b, d.lds, s, d.a);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pf

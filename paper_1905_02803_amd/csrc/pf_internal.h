@@ -1,0 +1,71 @@
+// pf_internal.h -- declarations shared by the host planner (capi.hip) and the
+// transform kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace pf {
+
+constexpr int kMaxStages = 16;  // radix stages of one 1D length
+constexpr int kEMax = 16;       // complex elements per thread per stage (F32; F64 uses half)
+constexpr int kMaxLds = 128 * 1024;  // dynamic LDS any kernel may request
+
+// Mixed-radix plan of one 1D length n = radix[0] * radix[1] * ...
+// Stage s has Ns = radix[0] * ... * radix[s-1] and reads its twiddles
+// W_{Ns R}^{r k} (k < Ns, 1 <= r < R) at twoff[s] + k (R - 1) + r - 1.
+struct FftSpec {
+    int n;
+    int nstages;
+    int radix[kMaxStages];
+    int twoff[kMaxStages];
+};
+
+// Address map of one side of a column-tile pass.  Tile (a, cb) holds columns
+// cb * TC .. cb * TC + TC - 1 of a grid of C columns; element (c, p) of the
+// tile sits at  a*sa + (cb / cpb)*sblk + (cb % cpb)*TC*sc + c*sc + p*sp.
+// Blocked workspace sides use cpb = B / TC; linear sides use cpb = CB, sblk = 0.
+struct Side {
+    long long sa, sblk, sc, sp, cpb;
+};
+
+enum PassKind { PASS_C2C = 0, PASS_R2C_X = 1, PASS_C2R_X = 2 };
+
+struct PassArgs {
+    const void *in;
+    void *out;
+    const void *tw;  // stage twiddle tables of fft.n, plan precision
+    FftSpec fft;
+    int tc_log2;   // TC = columns (C2C) or line pairs (X passes) per tile
+    int wpc_log2;  // threads per column
+    int pitch;     // LDS column pitch in complex elements
+    int C;         // valid columns (C2C passes)
+    long long A, CB;  // C2C tile grid: A * CB tiles
+    Side in_s, out_s;
+    // X passes: real lines (y, z) flattened as g = z * ny + y
+    long long lines;
+    long long ld_real;  // elements between consecutive real lines
+    int ny, nkb, b_log2, nxh;
+};
+
+struct PassDesc {
+    PassKind kind;
+    int dir;   // -1 forward, +1 backward
+    int prec;  // PF_F32 / PF_F64
+    unsigned blocks;
+    unsigned threads;
+    size_t lds;
+    PassArgs a;
+};
+
+// Allow every kernel instantiation up to max_lds bytes of dynamic LDS.
+hipError_t prepare_kernels(size_t max_lds);
+// Enqueue one pass.
+hipError_t launch_pass(const PassDesc &d, hipStream_t s);
+
+// LDS index with one pad slot every 16 complex elements (spreads the strided
+// Stockham writes over the banks).
+__host__ __device__ inline int pidx(int i) { return i + (i >> 4); }
+
+}  // namespace pf

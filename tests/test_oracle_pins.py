@@ -281,3 +281,18 @@ def test_sampled_points_and_lines_match_whole_transform(shape):
 def test_float32_input_is_promoted_exactly():
     u = synth.uniform(24, (6, 7, 10)).astype(np.float32)
     assert np.array_equal(oracle.r2c3d(u), oracle.r2c3d(u.astype(np.float64)))
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 8), (4, 9, 7)])
+def test_stages_compose_to_the_whole_transform(shape):
+    """X stage, then Y, then Z (Sec. 2) equals the brute-force 3D sum; the backward stages likewise."""
+    nz, ny, nx = shape
+    u = synth.uniform(25, shape)
+    A = oracle.stage_x_r2c(u)
+    assert rel(A, np.fft.rfft(u, axis=2)) < 1e-13
+    A = oracle.stage_c2c(A, nx, "y", -1)
+    A = oracle.stage_c2c(A, nx, "z", -1)
+    assert rel(A, brute_r2c(u)) < 1e-13
+    U = synth.complex_half(26, (nz, ny, nx // 2 + 1))
+    B = oracle.stage_c2c(oracle.stage_c2c(U, nx, "z", +1), nx, "y", +1)
+    assert rel(oracle.stage_x_c2r(B, nx), brute_c2r(U, nx)) < 1e-13
