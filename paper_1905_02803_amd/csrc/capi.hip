@@ -34,6 +34,7 @@ struct PassTiming {
 
 struct pf_plan {
     int nx, ny, nz, nxh;
+    int ncu;  // compute units of the device the plan was made on
     pf_layout lay;
     int csize;  // bytes per complex value
     int B, b_log2, nkb;
@@ -173,17 +174,41 @@ int built_options(const pf_layout *l) {
     return PF_OK;
 }
 
-void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc) {
-    d.kind = pf::PASS_C2C;
+// vec_ok: both sides are either the padded workspace (whole 16-column blocks,
+// 16-byte aligned rows) or whole contiguous lines -- what the power-of-two
+// kernel's 16-byte column-pair accesses need.
+void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc,
+                    bool vec_ok) {
     d.dir = dir;
     d.prec = p->lay.precision;
     PassArgs &a = d.a;
     std::memset(&a, 0, sizeof(a));
     a.fft = fs;
     a.tw = (const char *)p->tw_dev + twoff;
+    a.C = p->nxh;
+    if (vec_ok && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
+        // compile-time radix plan, persistent blocks (grid set once the tile count is known)
+        d.kind = pf::PASS_C2C_P2;
+        a.tc_log2 = ilog2(pf::p2_tc(fs.n));
+        a.wpc_log2 = ilog2(fs.n / 16);
+        d.threads = (unsigned)pf::p2_threads(fs.n);
+        d.lds = pf::p2_lds_bytes(fs.n);
+        return;
+    }
+    d.kind = pf::PASS_C2C;
     choose_tile(fs.n, p->csize, max_tc, &a.tc_log2, &a.wpc_log2, &a.pitch, &d.lds);
     d.threads = 1u << (a.tc_log2 + a.wpc_log2);
-    a.C = p->nxh;
+}
+
+// Grid of a C2C pass over A * CB tiles: one block per tile, or for the
+// persistent power-of-two kernel as many blocks as fit on the device at once.
+unsigned c2c_grid(const pf_plan *p, PassDesc &d) {
+    const long long tiles = d.a.A * d.a.CB;
+    if (d.kind != pf::PASS_C2C_P2) return (unsigned)tiles;
+    d.a.inp = (d.a.in_s.sp == 1 && d.a.in_s.sc != 1) ? 1 : 0;
+    d.a.outp = (d.a.out_s.sp == 1 && d.a.out_s.sc != 1) ? 1 : 0;
+    const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(d);
+    return (unsigned)(tiles < resident ? tiles : resident);
 }
 
 // Blocked workspace side seen by a C2C pass whose tile rows run along
@@ -244,22 +269,22 @@ void build_passes(pf_plan *p) {
         x.blocks = (unsigned)((pairs + tcx - 1) / tcx);
         // Y stage: in place on the workspace, tile (z, column block)
         PassDesc y;
-        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B);
+        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B, true);
         y.a.in_s = ws_side(p, zstride, p->B, y.a.tc_log2);
         y.a.out_s = y.a.in_s;
         y.a.A = p->nz;
         y.a.CB = (long long)p->nkb * (p->B >> y.a.tc_log2);
-        y.blocks = (unsigned)(y.a.A * y.a.CB);
+        y.blocks = c2c_grid(p, y);
         // Z stage: tile (y, column block)
         PassDesc z;
-        set_c2c_common(z, p, p->fz, p->tw_off[2], sgn, p->B);
+        set_c2c_common(z, p, p->fz, p->tw_off[2], sgn, p->B, p->lay.stride1 != 0);
         z.a.A = p->ny;
         z.a.CB = (long long)p->nkb * (p->B >> z.a.tc_log2);
         const Side wsz = ws_side(p, p->B, zstride, z.a.tc_log2);
         const Side usr = user_side(p, z.a.CB);
         z.a.in_s = dir == 0 ? wsz : usr;
         z.a.out_s = dir == 0 ? usr : wsz;
-        z.blocks = (unsigned)(z.a.A * z.a.CB);
+        z.blocks = c2c_grid(p, z);
 
         const double cbytes = M * 2 * rs;
         if (dir == 0) {
@@ -449,6 +474,11 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
     }
     e = hipMemcpy(p->tw_dev, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = pf::prepare_kernels(pf::kMaxLds);
+    int dev = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int n : {ny, nz})
+        if (e == hipSuccess && pf::p2_supported(n, l->precision)) e = pf::p2_prepare(n);
     if (e != hipSuccess) {
         hipFree(p->tw_dev);
         delete p;

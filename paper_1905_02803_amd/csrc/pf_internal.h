@@ -30,7 +30,7 @@ struct Side {
     long long sa, sblk, sc, sp, cpb;
 };
 
-enum PassKind { PASS_C2C = 0, PASS_R2C_X = 1, PASS_C2R_X = 2 };
+enum PassKind { PASS_C2C = 0, PASS_R2C_X = 1, PASS_C2R_X = 2, PASS_C2C_P2 = 3 };
 
 struct PassArgs {
     const void *in;
@@ -43,6 +43,7 @@ struct PassArgs {
     int C;         // valid columns (C2C passes)
     long long A, CB;  // C2C tile grid: A * CB tiles
     Side in_s, out_s;
+    int inp, outp;  // power-of-two C2C pass: 1 if that side's points are contiguous
     // X passes: real lines (y, z) flattened as g = z * ny + y
     long long lines;
     long long ld_real;  // elements between consecutive real lines
@@ -63,6 +64,15 @@ struct PassDesc {
 hipError_t prepare_kernels(size_t max_lds);
 // Enqueue one pass.
 hipError_t launch_pass(const PassDesc &d, hipStream_t s);
+
+// Power-of-two FP32 C2C pass (kernels_p2.hip).
+bool p2_supported(int n, int prec);
+int p2_tc(int n);
+int p2_threads(int n);
+size_t p2_lds_bytes(int n);
+hipError_t p2_prepare(int n);
+int p2_blocks_per_cu(const PassDesc &d);
+hipError_t p2_launch(const PassDesc &d, hipStream_t s);
 
 // LDS index with one pad slot every 16 complex elements (spreads the strided
 // Stockham writes over the banks).

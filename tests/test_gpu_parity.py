@@ -35,6 +35,11 @@ SHAPES = [
     (3, 1024, 2),     # along Y
     (1024, 2, 4),     # along Z
     (64, 64, 64),
+    (256, 12, 36),    # power-of-two Z (compile-time radix path), ragged column blocks
+    (16, 512, 36),    # power-of-two Y
+    (1024, 6, 40),
+    (3, 2048, 10),
+    (4096, 2, 6),
     (1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 5, 3), (3, 1, 4),
 ]
 
@@ -97,7 +102,8 @@ def test_forward_and_backward_match_oracle(shape, prec, stride1):
 
 
 @pytest.mark.parametrize("prec", [pf.PF_F32, pf.PF_F64])
-@pytest.mark.parametrize("shape", [(24, 20, 36), (9, 7, 15), (6, 10, 480), (3, 1024, 2)], ids=ids)
+@pytest.mark.parametrize("shape", [(24, 20, 36), (9, 7, 15), (6, 10, 480), (3, 1024, 2), (16, 512, 36), (1024, 6, 40)],
+                         ids=ids)
 def test_each_pass_matches_oracle_stage(shape, prec):
     """Every kernel alone against the oracle's own stage (forward X, Y, Z; backward Z, Y, X)."""
     nz, ny, nx = shape
@@ -141,7 +147,7 @@ def test_each_pass_matches_oracle_stage(shape, prec):
         assert rel(r.cpu().numpy(), oracle.stage_x_c2r(B, nx)) < tol
 
 
-@pytest.mark.parametrize("shape", [(24, 20, 36), (64, 64, 64)], ids=ids)
+@pytest.mark.parametrize("shape", [(24, 20, 36), (64, 64, 64), (16, 512, 36), (1024, 6, 40)], ids=ids)
 def test_repeat_runs_are_bitwise_identical(shape):
     """Same input, same kernels: results must not depend on timing (catches missing barriers)."""
     nz, ny, nx = shape
