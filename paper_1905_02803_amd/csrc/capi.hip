@@ -39,8 +39,10 @@ struct pf_plan {
     int csize;  // bytes per complex value
     int B, b_log2, nkb;
     FftSpec fx, fy, fz;
-    void *tw_dev;  // one allocation holding the x, y, z tables
-    size_t tw_off[3];
+    void *tw_dev;  // one allocation holding the x, y, z tables (+ the half-length X table)
+    size_t tw_off[4];
+    FftSpec fxh;   // nx / 2 plan of the even power-of-two X stage
+    bool fast_x;
     void *ws;
     size_t ws_bytes;
     bool own_ws;
@@ -267,6 +269,16 @@ void build_passes(pf_plan *p) {
         const long long pairs = (x.a.lines + 1) / 2;
         const long long tcx = 1LL << x.a.tc_log2;
         x.blocks = (unsigned)((pairs + tcx - 1) / tcx);
+        if (p->fast_x) {  // half-length complex transform, 16 lines per tile, persistent blocks
+            x.kind = dir == 0 ? pf::PASS_R2C_P2 : pf::PASS_C2R_P2;
+            x.a.fft = p->fxh;
+            x.a.tw = (const char *)p->tw_dev + p->tw_off[3];
+            x.threads = (unsigned)pf::p2x_threads(p->nx);
+            x.lds = pf::p2x_lds_bytes(p->nx);
+            const long long tiles = (x.a.lines + 15) / 16;
+            const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(x);
+            x.blocks = (unsigned)(tiles < resident ? tiles : resident);
+        }
         // Y stage: in place on the workspace, tile (z, column block)
         PassDesc y;
         set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B, true);
@@ -467,6 +479,25 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
         }
         host.resize((host.size() + 255) & ~(size_t)255, 0);
     }
+    p->fast_x = pf::p2x_supported(nx, l->precision);
+    p->tw_off[3] = host.size();
+    if (p->fast_x) {
+        // [M-point stage table (M - 1)][pad][W_nx^k, k = 0 .. M], M = nx / 2
+        const int M = nx / 2;
+        factor_length(M, &p->fxh);
+        std::vector<float> t;
+        build_twiddles<float>(p->fxh, t);
+        t.resize(2 * (size_t)(2 * M + 1), 0.f);
+        const double two_pi = 6.283185307179586476925286766559;
+        for (int k = 0; k <= M; ++k) {
+            const double ang = two_pi * (double)k / (double)nx;
+            t[2 * (size_t)(M + k)] = (float)std::cos(ang);
+            t[2 * (size_t)(M + k) + 1] = (float)(-std::sin(ang));
+        }
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
+        host.insert(host.end(), b, b + t.size() * sizeof(float));
+        host.resize((host.size() + 255) & ~(size_t)255, 0);
+    }
     hipError_t e = hipMalloc(&p->tw_dev, host.size());
     if (e != hipSuccess) {
         delete p;
@@ -479,6 +510,7 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, dev);
     for (int n : {ny, nz})
         if (e == hipSuccess && pf::p2_supported(n, l->precision)) e = pf::p2_prepare(n);
+    if (e == hipSuccess && p->fast_x) e = pf::p2x_prepare(nx);
     if (e != hipSuccess) {
         hipFree(p->tw_dev);
         delete p;

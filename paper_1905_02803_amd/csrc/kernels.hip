@@ -316,6 +316,8 @@ hipError_t launch_pass(const PassDesc &d, hipStream_t s) {
                 hipLaunchKernelGGL(k_c2r_x<float>, g, b, d.lds, s, d.a);
             break;
         case PASS_C2C_P2:
+        case PASS_R2C_P2:
+        case PASS_C2R_P2:
             return p2_launch(d, s);
     }
     return hipGetLastError();

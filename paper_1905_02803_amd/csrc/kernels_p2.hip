@@ -204,6 +204,341 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     }
 }
 
+// ---- X stage for even power-of-two nx, FP32 --------------------------------
+// A real line x of length nx = 2M is transformed as the complex line
+// z[m] = x[2m] + i x[2m+1] of length M (8-byte loads, half the butterflies),
+// then split: with Z = DFT_M(z), E[k] = (Z[k] + conj Z[M-k]) / 2,
+// O[k] = (Z[k] - conj Z[M-k]) / (2i), the modes are X[k] = E[k] + W_nx^k O[k]
+// for k = 0 .. M (the (nx+2)/2 modes of Sec. 3.2).  The backward transform
+// inverts the split, Zb[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k])
+// W_nx^-k, after replacing X[0] and X[M] by their real parts (the staged
+// complex-to-real transform), and an unnormalised inverse DFT_M returns
+// x[2m] + i x[2m+1].  A tile is 16 consecutive lines (8 line pairs); the
+// spectra go to / come from the blocked workspace [z][kb][y][16].  Twiddles:
+// a.tw holds the M-point stage table (M - 1 entries) and at offset M the
+// split table W_nx^k, k = 0 .. M.
+
+// Row offsets in the workspace of the 16 lines of tile t (line g = z ny + y
+// starts at (z nkb ny + y) 16).
+__device__ __forceinline__ long long x_rowoff(const PassArgs &a, int g) {
+    const int z = g / a.ny;
+    const int y = g - z * a.ny;
+    return (((long long)z * a.nkb) * a.ny + y) << 4;
+}
+
+template <int M>
+__global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
+    constexpr int TC = 16;
+    constexpr int T = M / 16;
+    constexpr int CP = 8;
+    constexpr int NT = T * CP;
+    constexpr int S = p2_stages(M);
+    constexpr int RL = p2_radix(M, S - 1);
+    constexpr int NSL = p2_ns(M, S - 1);
+    constexpr int NKB = M / 16 + 1;  // workspace column blocks for M + 1 modes
+    float4 *buf = reinterpret_cast<float4 *>(pf_smem);
+    cx<float> *twl = reinterpret_cast<cx<float> *>(buf + M * CP);
+    cx<float> *spl = twl + M;
+    __shared__ long long rowoff[16];
+    const int tid = threadIdx.x;
+    const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
+    for (int i = tid; i < 2 * M + 1; i += NT)
+        if (i != M - 1) twl[i] = tw[i];
+    const float *__restrict__ in = reinterpret_cast<const float *>(a.in);
+    cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
+    const int lines = (int)a.lines;
+    const int ntiles = (lines + 15) / 16;
+    const int cp_in = tid / T, q_in = tid % T;     // lines: lanes along points
+    const int cp_mid = tid % CP, q_mid = tid / CP; // exchanges: lanes along line pairs
+    const long long kbstride = (long long)a.ny << 4;
+
+    auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
+        const int ga = 16 * t + 2 * cp_in;
+        const float *pa = in + (long long)ga * a.ld_real + 2 * q_in;
+        if (ga < lines) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) d0[m] = *reinterpret_cast<const float2 *>(pa + 2 * T * m);
+        }
+        if (ga + 1 < lines) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) d1[m] = *reinterpret_cast<const float2 *>(pa + a.ld_real + 2 * T * m);
+        }
+    };
+
+    int t = blockIdx.x;
+    cx<float> p0[16], p1[16];
+    if (t < ntiles) load(p0, p1, t);
+    __syncthreads();
+    for (; t < ntiles; t += gridDim.x) {
+        cx<float> v0[16], v1[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            v0[m] = p0[m];
+            v1[m] = p1[m];
+        }
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(p0, p1, tn);
+        if (tid < 16 && 16 * t + tid < lines) rowoff[tid] = x_rowoff(a, 16 * t + tid);
+
+        Dft<float, 16, -1>::run(v0);
+        Dft<float, 16, -1>::run(v1);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
+        __syncthreads();
+        if constexpr (S == 3) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
+                v0[m] = make_float2(x.x, x.y);
+                v1[m] = make_float2(x.z, x.w);
+            }
+            __syncthreads();
+            p2_butterflies<M, 16, 16, -1>(v0, q_mid, twl + p2_twoff(M, 1));
+            p2_butterflies<M, 16, 16, -1>(v1, q_mid, twl + p2_twoff(M, 1));
+            const int k = q_mid & 15;
+            const int base = (q_mid - k) * 16 + k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(base + r * 16, cp_mid)] = pack2(v0[r], v1[r]);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
+            v0[m] = make_float2(x.x, x.y);
+            v1[m] = make_float2(x.z, x.w);
+        }
+        __syncthreads();
+        p2_butterflies<M, RL, NSL, -1>(v0, q_mid, twl + p2_twoff(M, S - 1));
+        p2_butterflies<M, RL, NSL, -1>(v1, q_mid, twl + p2_twoff(M, S - 1));
+#pragma unroll
+        for (int m = 0; m < 16; ++m) buf[p2_slot<TC>(q_mid + T * m, cp_mid)] = pack2(v0[m], v1[m]);
+        __syncthreads();
+
+        // split and store: chunk = (column block kb, line pair pr, mode pair kp)
+        for (int f = tid; f < NKB * 64; f += NT) {
+            const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
+            const int ga = 16 * t + 2 * pr;
+            const int k0 = kb * 16 + 2 * kp;
+            if (ga >= lines || k0 > M) continue;
+            float2 xa[2], xb[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = k0 + e;
+                const int kz = k < M ? k : k - M;       // Z is M-periodic
+                const int km = k == 0 ? 0 : M - k;      // (M - k) mod M for k <= M
+                const float4 zk = buf[p2_slot<TC>(kz < M ? kz : 0, pr)];
+                const float4 zm = buf[p2_slot<TC>(km < M ? km : 0, pr)];
+                const cx<float> w = spl[k <= M ? k : M];
+                // line a: (zk.x, zk.y), (zm.x, zm.y); line b: .z, .w
+                const float2 Ea = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+                const float2 Oa = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+                const float2 Eb = make_float2(0.5f * (zk.z + zm.z), 0.5f * (zk.w - zm.w));
+                const float2 Ob = make_float2(0.5f * (zk.w + zm.w), 0.5f * (zm.z - zk.z));
+                xa[e] = cadd(Ea, cmul(w, Oa));
+                xb[e] = cadd(Eb, cmul(w, Ob));
+            }
+            const long long col = (long long)kb * kbstride + 2 * kp;
+            cx<float> *oa = out + rowoff[2 * pr] + col;
+            if (k0 + 1 <= M)
+                *reinterpret_cast<float4 *>(oa) = pack2(xa[0], xa[1]);
+            else
+                *oa = xa[0];
+            if (ga + 1 < lines) {
+                cx<float> *ob = out + rowoff[2 * pr + 1] + col;
+                if (k0 + 1 <= M)
+                    *reinterpret_cast<float4 *>(ob) = pack2(xb[0], xb[1]);
+                else
+                    *ob = xb[0];
+            }
+        }
+        __syncthreads();  // LDS tile and row offsets are reused by the next tile
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2(PassArgs a) {
+    constexpr int TC = 16;
+    constexpr int T = M / 16;
+    constexpr int CP = 8;
+    constexpr int NT = T * CP;
+    constexpr int S = p2_stages(M);
+    constexpr int RL = p2_radix(M, S - 1);
+    constexpr int NSL = p2_ns(M, S - 1);
+    constexpr int NKB = M / 16 + 1;
+    constexpr int NCH = (NKB * 64 + NT - 1) / NT;  // 16-byte chunk pairs per thread per tile
+    float4 *buf = reinterpret_cast<float4 *>(pf_smem);
+    cx<float> *twl = reinterpret_cast<cx<float> *>(buf + M * CP);
+    cx<float> *spl = twl + M;
+    __shared__ float4 nyq[8];  // X[M] of each line pair
+    const int tid = threadIdx.x;
+    const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
+    for (int i = tid; i < 2 * M + 1; i += NT)
+        if (i != M - 1) twl[i] = tw[i];
+    const cx<float> *__restrict__ in = reinterpret_cast<const cx<float> *>(a.in);
+    float *__restrict__ out = reinterpret_cast<float *>(a.out);
+    const int lines = (int)a.lines;
+    const int ntiles = (lines + 15) / 16;
+    const int cp_mid = tid % CP, q_mid = tid / CP;
+    const int cp_out = tid / T, q_out = tid % T;
+    const long long kbstride = (long long)a.ny << 4;
+
+    // chunk i of this thread: f = tid + NT i -> (kb, pair, mode pair); rows of lines a, b
+    auto load = [&](float4(&ca)[NCH], float4(&cb)[NCH], int t) {
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) {
+            const int f = tid + NT * i;
+            const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
+            const int ga = 16 * t + 2 * pr;
+            const int k0 = kb * 16 + 2 * kp;
+            if (f < NKB * 64 && ga < lines && k0 <= M) {
+                const long long col = (long long)kb * kbstride + 2 * kp;
+                const cx<float> *ia = in + x_rowoff(a, ga) + col;
+                ca[i] = k0 + 1 <= M ? *reinterpret_cast<const float4 *>(ia)
+                                    : make_float4(ia[0].x, ia[0].y, 0.f, 0.f);
+                if (ga + 1 < lines) {
+                    const cx<float> *ib = in + x_rowoff(a, ga + 1) + col;
+                    cb[i] = k0 + 1 <= M ? *reinterpret_cast<const float4 *>(ib)
+                                        : make_float4(ib[0].x, ib[0].y, 0.f, 0.f);
+                } else {
+                    cb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+        }
+    };
+
+    int t = blockIdx.x;
+    float4 pa[NCH], pb[NCH];
+    if (t < ntiles) load(pa, pb, t);
+    __syncthreads();
+    for (; t < ntiles; t += gridDim.x) {
+        // spectra of the tile into LDS: slot (k, pair) = (X_a[k], X_b[k]); X[M] aside
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) {
+            const int f = tid + NT * i;
+            const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
+            const int k0 = kb * 16 + 2 * kp;
+            if (f < NKB * 64 && k0 <= M) {
+                const float4 A = pa[i], Bv = pb[i];
+                if (k0 < M) buf[p2_slot<TC>(k0, pr)] = make_float4(A.x, A.y, Bv.x, Bv.y);
+                else nyq[pr] = make_float4(A.x, A.y, Bv.x, Bv.y);
+                if (k0 + 1 < M) buf[p2_slot<TC>(k0 + 1, pr)] = make_float4(A.z, A.w, Bv.z, Bv.w);
+                else if (k0 + 1 == M) nyq[pr] = make_float4(A.z, A.w, Bv.z, Bv.w);
+            }
+        }
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(pa, pb, tn);
+        __syncthreads();
+
+        // inverse split, in place: item (k, pair) for k <= M/2 writes Zb[k] and Zb[M-k]
+        for (int f = tid; f < (M / 2 + 1) * 8; f += NT) {
+            const int k = f >> 3, pr = f & 7;
+            const float4 xk = buf[p2_slot<TC>(k, pr)];
+            float4 xm = k == 0 ? nyq[pr] : buf[p2_slot<TC>(M - k, pr)];
+            const cx<float> w = spl[k];
+            float2 Ak = make_float2(xk.x, xk.y), Bk = make_float2(xk.z, xk.w);
+            float2 Am = make_float2(xm.x, xm.y), Bm = make_float2(xm.z, xm.w);
+            if (k == 0) {  // modes 0 and M: real parts only
+                Ak.y = Bk.y = Am.y = Bm.y = 0.f;
+            }
+            const float2 wc = make_float2(w.x, -w.y);  // W_nx^-k
+            // Zb[k] = (Xk + conj Xm) + i (Xk - conj Xm) W^-k, per line
+            auto zb = [&](float2 Xk, float2 Xm, float2 ww) {
+                const float2 E = make_float2(Xk.x + Xm.x, Xk.y - Xm.y);
+                const float2 O = cmul(make_float2(Xk.x - Xm.x, Xk.y + Xm.y), ww);
+                return make_float2(E.x - O.y, E.y + O.x);
+            };
+            const float2 za = zb(Ak, Am, wc), zbv = zb(Bk, Bm, wc);
+            buf[p2_slot<TC>(k, pr)] = pack2(za, zbv);
+            if (k != 0 && 2 * k != M) {
+                // Zb[M-k] uses W^-(M-k) = -W^k
+                const float2 wm = make_float2(-w.x, -w.y);
+                buf[p2_slot<TC>(M - k, pr)] = pack2(zb(Am, Ak, wm), zb(Bm, Bk, wm));
+            }
+        }
+        __syncthreads();
+
+        cx<float> v0[16], v1[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
+            v0[m] = make_float2(x.x, x.y);
+            v1[m] = make_float2(x.z, x.w);
+        }
+        __syncthreads();
+        Dft<float, 16, 1>::run(v0);
+        Dft<float, 16, 1>::run(v1);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_mid * 16 + r, cp_mid)] = pack2(v0[r], v1[r]);
+        __syncthreads();
+        if constexpr (S == 3) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
+                v0[m] = make_float2(x.x, x.y);
+                v1[m] = make_float2(x.z, x.w);
+            }
+            __syncthreads();
+            p2_butterflies<M, 16, 16, 1>(v0, q_mid, twl + p2_twoff(M, 1));
+            p2_butterflies<M, 16, 16, 1>(v1, q_mid, twl + p2_twoff(M, 1));
+            const int k = q_mid & 15;
+            const int base = (q_mid - k) * 16 + k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(base + r * 16, cp_mid)] = pack2(v0[r], v1[r]);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const float4 x = buf[p2_slot<TC>(q_out + T * m, cp_out)];
+            v0[m] = make_float2(x.x, x.y);
+            v1[m] = make_float2(x.z, x.w);
+        }
+        p2_butterflies<M, RL, NSL, 1>(v0, q_out, twl + p2_twoff(M, S - 1));
+        p2_butterflies<M, RL, NSL, 1>(v1, q_out, twl + p2_twoff(M, S - 1));
+        {
+            const int ga = 16 * t + 2 * cp_out;
+            float *oa = out + (long long)ga * a.ld_real + 2 * q_out;
+            if (ga < lines) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) *reinterpret_cast<float2 *>(oa + 2 * T * m) = v0[m];
+            }
+            if (ga + 1 < lines) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) *reinterpret_cast<float2 *>(oa + a.ld_real + 2 * T * m) = v1[m];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+bool p2x_supported(int nx, int prec) { return prec == 0 && (nx == 512 || nx == 1024 || nx == 2048); }
+
+int p2x_threads(int nx) { return nx / 2 / 16 * 8; }
+
+size_t p2x_lds_bytes(int nx) {
+    const int M = nx / 2;
+    return (size_t)M * 16 * sizeof(float2) + (size_t)(2 * M + 1) * sizeof(float2);
+}
+
+static const void *p2x_pick(int nx, int fwd) {
+    switch (nx) {
+        case 512: return fwd ? (const void *)&k_r2c_p2<256> : (const void *)&k_c2r_p2<256>;
+        case 1024: return fwd ? (const void *)&k_r2c_p2<512> : (const void *)&k_c2r_p2<512>;
+        case 2048: return fwd ? (const void *)&k_r2c_p2<1024> : (const void *)&k_c2r_p2<1024>;
+        default: return nullptr;
+    }
+}
+
+hipError_t p2x_prepare(int nx) {
+    hipError_t e = hipSuccess;
+    for (int fwd : {0, 1}) {
+        const void *k = p2x_pick(nx, fwd);
+        if (!k) continue;
+        hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx));
+        if (r != hipSuccess && e == hipSuccess) e = r;
+    }
+    return e;
+}
+
 int p2_tc(int n) { return n <= 1024 ? 16 : 16384 / n; }
 
 size_t p2_lds_bytes(int n) { return ((size_t)n * p2_tc(n) + n) * sizeof(float2); }
@@ -241,7 +576,11 @@ static const void *p2_pick(int n, int dir, int inp, int outp) {
     return nullptr;
 }
 
-const void *p2_symbol(const PassDesc &d) { return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp); }
+const void *p2_symbol(const PassDesc &d) {
+    if (d.kind == PASS_R2C_P2) return p2x_pick(2 * d.a.fft.n, 1);
+    if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0);
+    return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
+}
 
 hipError_t p2_prepare(int n) {
     const size_t lds = p2_lds_bytes(n);

@@ -30,7 +30,7 @@ struct Side {
     long long sa, sblk, sc, sp, cpb;
 };
 
-enum PassKind { PASS_C2C = 0, PASS_R2C_X = 1, PASS_C2R_X = 2, PASS_C2C_P2 = 3 };
+enum PassKind { PASS_C2C = 0, PASS_R2C_X = 1, PASS_C2R_X = 2, PASS_C2C_P2 = 3, PASS_R2C_P2 = 4, PASS_C2R_P2 = 5 };
 
 struct PassArgs {
     const void *in;
@@ -73,6 +73,11 @@ size_t p2_lds_bytes(int n);
 hipError_t p2_prepare(int n);
 int p2_blocks_per_cu(const PassDesc &d);
 hipError_t p2_launch(const PassDesc &d, hipStream_t s);
+// Even power-of-two X stage, FP32 (fft.n of the pass is nx / 2).
+bool p2x_supported(int nx, int prec);
+int p2x_threads(int nx);
+size_t p2x_lds_bytes(int nx);
+hipError_t p2x_prepare(int nx);
 
 // LDS index with one pad slot every 16 complex elements (spreads the strided
 // Stockham writes over the banks).

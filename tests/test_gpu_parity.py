@@ -40,6 +40,9 @@ SHAPES = [
     (1024, 6, 40),
     (3, 2048, 10),
     (4096, 2, 6),
+    (5, 7, 512),      # even power-of-two X (half-length path): 35 lines, tiles cross z planes
+    (3, 5, 2048),
+    (40, 24, 1024),
     (1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 5, 3), (3, 1, 4),
 ]
 
@@ -102,8 +105,8 @@ def test_forward_and_backward_match_oracle(shape, prec, stride1):
 
 
 @pytest.mark.parametrize("prec", [pf.PF_F32, pf.PF_F64])
-@pytest.mark.parametrize("shape", [(24, 20, 36), (9, 7, 15), (6, 10, 480), (3, 1024, 2), (16, 512, 36), (1024, 6, 40)],
-                         ids=ids)
+@pytest.mark.parametrize("shape", [(24, 20, 36), (9, 7, 15), (6, 10, 480), (3, 1024, 2), (16, 512, 36), (1024, 6, 40),
+                                   (5, 7, 512), (40, 24, 1024)], ids=ids)
 def test_each_pass_matches_oracle_stage(shape, prec):
     """Every kernel alone against the oracle's own stage (forward X, Y, Z; backward Z, Y, X)."""
     nz, ny, nx = shape
@@ -147,7 +150,8 @@ def test_each_pass_matches_oracle_stage(shape, prec):
         assert rel(r.cpu().numpy(), oracle.stage_x_c2r(B, nx)) < tol
 
 
-@pytest.mark.parametrize("shape", [(24, 20, 36), (64, 64, 64), (16, 512, 36), (1024, 6, 40)], ids=ids)
+@pytest.mark.parametrize("shape", [(24, 20, 36), (64, 64, 64), (16, 512, 36), (1024, 6, 40), (40, 24, 1024)],
+                         ids=ids)
 def test_repeat_runs_are_bitwise_identical(shape):
     """Same input, same kernels: results must not depend on timing (catches missing barriers)."""
     nz, ny, nx = shape
