@@ -44,31 +44,41 @@ __device__ __forceinline__ int p2_slot(int p, int cp) {
     return ((p ^ ((p >> 4) & 1)) * CP) + (cp ^ (((p >> 1) ^ (p >> 5)) & (CP - 1)));
 }
 
-// One stage's butterflies on the 16 registers of a column: butterfly i
-// (j = q + i N/16) takes v[i + r 16/R], r < R, twiddles by W_{NS R}^{r k},
-// k = j mod NS, and leaves its R outputs in the same registers.
+// One stage's butterflies on the 16 registers of each of a thread's two
+// columns: butterfly i (j = q + i N/16) takes v[i + r 16/R], r < R, twiddles
+// by W_{NS R}^{r k}, k = j mod NS, and leaves its R outputs in the same
+// registers.  Each twiddle is read once and applied to both columns.
 template <int N, int R, int NS, int DIR>
-__device__ __forceinline__ void p2_butterflies(cx<float> (&v)[16], int q, const cx<float> *tws) {
+__device__ __forceinline__ void p2_butterflies2(cx<float> (&v0)[16], cx<float> (&v1)[16], int q,
+                                                const cx<float> *tws) {
     constexpr int T = N / 16;
     constexpr int BPT = 16 / R;
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
         const int j = q + i * T;
         const int k = j & (NS - 1);
-        cx<float> w[R];
+        cx<float> w0[R], w1[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) w[r] = v[i + r * BPT];
+        for (int r = 0; r < R; ++r) {
+            w0[r] = v0[i + r * BPT];
+            w1[r] = v1[i + r * BPT];
+        }
         if (NS > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 cx<float> t = tws[k * (R - 1) + r - 1];
                 if (DIR > 0) t.y = -t.y;
-                w[r] = cmul(w[r], t);
+                w0[r] = cmul(w0[r], t);
+                w1[r] = cmul(w1[r], t);
             }
         }
-        Dft<float, R, DIR>::run(w);
+        Dft<float, R, DIR>::run(w0);
+        Dft<float, R, DIR>::run(w1);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[i + r * BPT] = w[r];
+        for (int r = 0; r < R; ++r) {
+            v0[i + r * BPT] = w0[r];
+            v1[i + r * BPT] = w1[r];
+        }
     }
 }
 
@@ -164,8 +174,7 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
                 v1[m] = make_float2(x.z, x.w);
             }
             __syncthreads();
-            p2_butterflies<N, 16, 16, DIR>(v0, q_mid, twl + p2_twoff(N, 1));
-            p2_butterflies<N, 16, 16, DIR>(v1, q_mid, twl + p2_twoff(N, 1));
+            p2_butterflies2<N, 16, 16, DIR>(v0, v1, q_mid, twl + p2_twoff(N, 1));
             const int k = q_mid & 15;
             const int base = (q_mid - k) * 16 + k;
 #pragma unroll
@@ -180,8 +189,7 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
             v0[m] = make_float2(x.x, x.y);
             v1[m] = make_float2(x.z, x.w);
         }
-        p2_butterflies<N, RL, NSL, DIR>(v0, q_out, twl + p2_twoff(N, S - 1));
-        p2_butterflies<N, RL, NSL, DIR>(v1, q_out, twl + p2_twoff(N, S - 1));
+        p2_butterflies2<N, RL, NSL, DIR>(v0, v1, q_out, twl + p2_twoff(N, S - 1));
         {
             int ncol;
             const long long b = side_addr(a.out_s, t, cp_out, q_out, ncol);
@@ -293,8 +301,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
                 v1[m] = make_float2(x.z, x.w);
             }
             __syncthreads();
-            p2_butterflies<M, 16, 16, -1>(v0, q_mid, twl + p2_twoff(M, 1));
-            p2_butterflies<M, 16, 16, -1>(v1, q_mid, twl + p2_twoff(M, 1));
+            p2_butterflies2<M, 16, 16, -1>(v0, v1, q_mid, twl + p2_twoff(M, 1));
             const int k = q_mid & 15;
             const int base = (q_mid - k) * 16 + k;
 #pragma unroll
@@ -308,8 +315,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
             v1[m] = make_float2(x.z, x.w);
         }
         __syncthreads();
-        p2_butterflies<M, RL, NSL, -1>(v0, q_mid, twl + p2_twoff(M, S - 1));
-        p2_butterflies<M, RL, NSL, -1>(v1, q_mid, twl + p2_twoff(M, S - 1));
+        p2_butterflies2<M, RL, NSL, -1>(v0, v1, q_mid, twl + p2_twoff(M, S - 1));
 #pragma unroll
         for (int m = 0; m < 16; ++m) buf[p2_slot<TC>(q_mid + T * m, cp_mid)] = pack2(v0[m], v1[m]);
         __syncthreads();
@@ -356,7 +362,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
 }
 
 template <int M>
-__global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2(PassArgs a) {
+__global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     constexpr int TC = 16;
     constexpr int T = M / 16;
     constexpr int CP = 8;
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2(PassArgs a) {
     constexpr int RL = p2_radix(M, S - 1);
     constexpr int NSL = p2_ns(M, S - 1);
     constexpr int NKB = M / 16 + 1;
-    constexpr int NCH = (NKB * 64 + NT - 1) / NT;  // 16-byte chunk pairs per thread per tile
+    constexpr int NCH = (M / 16) * 64 / NT;  // 16-byte chunk pairs per thread per tile (modes < M)
     float4 *buf = reinterpret_cast<float4 *>(pf_smem);
     cx<float> *twl = reinterpret_cast<cx<float> *>(buf + M * CP);
     cx<float> *spl = twl + M;
@@ -382,33 +388,44 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2(PassArgs a) {
     const int cp_out = tid / T, q_out = tid % T;
     const long long kbstride = (long long)a.ny << 4;
 
-    // chunk i of this thread: f = tid + NT i -> (kb, pair, mode pair); rows of lines a, b
-    auto load = [&](float4(&ca)[NCH], float4(&cb)[NCH], int t) {
+    // chunk i of this thread: f = tid + NT i -> (kb, pair, mode pair); rows of lines a, b.
+    // Addresses: one 64-bit tile base (uniform) plus 32-bit offsets (16 lines
+    // span at most 16 z planes of the workspace).
+    auto load = [&](float4(&ca)[NCH], float4(&cb)[NCH], float2 &nq, int t) {
+        const int g0 = 16 * t;
+        const int z0 = g0 / a.ny;
+        const int y0 = g0 - z0 * a.ny;
+        const cx<float> *tb = in + ((((long long)z0 * a.nkb) * a.ny + y0) << 4);
+        const int zplane = a.nkb * a.ny * 16;  // elements per z plane of the workspace
+        const int kbs = a.ny * 16;
+        // line l of the tile (g = g0 + l, any number of z planes when ny < 16)
+        // starts at row offset rowrel(l) from the tile base (z0, y0)
+        auto rowrel = [&](int l) {
+            const int g = g0 + l;
+            const int z = g / a.ny;
+            const int y = g - z * a.ny;
+            return (z - z0) * zplane + (y - y0) * 16;
+        };
 #pragma unroll
         for (int i = 0; i < NCH; ++i) {
             const int f = tid + NT * i;
             const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
-            const int ga = 16 * t + 2 * pr;
-            const int k0 = kb * 16 + 2 * kp;
-            if (f < NKB * 64 && ga < lines && k0 <= M) {
-                const long long col = (long long)kb * kbstride + 2 * kp;
-                const cx<float> *ia = in + x_rowoff(a, ga) + col;
-                ca[i] = k0 + 1 <= M ? *reinterpret_cast<const float4 *>(ia)
-                                    : make_float4(ia[0].x, ia[0].y, 0.f, 0.f);
-                if (ga + 1 < lines) {
-                    const cx<float> *ib = in + x_rowoff(a, ga + 1) + col;
-                    cb[i] = k0 + 1 <= M ? *reinterpret_cast<const float4 *>(ib)
-                                        : make_float4(ib[0].x, ib[0].y, 0.f, 0.f);
-                } else {
-                    cb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
+            const int col = kb * kbs + 2 * kp;
+            if (g0 + 2 * pr < lines) ca[i] = *reinterpret_cast<const float4 *>(tb + rowrel(2 * pr) + col);
+            if (g0 + 2 * pr + 1 < lines) cb[i] = *reinterpret_cast<const float4 *>(tb + rowrel(2 * pr + 1) + col);
+            else cb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        // mode M (first slot of the last column block) of line tid
+        if (tid < 16) {
+            if (g0 + tid < lines) nq = tb[rowrel(tid) + (NKB - 1) * kbs];
+            else nq = make_float2(0.f, 0.f);
         }
     };
 
     int t = blockIdx.x;
     float4 pa[NCH], pb[NCH];
-    if (t < ntiles) load(pa, pb, t);
+    float2 pq;
+    if (t < ntiles) load(pa, pb, pq, t);
     __syncthreads();
     for (; t < ntiles; t += gridDim.x) {
         // spectra of the tile into LDS: slot (k, pair) = (X_a[k], X_b[k]); X[M] aside
@@ -417,16 +434,13 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2(PassArgs a) {
             const int f = tid + NT * i;
             const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
             const int k0 = kb * 16 + 2 * kp;
-            if (f < NKB * 64 && k0 <= M) {
-                const float4 A = pa[i], Bv = pb[i];
-                if (k0 < M) buf[p2_slot<TC>(k0, pr)] = make_float4(A.x, A.y, Bv.x, Bv.y);
-                else nyq[pr] = make_float4(A.x, A.y, Bv.x, Bv.y);
-                if (k0 + 1 < M) buf[p2_slot<TC>(k0 + 1, pr)] = make_float4(A.z, A.w, Bv.z, Bv.w);
-                else if (k0 + 1 == M) nyq[pr] = make_float4(A.z, A.w, Bv.z, Bv.w);
-            }
+            const float4 A = pa[i], Bv = pb[i];
+            buf[p2_slot<TC>(k0, pr)] = make_float4(A.x, A.y, Bv.x, Bv.y);
+            buf[p2_slot<TC>(k0 + 1, pr)] = make_float4(A.z, A.w, Bv.z, Bv.w);
         }
+        if (tid < 16) reinterpret_cast<float2 *>(nyq)[(tid >> 1) * 2 + (tid & 1)] = pq;
         const int tn = t + gridDim.x;
-        if (tn < ntiles) load(pa, pb, tn);
+        if (tn < ntiles) load(pa, pb, pq, tn);
         __syncthreads();
 
         // inverse split, in place: item (k, pair) for k <= M/2 writes Zb[k] and Zb[M-k]
@@ -478,8 +492,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2(PassArgs a) {
                 v1[m] = make_float2(x.z, x.w);
             }
             __syncthreads();
-            p2_butterflies<M, 16, 16, 1>(v0, q_mid, twl + p2_twoff(M, 1));
-            p2_butterflies<M, 16, 16, 1>(v1, q_mid, twl + p2_twoff(M, 1));
+            p2_butterflies2<M, 16, 16, 1>(v0, v1, q_mid, twl + p2_twoff(M, 1));
             const int k = q_mid & 15;
             const int base = (q_mid - k) * 16 + k;
 #pragma unroll
@@ -492,8 +505,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2(PassArgs a) {
             v0[m] = make_float2(x.x, x.y);
             v1[m] = make_float2(x.z, x.w);
         }
-        p2_butterflies<M, RL, NSL, 1>(v0, q_out, twl + p2_twoff(M, S - 1));
-        p2_butterflies<M, RL, NSL, 1>(v1, q_out, twl + p2_twoff(M, S - 1));
+        p2_butterflies2<M, RL, NSL, 1>(v0, v1, q_out, twl + p2_twoff(M, S - 1));
         {
             const int ga = 16 * t + 2 * cp_out;
             float *oa = out + (long long)ga * a.ld_real + 2 * q_out;
