@@ -35,33 +35,113 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024, help="grid edge (default 1024)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=512, help="grid edge of the CPU baseline sample")
+    ap.add_argument("--cpu-n", type=int, default=1024, help="grid edge of the CPU baseline sample")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, WRITE_SIZE) "
+                         "into profiles/ and exit")
+    ap.add_argument("--pmc-commands", nargs=2, default=None, help="the two commands that produced the CSVs")
     return ap.parse_args()
 
 
-def traffic_from_profile(kernel: str, n: int):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it matches the current kernels."""
+KERNEL_SOURCES = ("kernels.hip", "kernels_p2.hip", "fft_device.h", "pf_internal.h")
+PASS_ORDER = ("fwd_x_r2c", "fwd_y_c2c", "fwd_z_c2c", "bwd_z_c2c", "bwd_y_c2c", "bwd_x_c2r")
+
+
+def kernels_digest() -> str:
+    """sha256 over the kernel sources: counters taken from other kernels do not apply."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{n}cubed.json")
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1905_02803_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_path(n: int) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_fft_{n}cubed.json")
+
+
+def traffic_from_profile(pass_name: str, n: int):
+    """Measured HBM bytes per launch of a pass from the committed counter summary, if the kernels match."""
+    path = traffic_path(n)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, "paper_1905_02803_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("kernels_sha256") != digest:
+    if rec.get("kernels_sha256") != kernels_digest():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    p = rec.get("passes", {}).get(pass_name)
+    return None if p is None else p["hbm_bytes"]
 
 
-def cpu_baseline(n: int):
-    """The oracle, untuned, on one forward+backward pair of an n^3 GRF (a bounded sample)."""
+def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
+    """Turn two rocprofv3 --pmc runs of this benchmark into profiles/traffic_fft_<n>cubed.{json,txt}.
+
+    FETCH_SIZE / WRITE_SIZE are read per dispatch (KiB) and scaled by what the
+    same counters read for the plain copy kernel k_copy, whose bytes are known.
+    The transform's own kernels are assigned to passes in launch order
+    (forward X, Y, Z, backward Z, Y, X, repeated).
+    """
+    import csv
+    import statistics
+
+    def read(path):
+        rows = list(csv.DictReader(open(path)))
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    out = {"kernels_sha256": kernels_digest(), "grid": n, "commands": commands, "passes": {}}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in read(path) if r["Counter_Name"] == counter]
+        copies = [float(r["Counter_Value"]) * 1024.0 for r in rows if "k_copy" in r["Kernel_Name"]]
+        ours = [r for r in rows if "pf::k_" in r["Kernel_Name"] and "k_copy" not in r["Kernel_Name"]]
+        copy_bytes = COPY_BYTES(n)
+        factor = copy_bytes / statistics.mean(copies) if copies else None
+        out[counter] = {"copy_bytes_per_dispatch": copy_bytes,
+                        "copy_counter_bytes": statistics.mean(copies) if copies else None,
+                        "scale": factor}
+        per = {}
+        for i, r in enumerate(ours):
+            name = PASS_ORDER[i % len(PASS_ORDER)]
+            per.setdefault(name, {"kernel": r["Kernel_Name"], "vals": []})["vals"].append(
+                float(r["Counter_Value"]) * 1024.0 * (factor or 1.0))
+        for name, d in per.items():
+            e = out["passes"].setdefault(name, {"kernel": d["kernel"]})
+            e["fetch_bytes" if counter == "FETCH_SIZE" else "write_bytes"] = statistics.mean(d["vals"])
+            e["dispatches"] = len(d["vals"])
+    for e in out["passes"].values():
+        e["hbm_bytes"] = e.get("fetch_bytes", 0.0) + e.get("write_bytes", 0.0)
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(traffic_path(n), "w") as f:
+        json.dump(out, f, indent=1)
+    lines = [f"HBM traffic per launch, {n}^3 FP32 R2C+C2R (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by k_copy)",
+             f"commands: {commands}",
+             f"copy probe: {COPY_BYTES(n)} B read and written per dispatch; "
+             f"scale FETCH {out['FETCH_SIZE']['scale']}, WRITE {out['WRITE_SIZE']['scale']}",
+             f"{'pass':<12} {'fetch GB':>9} {'write GB':>9} {'total GB':>9}  kernel"]
+    for name in PASS_ORDER:
+        e = out["passes"].get(name)
+        if e:
+            lines.append(f"{name:<12} {e.get('fetch_bytes', 0) / 1e9:9.3f} {e.get('write_bytes', 0) / 1e9:9.3f} "
+                         f"{e['hbm_bytes'] / 1e9:9.3f}  {e['kernel']}")
+    with open(traffic_path(n).replace(".json", ".txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def COPY_BYTES(n: int) -> int:
+    """Bytes the copy probe moves each way: the n^3 float32 real array."""
+    return 4 * n ** 3
+
+
+def cpu_baseline(n: int, u=None):
+    """The oracle, untuned, on one forward+backward pair of an n^3 GRF (the benchmark's own input if given)."""
     import oracle
     import synth
 
-    u = synth.grf(3, (n, n, n))
+    if u is None or u.shape != (n, n, n):
+        u = synth.grf(3, (n, n, n))
     t0 = time.perf_counter()
     U = oracle.r2c3d(u)
     oracle.c2r3d(U, n)
@@ -78,6 +158,9 @@ def cpu_baseline(n: int):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.n, args.pmc_commands)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
               "note, not built", file=sys.stderr)
@@ -94,7 +177,6 @@ def main():
     u_host = synth.grf(3, (nz, ny, nx))
     plan = pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F32, stride1=1))
     u = torch.from_numpy(u_host).to(dev)
-    del u_host
     U = plan.empty_complex(dev)
     r = plan.empty_real(dev)
     stream = torch.cuda.current_stream()
@@ -109,6 +191,18 @@ def main():
     # round-trip error of the last warm-up step (GPU only): ||btran(ftran u)/N - u|| / ||u||
     Nf = float(nx) * ny * nz
     rt_err = (torch.linalg.vector_norm((r.double() / Nf - u.double())) / torch.linalg.vector_norm(u.double())).item()
+
+    # HBM ceiling: a plain copy of the real array (the same bytes in and out as one pass of it)
+    copy_reps = 5
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    pf.pf_copy(r.data_ptr(), u.data_ptr(), COPY_BYTES(n), stream.cuda_stream)
+    c0.record(stream)
+    for _ in range(copy_reps):
+        pf.pf_copy(r.data_ptr(), u.data_ptr(), COPY_BYTES(n), stream.cuda_stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_GBps = 2.0 * COPY_BYTES(n) / (c0.elapsed_time(c1) / copy_reps * 1e-3) / 1e9
 
     plan.set_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -139,7 +233,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(min(args.cpu_n, n))
+        cpu = cpu_baseline(min(args.cpu_n, n), u_host)
+    del u_host
 
     out = {
         "metric": "3D R2C+C2R GFLOP/s & HBM GB/s at 1024^3; MFMA-mixed vs FP32 at stated err",
@@ -157,6 +252,7 @@ def main():
         "config": {"workload": f"3D R2C+C2R FP32 {nx}x{ny}x{nz}, GRF |k|^-5/3, STRIDE1, out-of-place",
                    "grid": [nx, ny, nz], "precision": "f32", "math": "plain", "layout": "1x1"},
         "hbm_GBps_alg": alg_bytes / (ms * 1e-3) / 1e9,
+        "copy_probe_GBps": copy_GBps,
         "round_trip_rel_l2": rt_err,
         "roofline": {
             "bound": "hbm",
@@ -165,6 +261,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom["alg_GBps"] / HBM_PEAK_GBS,
+            "frac_of_copy_probe": dom["alg_GBps"] / copy_GBps,
             "traffic": traffic_from_profile(dom["pass"], n),
         },
         "passes": passes,

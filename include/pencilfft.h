@@ -194,6 +194,18 @@ const char *pf_pass_name(const pf_plan *p, int dir, int pass);
  */
 double pf_pass_bytes(const pf_plan *p, int dir, int pass);
 
+/* ---- HBM roofline probe --------------------------------------------------- */
+
+/*
+ * Plain device-to-device copy of `bytes` bytes (a multiple of 16, both
+ * pointers 16-byte aligned, non-overlapping), enqueued on `stream`.  It is the
+ * measured ceiling for the memory term of the paper's cost model (Eq. 3: the
+ * bytes each element moves divided by the memory bandwidth): every transform
+ * pass moves its array once in and once out, as this copy does.  Returns
+ * PF_EINVAL for NULL pointers, PF_EALIGN for misaligned pointers or sizes.
+ */
+int pf_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /* ---- per-pass timing with HIP events ------------------------------------ */
 
 /*

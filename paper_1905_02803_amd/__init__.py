@@ -39,7 +39,7 @@ PF_DIR_FORWARD, PF_DIR_BACKWARD = 0, 1
 EXPORTED = (
     "pf_layout_init", "pf_check", "pf_query_dims", "pf_setup", "pf_get_dims", "pf_workspace_bytes",
     "pf_set_workspace", "pf_ftran_r2c", "pf_btran_c2r", "pf_destroy", "pf_strerror", "pf_num_passes",
-    "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing",
+    "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
 )
 
 
@@ -104,6 +104,7 @@ def lib():
             "pf_pass_name": (ctypes.c_char_p, [vp, i, i]),
             "pf_pass_bytes": (ctypes.c_double, [vp, i, i]),
             "pf_set_timing": (i, [vp, i]),
+            "pf_copy": (i, [vp, vp, sz, vp]),
             "pf_get_timing": (i, [vp, i, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
         }
         for name, (res, args) in sig.items():
@@ -197,6 +198,11 @@ def pf_get_timing(h, direction: int, pass_index: int):
     n = ctypes.c_longlong()
     _raise(lib().pf_get_timing(h, direction, pass_index, ctypes.byref(ms), ctypes.byref(n)), "pf_get_timing")
     return ms.value, n.value
+
+
+def pf_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int = 0) -> None:
+    """Plain device copy (the HBM roofline probe)."""
+    _raise(lib().pf_copy(dst_ptr, src_ptr, nbytes, stream), "pf_copy")
 
 
 def pf_get_dims(h, pencil, r1=0, r2=0):

@@ -600,6 +600,12 @@ double pf_pass_bytes(const pf_plan *p, int dir, int pass) {
     return p->pass_bytes[dir][pass];
 }
 
+int pf_copy(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return PF_EINVAL;
+    if (!aligned16(dst) || !aligned16(src) || (bytes & 15u)) return PF_EALIGN;
+    return hip_status(pf::launch_copy(src, dst, bytes, (hipStream_t)stream));
+}
+
 int pf_set_timing(pf_plan *p, int enable) {
     if (!p) return PF_EINVAL;
     release_timing(p);

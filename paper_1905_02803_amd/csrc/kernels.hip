@@ -261,6 +261,36 @@ __global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
     }
 }
 
+// Plain HBM copy, 16 bytes per lane, a fixed number of 16-byte words per
+// thread (all loads issued before the stores).  The bandwidth this reaches is
+// the practical ceiling the transform passes are measured against.
+__global__ __launch_bounds__(512) void k_copy(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n) {
+    constexpr int U = 4;
+    const size_t base = (size_t)blockIdx.x * blockDim.x * U + threadIdx.x;
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const size_t i = base + (size_t)u * blockDim.x;
+        if (i < n) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const size_t i = base + (size_t)u * blockDim.x;
+        if (i < n) dst[i] = v[u];
+    }
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const size_t per_block = 512 * 4;
+    const size_t blocks = (n + per_block - 1) / per_block;
+    if (blocks > 0x7fffffffULL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(512), 0, s, reinterpret_cast<const float4 *>(src),
+                       reinterpret_cast<float4 *>(dst), n);
+    return hipGetLastError();
+}
+
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,

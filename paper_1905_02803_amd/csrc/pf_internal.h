@@ -64,6 +64,8 @@ struct PassDesc {
 hipError_t prepare_kernels(size_t max_lds);
 // Enqueue one pass.
 hipError_t launch_pass(const PassDesc &d, hipStream_t s);
+// Plain 16-byte-per-lane device copy (bytes a multiple of 16).
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // Power-of-two FP32 C2C pass (kernels_p2.hip).
 bool p2_supported(int n, int prec);
