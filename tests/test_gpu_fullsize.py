@@ -1,0 +1,97 @@
+"""Parity at the benchmark's own grid sizes, in the launch configuration bench.py times.
+
+* 1024^3 FP32 Gaussian random field (shell spectrum |k|^-5/3), STRIDE1,
+  out-of-place: the forward output against the oracle's whole transform, the
+  backward of an arbitrary half spectrum against the oracle's staged C2R, the
+  round trip (Sec. 4.1) and Parseval.
+* 512^3 and 480 x 360 x 250 FP32 random fields: the same checks.
+* 32^3 FP64, uniform[-1, 1] from seed 1: forward, backward and round trip at
+  1e-12.
+The oracle runs in FP64 on the host (OpenMP); FP32 inputs are promoted exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1905_02803_amd as pf  # noqa: E402
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def half_weights(nx):
+    w = np.full(nx // 2 + 1, 2.0)
+    w[0] = 1.0
+    if nx % 2 == 0:
+        w[-1] = 1.0
+    return w
+
+
+def check_grid(shape, seed, tol):
+    nz, ny, nx = shape
+    print(f"case shape={shape} seed={seed}", flush=True)
+    u = synth.grf(seed, shape)
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F32, stride1=1)) as plan:
+        ud = torch.from_numpy(u).cuda()
+        Ud = plan.ftran(ud)
+        back = plan.btran(Ud)
+        torch.cuda.synchronize()
+        # round trip and Parseval on the device result (independent of the oracle)
+        N = float(nx) * ny * nz
+        rt = (torch.linalg.vector_norm(back.double() / N - ud.double()) / torch.linalg.vector_norm(ud.double())).item()
+        assert rt < tol, rt
+        w = torch.from_numpy(half_weights(nx)).cuda()
+        e_spec = (Ud.abs().double() ** 2 * w[:, None, None]).sum().item() / N
+        e_real = (ud.double() ** 2).sum().item()
+        assert abs(e_spec - e_real) / e_real < tol
+        del back
+        got = Ud.cpu().numpy()
+        del Ud
+        ref = oracle.to_stride1(oracle.r2c3d(u))
+        err = rel(got, ref)
+        print(f"forward rel L2 {err:.3e}, round trip {rt:.3e}", flush=True)
+        assert err < tol
+        del got, ref
+        # backward of an arbitrary half spectrum
+        V = synth.complex_half(seed + 1000, (nz, ny, nx // 2 + 1)).astype(np.complex64)
+        Vd = torch.from_numpy(oracle.to_stride1(V)).cuda()
+        vd = plan.btran(Vd)
+        torch.cuda.synchronize()
+        del Vd
+        err_b = rel(vd.cpu().numpy(), oracle.c2r3d(V, nx))
+        print(f"backward rel L2 {err_b:.3e}", flush=True)
+        assert err_b < tol
+
+
+@pytest.mark.timeout(1200)
+def test_1024_cubed_grf_matches_oracle():
+    check_grid((1024, 1024, 1024), 3, 1e-6)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("shape,seed", [((512, 512, 512), 2), ((250, 360, 480), 22)])
+def test_512_cubed_and_uneven_grf_match_oracle(shape, seed):
+    check_grid(shape, seed, 1e-6)
+
+
+def test_32_cubed_f64_matches_oracle():
+    shape = (32, 32, 32)
+    u = synth.uniform(1, shape)
+    with pf.Plan(32, 32, 32, pf.Layout(precision=pf.PF_F64)) as plan:
+        Ud = plan.ftran(torch.from_numpy(u).cuda())
+        back = plan.btran(Ud)
+        torch.cuda.synchronize()
+        assert rel(Ud.cpu().numpy(), oracle.to_stride1(oracle.r2c3d(u))) < 1e-12
+        assert rel(back.cpu().numpy() / u.size, u) < 1e-12
+        V = synth.complex_half(2, (32, 32, 17))
+        vd = plan.btran(torch.from_numpy(oracle.to_stride1(V)).cuda())
+        torch.cuda.synchronize()
+        assert rel(vd.cpu().numpy(), oracle.c2r3d(V, 32)) < 1e-12
