@@ -83,8 +83,14 @@ extern "C" {
  * Layout and options of a plan.  Initialise with pf_layout_init, then change
  * fields.  m1 x m2 is the virtual processor grid of Sec. 2 (m1 * m2 = P; 1 x P
  * is the slab decomposition of Sec. 4.3); the default 1 x 1 is one whole grid.
- * stride1 selects the Table 1 storage orders (Sec. 3.2, 3.3).  useeven pads
- * exchange blocks to equal size (Sec. 3.4).  inplace: in == out, and the
+ * With m1 * m2 > 1 the user arrays are the P ranks' local pencil blocks of
+ * Table 1, concatenated in rank order r2 * m1 + r1, each block in its Table 1
+ * storage order (pf_query_dims gives each block's extents): the forward input
+ * is the ranks' X-pencils, the forward output their Z-pencils (and the reverse
+ * for the backward transform).  The results equal the corresponding slices of
+ * the 1 x 1 transform bit for bit.  stride1 selects the Table 1 storage orders
+ * (Sec. 3.2, 3.3).  useeven pads exchange blocks to equal size (Sec. 3.4; not
+ * built: pf_setup returns PF_EUNSUPPORTED).  inplace: in == out, and the
  * buffer must hold max(real, complex) bytes; real data sits unpadded at the
  * start of the buffer (Sec. 3.1 lists in- and out-of-place transforms).
  */
@@ -170,20 +176,25 @@ const char *pf_strerror(int code);
 
 /*
  * Number of HBM passes (kernel launches) one transform makes in direction dir
- * (PF_DIR_FORWARD or PF_DIR_BACKWARD).
+ * (PF_DIR_FORWARD or PF_DIR_BACKWARD): 3 for a 1 x 1 grid, 5 for m1 * m2 > 1
+ * (a pack pass before and an unpack pass after the three transform passes).
  */
 int pf_num_passes(const pf_plan *p, int dir);
 
 /*
- * Run pass `pass` of direction `dir` alone.  Between passes the data lives in
- * the workspace layout: complex [nz][nkb][ny][B] where B = 128 bytes / complex
- * size (16 for F32, 8 for F64), nkb = ceil(nxh / B), and mode kx of line
- * (y, z) sits at [z][kx / B][y][kx % B]; slots with kx >= nxh are unused.
- * Forward: pass 0 X stage (user real -> workspace), pass 1 Y stage (workspace
- * in place), pass 2 Z stage (workspace -> user complex).  Backward: pass 0 Z
- * stage (user complex -> workspace), pass 1 Y stage (in place), pass 2 X stage
- * (workspace -> user real).  `in`/`out` that name the workspace may be any
- * buffer of pf_workspace_bytes bytes.  pass_name writes a short static name.
+ * Run pass `pass` of direction `dir` alone.  Between transform passes the
+ * data lives in the workspace layout: complex [nz][nkb][ny][B] where B = 128
+ * bytes / complex size (16 for F32, 8 for F64), nkb = ceil(nxh / B), and mode
+ * kx of line (y, z) sits at [z][kx / B][y][kx % B]; slots with kx >= nxh are
+ * unused.  For a 1 x 1 grid -- forward: pass 0 X stage (user real ->
+ * workspace), pass 1 Y stage (workspace in place), pass 2 Z stage (workspace ->
+ * user complex); backward: pass 0 Z stage (user complex -> workspace), pass 1 Y
+ * stage (in place), pass 2 X stage (workspace -> user real).  For m1 * m2 > 1
+ * the transform passes are 1 .. 3 and read / write the global arrays
+ * ([nz][ny][nx] real, the 1 x 1 Z-pencil layout complex); pass 0 packs the
+ * user's blocks into the global array and pass 4 unpacks the global array into
+ * the user's blocks.  `in`/`out` that name the workspace may be any buffer of
+ * pf_workspace_bytes bytes.  pass_name returns a short static name.
  */
 int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *stream);
 const char *pf_pass_name(const pf_plan *p, int dir, int pass);

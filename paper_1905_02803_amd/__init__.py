@@ -348,7 +348,7 @@ def workspace_to_half_spectrum(ws, nx: int, ny: int, nz: int):
     nxh = nx // 2 + 1
     B = 128 // ws.element_size()
     nkb = (nxh + B - 1) // B
-    w = ws.reshape(nz, nkb, ny, B).permute(0, 2, 1, 3).reshape(nz, ny, nkb * B)
+    w = ws[: nz * nkb * ny * B].reshape(nz, nkb, ny, B).permute(0, 2, 1, 3).reshape(nz, ny, nkb * B)
     return w[:, :, :nxh]
 
 
@@ -357,7 +357,7 @@ def half_spectrum_to_workspace(U, ws):
     nz, ny, nxh = U.shape
     B = 128 // ws.element_size()
     nkb = (nxh + B - 1) // B
-    w = ws.reshape(nz, nkb, ny, B)
+    w = ws[: nz * nkb * ny * B].reshape(nz, nkb, ny, B)
     full = U.new_zeros((nz, ny, nkb * B))
     full[:, :, :nxh] = U
     w.copy_(full.reshape(nz, ny, nkb, B).permute(0, 2, 1, 3))

@@ -19,7 +19,7 @@ using pf::Side;
 
 namespace {
 
-constexpr int kPasses = 3;
+constexpr int kPasses = 5;  // at most: pack, X/Z, Y, Z/X, unpack
 constexpr size_t kLdsBudget = 80 * 1024;  // two workgroups per CU fit in 160 KB
 
 struct EventPair {
@@ -43,9 +43,11 @@ struct pf_plan {
     size_t tw_off[4];
     FftSpec fxh;   // nx / 2 plan of the even power-of-two X stage
     bool fast_x;
-    void *ws;
+    void *ws;          // the workspace: W, then (m1 m2 > 1) the global-array buffer
     size_t ws_bytes;
+    size_t w_bytes;    // bytes of W
     bool own_ws;
+    bool blocked;      // m1 m2 > 1: user arrays are the concatenated Table 1 blocks
     int npass[2];
     PassDesc pass[2][kPasses];
     const char *pass_names[2][kPasses];
@@ -169,7 +171,6 @@ int check_impl(int nx, int ny, int nz, const pf_layout *l) {
 
 // Options accepted by pf_check but not built into the transform yet.
 int built_options(const pf_layout *l) {
-    if (l->m1 != 1 || l->m2 != 1) return PF_EUNSUPPORTED;
     if (l->math != PF_PLAIN) return PF_EUNSUPPORTED;
     if (l->third != PF_THIRD_FFT) return PF_EUNSUPPORTED;
     if (l->useeven) return PF_EUNSUPPORTED;
@@ -240,6 +241,56 @@ Side user_side(const pf_plan *p, long long CB) {
     s.sblk = 0;
     s.cpb = CB;
     return s;
+}
+
+// m1 x m2 grids: pack the ranks' blocks into the global array before the three
+// passes and unpack the result into the ranks' blocks after them (the paper's
+// pack / exchange / unpack around each transpose, Sec. 3.3, as on-device
+// reorders of whole lines).
+void add_remaps(pf_plan *p, int dir) {
+    const int rw = p->lay.precision == PF_F64 ? 2 : 1;  // 4-byte words per real
+    auto remap = [&](int kind, int gather) {
+        PassDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.kind = pf::PASS_REMAP;
+        d.prec = p->lay.precision;
+        pf::RemapArgs &r = d.r;
+        r.kind = kind;
+        r.gather = gather;
+        r.words = kind == pf::REMAP_XPENCIL ? rw : 2 * rw;
+        r.nx = p->nx, r.ny = p->ny, r.nz = p->nz, r.nxh = p->nxh, r.m1 = p->lay.m1, r.m2 = p->lay.m2;
+        if (kind == pf::REMAP_XPENCIL) r.nlines = (long long)p->ny * p->nz;
+        else if (kind == pf::REMAP_ZSTRIDE1) r.nlines = (long long)p->nxh * p->ny;
+        else r.nlines = (long long)p->nz * p->ny * p->lay.m1;
+        d.blocks = (unsigned)r.nlines;
+        d.threads = 256;
+        return d;
+    };
+    const int zkind = p->lay.stride1 ? pf::REMAP_ZSTRIDE1 : pf::REMAP_ZXYZ;
+    const double rs = p->lay.precision == PF_F64 ? 8.0 : 4.0;
+    const double xb = 2.0 * p->nx * p->ny * p->nz * rs;
+    const double zb = 2.0 * 2.0 * p->nxh * p->ny * p->nz * rs;
+    for (int i = 3; i >= 1; --i) {
+        p->pass[dir][i] = p->pass[dir][i - 1];
+        p->pass_names[dir][i] = p->pass_names[dir][i - 1];
+        p->pass_bytes[dir][i] = p->pass_bytes[dir][i - 1];
+    }
+    if (dir == 0) {
+        p->pass[0][0] = remap(pf::REMAP_XPENCIL, 1);
+        p->pass_names[0][0] = "fwd_pack_x_pencils";
+        p->pass_bytes[0][0] = xb;
+        p->pass[0][4] = remap(zkind, 0);
+        p->pass_names[0][4] = "fwd_unpack_z_pencils";
+        p->pass_bytes[0][4] = zb;
+    } else {
+        p->pass[1][0] = remap(zkind, 1);
+        p->pass_names[1][0] = "bwd_pack_z_pencils";
+        p->pass_bytes[1][0] = zb;
+        p->pass[1][4] = remap(pf::REMAP_XPENCIL, 0);
+        p->pass_names[1][4] = "bwd_unpack_x_pencils";
+        p->pass_bytes[1][4] = xb;
+    }
+    p->npass[dir] = 5;
 }
 
 void build_passes(pf_plan *p) {
@@ -320,7 +371,8 @@ void build_passes(pf_plan *p) {
             p->pass_bytes[1][1] = 2 * cbytes;
             p->pass_bytes[1][2] = N * rs + cbytes;
         }
-        p->npass[dir] = kPasses;
+        p->npass[dir] = 3;
+        if (p->blocked) add_remaps(p, dir);
     }
 }
 
@@ -349,6 +401,8 @@ int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s
     PassDesc d = p->pass[dir][i];
     d.a.in = in;
     d.a.out = out;
+    d.r.src = in;
+    d.r.dst = out;
     EventPair ev{nullptr, nullptr};
     if (p->timing) {
         ev = take_events(p);
@@ -377,10 +431,20 @@ int run_chain(pf_plan *p, int dir, const void *in, void *out, void *stream) {
     const int rc = check_call(p, in, out);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    // pass 0: user -> workspace; pass 1: workspace in place; pass 2: workspace -> user
-    int r = run_one(p, dir, 0, in, p->ws, s);
-    if (!r) r = run_one(p, dir, 1, p->ws, p->ws, s);
-    if (!r) r = run_one(p, dir, 2, p->ws, out, s);
+    if (!p->blocked) {
+        // pass 0: user -> workspace; pass 1: workspace in place; pass 2: workspace -> user
+        int r = run_one(p, dir, 0, in, p->ws, s);
+        if (!r) r = run_one(p, dir, 1, p->ws, p->ws, s);
+        if (!r) r = run_one(p, dir, 2, p->ws, out, s);
+        return r;
+    }
+    // pack: user blocks -> global array G; then G -> W, W in place, W -> G; unpack: G -> user blocks
+    void *g = (char *)p->ws + p->w_bytes;
+    int r = run_one(p, dir, 0, in, g, s);
+    if (!r) r = run_one(p, dir, 1, g, p->ws, s);
+    if (!r) r = run_one(p, dir, 2, p->ws, p->ws, s);
+    if (!r) r = run_one(p, dir, 3, p->ws, g, s);
+    if (!r) r = run_one(p, dir, 4, g, out, s);
     return r;
 }
 
@@ -516,7 +580,14 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
         delete p;
         return hip_status(e);
     }
-    p->ws_bytes = (size_t)p->nz * p->nkb * p->ny * p->B * p->csize;
+    p->blocked = l->m1 * l->m2 > 1;
+    p->w_bytes = ((size_t)p->nz * p->nkb * p->ny * p->B * p->csize + 255) & ~(size_t)255;
+    p->ws_bytes = p->w_bytes;
+    if (p->blocked) {
+        const size_t real_b = (size_t)nx * ny * nz * (p->csize / 2);
+        const size_t cplx_b = (size_t)p->nxh * ny * nz * p->csize;
+        p->ws_bytes += real_b > cplx_b ? real_b : cplx_b;
+    }
     e = hipMalloc(&p->ws, p->ws_bytes);
     if (e != hipSuccess) {
         hipFree(p->tw_dev);
@@ -614,7 +685,7 @@ int pf_set_timing(pf_plan *p, int enable) {
 }
 
 int pf_get_timing(pf_plan *p, int dir, int pass, double *total_ms, long long *count) {
-    if (!p || !total_ms || !count || dir < 0 || dir > 1 || pass < 0 || pass >= kPasses) return PF_EINVAL;
+    if (!p || !total_ms || !count || dir < 0 || dir > 1 || pass < 0 || pass >= p->npass[dir]) return PF_EINVAL;
     double tot = 0.0;
     long long n = 0;
     for (auto &e : p->tim[dir][pass].used) {

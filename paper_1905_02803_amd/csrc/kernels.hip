@@ -261,6 +261,71 @@ __global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
     }
 }
 
+// ---- pack / unpack between the global arrays and the Table 1 blocks ------
+// An axis of length n split over M ranks: rank r holds floor(n/M) + (r < n mod M)
+// elements starting at r floor(n/M) + min(r, n mod M) (blocks differ by at most
+// one element, Sec. 3.4).
+__device__ __forceinline__ void blk(int n, int M, int r, int &start, int &size) {
+    const int q = n / M, rem = n % M;
+    size = q + (r < rem ? 1 : 0);
+    start = r * q + (r < rem ? r : rem);
+}
+__device__ __forceinline__ int block_of(int i, int n, int M) {
+    const int q = n / M, rem = n % M;
+    return i < rem * (q + 1) ? i / (q + 1) : rem + (i - rem * (q + 1)) / q;
+}
+
+// One line per workgroup; the block of rank (r1, r2) starts where the blocks
+// of all earlier ranks (order r2 m1 + r1) end, which in closed form is
+// nx (ny z0 + y0 L3) for X-pencils and nz (nxh ky0 + kx0 Ly) for Z-pencils.
+__global__ __launch_bounds__(256) void k_remap(RemapArgs a) {
+    const long long L = blockIdx.x;
+    long long goff, boff;
+    int len;
+    if (a.kind == REMAP_XPENCIL) {
+        const int z = (int)(L / a.ny), y = (int)(L - (long long)z * a.ny);
+        int y0, L2, z0, L3;
+        blk(a.ny, a.m1, block_of(y, a.ny, a.m1), y0, L2);
+        blk(a.nz, a.m2, block_of(z, a.nz, a.m2), z0, L3);
+        len = a.nx;
+        goff = L * a.nx;
+        boff = (long long)a.nx * ((long long)a.ny * z0 + (long long)y0 * L3 + (long long)(z - z0) * L2 + (y - y0));
+    } else if (a.kind == REMAP_ZSTRIDE1) {
+        const int kx = (int)(L / a.ny), ky = (int)(L - (long long)kx * a.ny);
+        int kx0, Lx, ky0, Ly;
+        blk(a.nxh, a.m1, block_of(kx, a.nxh, a.m1), kx0, Lx);
+        blk(a.ny, a.m2, block_of(ky, a.ny, a.m2), ky0, Ly);
+        len = a.nz;
+        goff = L * a.nz;
+        boff = (long long)a.nz *
+               ((long long)a.nxh * ky0 + (long long)kx0 * Ly + (long long)(kx - kx0) * Ly + (ky - ky0));
+    } else {
+        const int r1 = (int)(L % a.m1);
+        const long long row = L / a.m1;  // kz ny + ky
+        const int kz = (int)(row / a.ny), ky = (int)(row - (long long)kz * a.ny);
+        int kx0, Lx, ky0, Ly;
+        blk(a.nxh, a.m1, r1, kx0, Lx);
+        blk(a.ny, a.m2, block_of(ky, a.ny, a.m2), ky0, Ly);
+        len = Lx;
+        goff = row * a.nxh + kx0;
+        boff = (long long)a.nz * ((long long)a.nxh * ky0 + (long long)kx0 * Ly) +
+               ((long long)kz * Ly + (ky - ky0)) * Lx;
+    }
+    const unsigned *__restrict__ src = reinterpret_cast<const unsigned *>(a.src);
+    unsigned *__restrict__ dst = reinterpret_cast<unsigned *>(a.dst);
+    const long long so = (a.gather ? boff : goff) * a.words;
+    const long long d0 = (a.gather ? goff : boff) * a.words;
+    const int nw = len * a.words;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[d0 + i] = src[so + i];
+}
+
+hipError_t launch_remap(const RemapArgs &r, hipStream_t s) {
+    if (r.nlines <= 0) return hipSuccess;
+    if (r.nlines > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_remap, dim3((unsigned)r.nlines), dim3(256), 0, s, r);
+    return hipGetLastError();
+}
+
 // Plain HBM copy, 16 bytes per lane, a fixed number of 16-byte words per
 // thread (all loads issued before the stores).  The bandwidth this reaches is
 // the practical ceiling the transform passes are measured against.
@@ -349,6 +414,8 @@ hipError_t launch_pass(const PassDesc &d, hipStream_t s) {
         case PASS_R2C_P2:
         case PASS_C2R_P2:
             return p2_launch(d, s);
+        case PASS_REMAP:
+            return launch_remap(d.r, s);
     }
     return hipGetLastError();
 }

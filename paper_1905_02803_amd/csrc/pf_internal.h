@@ -30,7 +30,34 @@ struct Side {
     long long sa, sblk, sc, sp, cpb;
 };
 
-enum PassKind { PASS_C2C = 0, PASS_R2C_X = 1, PASS_C2R_X = 2, PASS_C2C_P2 = 3, PASS_R2C_P2 = 4, PASS_C2R_P2 = 5 };
+enum PassKind {
+    PASS_C2C = 0,
+    PASS_R2C_X = 1,
+    PASS_C2R_X = 2,
+    PASS_C2C_P2 = 3,
+    PASS_R2C_P2 = 4,
+    PASS_C2R_P2 = 5,
+    PASS_REMAP = 6
+};
+
+// Reorder between the global arrays and the concatenated Table 1 pencil
+// blocks of an m1 x m2 processor grid (ranks in the order r2 m1 + r1).  Lines
+// are whole in every pencil, so the reorder copies lines:
+//   REMAP_XPENCIL  real lines (y, z) of length nx;
+//   REMAP_ZSTRIDE1 complex lines (kx, ky) of length nz (Z-pencil ZYX);
+//   REMAP_ZXYZ     complex row segments (kz, ky, r1) of length b(nxh, m1, r1)
+//                  (Z-pencil XYZ).
+enum RemapKind { REMAP_XPENCIL = 0, REMAP_ZSTRIDE1 = 1, REMAP_ZXYZ = 2 };
+
+struct RemapArgs {
+    const void *src;
+    void *dst;
+    int kind;
+    int gather;  // 1: blocks -> global array, 0: global array -> blocks
+    int words;   // 4-byte words per element
+    int nx, ny, nz, nxh, m1, m2;
+    long long nlines;
+};
 
 struct PassArgs {
     const void *in;
@@ -52,6 +79,7 @@ struct PassArgs {
 
 struct PassDesc {
     PassKind kind;
+    RemapArgs r;  // PASS_REMAP only
     int dir;   // -1 forward, +1 backward
     int prec;  // PF_F32 / PF_F64
     unsigned blocks;
@@ -64,6 +92,7 @@ struct PassDesc {
 hipError_t prepare_kernels(size_t max_lds);
 // Enqueue one pass.
 hipError_t launch_pass(const PassDesc &d, hipStream_t s);
+hipError_t launch_remap(const RemapArgs &r, hipStream_t s);
 // Plain 16-byte-per-lane device copy (bytes a multiple of 16).
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
