@@ -135,8 +135,13 @@ def COPY_BYTES(n: int) -> int:
     return 4 * n ** 3
 
 
-def cpu_baseline(n: int, u=None):
-    """The oracle, untuned, on one forward+backward pair of an n^3 GRF (the benchmark's own input if given)."""
+def cpu_baseline(n: int, u=None, forward_outputs=None):
+    """The oracle, untuned, on one forward+backward pair of an n^3 GRF (the benchmark's own input if given).
+
+    forward_outputs: {name: host array [nxh][ny][nz]} of GPU forward results on
+    the same input; their relative L2 error against the oracle's FP64 forward
+    is returned next to the timing.
+    """
     import oracle
     import synth
 
@@ -147,13 +152,23 @@ def cpu_baseline(n: int, u=None):
     oracle.c2r3d(U, n)
     dt = time.perf_counter() - t0
     N = float(n) ** 3
+    errs = {}
+    for name, got in (forward_outputs or {}).items():
+        if got is None or got.shape != (U.shape[2], U.shape[1], U.shape[0]):
+            continue
+        num = den = 0.0
+        for kx in range(got.shape[0]):  # plane by plane: got[kx] is [ky][kz], U[:, :, kx] is [kz][ky]
+            ref = U[:, :, kx].T
+            num += float(np.sum(np.abs(got[kx].astype(np.complex128) - ref) ** 2))
+            den += float(np.sum(np.abs(ref) ** 2))
+        errs[name] = math.sqrt(num / den)
     return {
         "value": 5.0 * N * math.log2(N) / dt / 1e9,
         "unit": "GFLOP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": f"one R2C+C2R pair at {n}^3 (FP64, OpenMP over lines), {dt:.2f} s wall",
-    }
+    }, errs
 
 
 def main():
@@ -227,14 +242,46 @@ def main():
                            "alg_bytes": nbytes, "alg_GBps": nbytes / (avg * 1e-3) / 1e9 if avg > 0 else None})
     plan.set_timing(False)
     dom = max(passes, key=lambda p: p["avg_ms"])
+    keep_host = not args.no_cpu_baseline
+    fwd_host = {"plain": U.cpu().numpy() if keep_host else None}
+
+    # the matrix-core precision variants on the same input, same protocol
+    mfma = {}
+    for name, mth in (("fp16x2", pf.PF_MFMA_FP16X2), ("bf16x2", pf.PF_MFMA_BF16X2)):
+        pm = pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F32, stride1=1, math=mth))
+        Um = pm.empty_complex(dev)
+        for _ in range(args.warmup):
+            pm.ftran(u, Um)
+            pm.btran(Um, r)
+        torch.cuda.synchronize()
+        m0 = torch.cuda.Event(enable_timing=True)
+        m1 = torch.cuda.Event(enable_timing=True)
+        m0.record(stream)
+        for _ in range(args.steps):
+            pm.ftran(u, Um)
+            pm.btran(Um, r)
+        m1.record(stream)
+        torch.cuda.synchronize()
+        mms = m0.elapsed_time(m1) / args.steps
+        mfma[name] = {"ms_per_step": mms, "value": 5.0 * Nf * math.log2(Nf) / (mms * 1e-3) / 1e9,
+                      "speedup_vs_plain": ms / mms}
+        pm.ftran(u, Um)
+        torch.cuda.synchronize()
+        if keep_host:
+            fwd_host[name] = Um.cpu().numpy()
+        del Um
+        pm.destroy()
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
     gflops = flops / (ms * 1e-3) / 1e9
 
     cpu = None
+    errs = {}
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(min(args.cpu_n, n), u_host)
-    del u_host
+        cpu, errs = cpu_baseline(min(args.cpu_n, n), u_host, fwd_host)
+    del u_host, fwd_host
+    for name in mfma:
+        mfma[name]["rel_l2_fwd_vs_fp64_oracle"] = errs.get(name)
 
     out = {
         "metric": "3D R2C+C2R GFLOP/s & HBM GB/s at 1024^3; MFMA-mixed vs FP32 at stated err",
@@ -254,6 +301,8 @@ def main():
         "hbm_GBps_alg": alg_bytes / (ms * 1e-3) / 1e9,
         "copy_probe_GBps": copy_GBps,
         "round_trip_rel_l2": rt_err,
+        "rel_l2_fwd_vs_fp64_oracle": errs.get("plain"),
+        "mfma": mfma,
         "roofline": {
             "bound": "hbm",
             "kernel": dom["pass"],

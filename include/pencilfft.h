@@ -65,9 +65,19 @@ extern "C" {
 #define PF_F32 0 /* single precision (Sec. 3.1: single and double supported) */
 #define PF_F64 1
 
-#define PF_PLAIN 0       /* FP32 / FP64 butterflies on the vector ALUs           */
-#define PF_MFMA_FP16X2 1 /* radix-16 stages as split FP16 (hi+lo) matrix products */
-#define PF_MFMA_BF16X2 2 /* radix-16 stages as split BF16 (hi+lo) matrix products */
+/*
+ * math: PF_PLAIN computes every butterfly on the vector ALUs in the plan
+ * precision.  The MFMA options (F32 plans only) run the middle radix-16 stage
+ * of the power-of-two passes (lengths 512 and 1024 for Y and Z, nx 1024 and
+ * 2048 for X) as 16 x 16 complex DFT-matrix products on the matrix cores, with
+ * both operands split into high and low half-precision parts (three products,
+ * FP32 accumulation); FP16 inputs are scaled by a power of two per butterfly.
+ * Other passes run as PF_PLAIN.  The result differs from PF_PLAIN by rounding
+ * only (relative L2 against the FP64 oracle is reported by the tests).
+ */
+#define PF_PLAIN 0
+#define PF_MFMA_FP16X2 1
+#define PF_MFMA_BF16X2 2
 
 #define PF_THIRD_FFT 0   /* Fourier transform along Z (default)                 */
 #define PF_THIRD_EMPTY 1 /* no transform along Z (Sec. 3.1: empty transform)   */

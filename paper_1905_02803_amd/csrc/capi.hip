@@ -171,7 +171,7 @@ int check_impl(int nx, int ny, int nz, const pf_layout *l) {
 
 // Options accepted by pf_check but not built into the transform yet.
 int built_options(const pf_layout *l) {
-    if (l->math != PF_PLAIN) return PF_EUNSUPPORTED;
+    if (l->math != PF_PLAIN && l->precision != PF_F32) return PF_EUNSUPPORTED;
     if (l->third != PF_THIRD_FFT) return PF_EUNSUPPORTED;
     if (l->useeven) return PF_EUNSUPPORTED;
     return PF_OK;
@@ -192,10 +192,11 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
     if (vec_ok && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
         // compile-time radix plan, persistent blocks (grid set once the tile count is known)
         d.kind = pf::PASS_C2C_P2;
+        a.math = pf::p2_has_mfma(fs.n) ? p->lay.math : 0;
         a.tc_log2 = ilog2(pf::p2_tc(fs.n));
         a.wpc_log2 = ilog2(fs.n / 16);
         d.threads = (unsigned)pf::p2_threads(fs.n);
-        d.lds = pf::p2_lds_bytes(fs.n);
+        d.lds = pf::p2_lds_bytes(fs.n, a.math);
         return;
     }
     d.kind = pf::PASS_C2C;
@@ -323,9 +324,10 @@ void build_passes(pf_plan *p) {
         if (p->fast_x) {  // half-length complex transform, 16 lines per tile, persistent blocks
             x.kind = dir == 0 ? pf::PASS_R2C_P2 : pf::PASS_C2R_P2;
             x.a.fft = p->fxh;
+            x.a.math = pf::p2_has_mfma(p->nx / 2) ? p->lay.math : 0;
             x.a.tw = (const char *)p->tw_dev + p->tw_off[3];
             x.threads = (unsigned)pf::p2x_threads(p->nx);
-            x.lds = pf::p2x_lds_bytes(p->nx);
+            x.lds = pf::p2x_lds_bytes(p->nx, x.a.math);
             const long long tiles = (x.a.lines + 15) / 16;
             const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(x);
             x.blocks = (unsigned)(tiles < resident ? tiles : resident);

@@ -84,10 +84,186 @@ __device__ __forceinline__ void p2_butterflies2(cx<float> (&v0)[16], cx<float> (
 
 __device__ __forceinline__ float4 pack2(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
 
+// ---- radix-16 stage as DFT-matrix products on the matrix cores ------------
+// For 16 butterflies at once (the MFMA's 16 columns) the radix-16 DFT
+// Y[k] = sum_r W16^{DIR r k} X[r] is the real product C = A B with K = 32
+// interleaving real and imaginary parts (K index 2r + c):
+//   B[2r + c][b] = (Re, Im)[c] of X_b[r],
+//   Ar[k][2r] = cos,  Ar[k][2r+1] = -DIR sin   (C = Re Y)
+//   Ai[k][2r] = DIR sin, Ai[k][2r+1] = cos     (C = Im Y),  angle 2 pi r k / 16.
+// v_mfma_f32_16x16x32 lane l holds A[l%16][8(l/16) .. +8), B[8(l/16) .. +8)[l%16]
+// and returns C[4(l/16) .. +4)[l%16]: lane (b, g) brings points 4g .. 4g+3 of
+// butterfly b and receives outputs 4g .. 4g+3 of it.  Both operands are split
+// into a high and a low half-precision part; hi*hi + hi*lo + lo*hi is
+// accumulated in FP32 (the lo*lo term is below FP32 rounding).  FP16 inputs
+// are first scaled by a power of two per butterfly (largest component in
+// [1, 2)); BF16 keeps FP32's exponent range and needs no scale.
+typedef _Float16 mf_h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mf_b8 __attribute__((ext_vector_type(8)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+constexpr size_t kMfmaTableBytes = 64 * 4 * 16;  // A operands: 4 vectors of 16 bytes per lane
+
+// cos(2 pi m / 16) for any integer m (closed forms cos(pi/8), cos(pi/4),
+// sin(pi/8)), by selects: no runtime-indexed table in private memory.
+__device__ __forceinline__ float cos16(int m) {
+    const int a = m & 15;
+    const int f = a <= 8 ? a : 16 - a;  // cos is even: fold to 0 .. 8
+    const float c1 = (float)kCosPi8, c2 = (float)kSqrtHalf, c3 = (float)kSinPi8;
+    const float mag = f == 0 || f == 8 ? 1.f : f == 1 || f == 7 ? c1 : f == 2 || f == 6 ? c2 : f == 3 || f == 5 ? c3 : 0.f;
+    return f > 4 ? -mag : mag;
+}
+__device__ __forceinline__ float sin16(int m) { return cos16(m - 4); }
+
+template <int MT>
+struct MfmaSplit;
+template <>
+struct MfmaSplit<1> {  // FP16 hi + lo
+    typedef mf_h8 vec;
+    typedef _Float16 elem;
+    __device__ static void split(float x, _Float16 &h, _Float16 &l) {
+        h = (_Float16)x;
+        l = (_Float16)(x - (float)h);
+    }
+    __device__ static mf_f4 mma(vec a, vec b, mf_f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct MfmaSplit<2> {  // BF16 hi + lo
+    typedef mf_b8 vec;
+    typedef __bf16 elem;
+    __device__ static void split(float x, __bf16 &h, __bf16 &l) {
+        h = (__bf16)x;
+        l = (__bf16)(x - (float)h);
+    }
+    __device__ static mf_f4 mma(vec a, vec b, mf_f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+
+// The constant A operands of a lane (row k = l % 16, K = 8 (l/16) + e).  They
+// are built once per block into LDS (4 vectors per lane, 4 KB) and read back
+// only inside the matrix-core stage.
+template <int DIR, int MT>
+struct MfmaDft16 {
+    typedef typename MfmaSplit<MT>::vec vec;
+    vec arh, arl, aih, ail;
+    __device__ void init(int lane) {
+        const int k = lane & 15, g = lane >> 4;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int r = 4 * g + (e >> 1);
+            const float c = cos16(r * k), sn = (float)DIR * sin16(r * k);
+            const float ar = (e & 1) ? -sn : c;
+            const float ai = (e & 1) ? c : sn;
+            typename MfmaSplit<MT>::elem h, l;
+            MfmaSplit<MT>::split(ar, h, l);
+            arh[e] = h;
+            arl[e] = l;
+            MfmaSplit<MT>::split(ai, h, l);
+            aih[e] = h;
+            ail[e] = l;
+        }
+    }
+    __device__ void store(vec *t, int lane) const {
+        t[4 * lane] = arh;
+        t[4 * lane + 1] = arl;
+        t[4 * lane + 2] = aih;
+        t[4 * lane + 3] = ail;
+    }
+    __device__ void load(const vec *t, int lane) {
+        arh = t[4 * lane];
+        arl = t[4 * lane + 1];
+        aih = t[4 * lane + 2];
+        ail = t[4 * lane + 3];
+    }
+    // x: this lane's 4 inputs (points 4g .. 4g+3) of butterfly l % 16; returns the outputs 4g .. 4g+3.
+    __device__ void run(cx<float> (&x)[4]) const {
+        float sc = 1.f;
+        int ex = 127;
+        if (MT == 1) {  // per-butterfly power-of-two scale: largest |component| into [1, 2)
+            float m = 0.f;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) m = fmaxf(m, fmaxf(fabsf(x[s].x), fabsf(x[s].y)));
+            m = fmaxf(m, __shfl_xor(m, 16));
+            m = fmaxf(m, __shfl_xor(m, 32));
+            ex = m > 0.f ? ((__float_as_int(m) >> 23) & 255) : 127;
+            ex = min(max(ex, 1), 253);
+            sc = __int_as_float((254 - ex) << 23);  // 2^(127 - ex), exact
+        }
+        vec bh, bl;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            typename MfmaSplit<MT>::elem h, l;
+            MfmaSplit<MT>::split(x[s].x * sc, h, l);
+            bh[2 * s] = h;
+            bl[2 * s] = l;
+            MfmaSplit<MT>::split(x[s].y * sc, h, l);
+            bh[2 * s + 1] = h;
+            bl[2 * s + 1] = l;
+        }
+        mf_f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+        cr = MfmaSplit<MT>::mma(arh, bh, cr);
+        ci = MfmaSplit<MT>::mma(aih, bh, ci);
+        cr = MfmaSplit<MT>::mma(arh, bl, cr);
+        ci = MfmaSplit<MT>::mma(aih, bl, ci);
+        cr = MfmaSplit<MT>::mma(arl, bh, cr);
+        ci = MfmaSplit<MT>::mma(ail, bh, ci);
+        const float inv = MT == 1 ? __int_as_float(ex << 23) : 1.f;  // 2^(ex - 127)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) x[s] = make_float2(cr[s] * inv, ci[s] * inv);
+    }
+};
+
+// Stage 1 (radix 16, NS = 16) of an N-point column FFT on the LDS tile, on the
+// matrix cores.  Wave w takes butterflies q = 8w .. 8w+7 of all 16 columns;
+// within a group lane (b, g) holds column b, points q + (N/16)(4g + s).
+// Twiddles W_{256}^{r (q mod 16)} are applied in FP32 before the product.
+// Butterfly q reads and writes only LDS rows congruent to q mod 8, so the
+// groups 0-3 and 4-7 of all waves touch disjoint rows: each half is read,
+// synchronised, transformed and written in turn (half the live operands).
+template <int N, int TC, int DIR, int MT>
+__device__ __forceinline__ void p2_stage1_mfma(float4 *buf, const cx<float> *tws,
+                                               const typename MfmaSplit<MT>::vec *atab, int tid) {
+    constexpr int T = N / 16;
+    static_assert(TC == 16, "the matrix-core stage takes 16 columns");
+    const int lane = tid & 63, w = tid >> 6;
+    MfmaDft16<DIR, MT> dft;
+    dft.load(atab, lane);
+    const int b = lane & 15, g = lane >> 4;
+    float2 *lds2 = reinterpret_cast<float2 *>(buf);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cx<float> x[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = 8 * w + 4 * h + i;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) x[i][s] = lds2[2 * p2_slot<TC>(q + T * (4 * g + s), b >> 1) + (b & 1)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = 8 * w + 4 * h + i;
+            const int k = q & 15;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int r = 4 * g + s;
+                if (r > 0 && k > 0) {
+                    cx<float> t = tws[k * 15 + r - 1];
+                    if (DIR > 0) t.y = -t.y;
+                    x[i][s] = cmul(x[i][s], t);
+                }
+            }
+            dft.run(x[i]);
+            const int base = (q - k) * 16 + k;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) lds2[2 * p2_slot<TC>(base + 16 * (4 * g + s), b >> 1) + (b & 1)] = x[i][s];
+        }
+    }
+    __syncthreads();
+}
+
 // Each thread owns a pair of adjacent columns (2 cp, 2 cp + 1) and 16 points
 // q + (N/16) m of both.  INP / OUTP: 1 if that side's points are contiguous
 // (lines), 0 if its columns are contiguous (rows, loaded 16 bytes at a time).
-template <int N, int TC, int DIR, int INP, int OUTP>
+template <int N, int TC, int DIR, int INP, int OUTP, int MT>
 __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     constexpr int T = N / 16;
     constexpr int CP = TC / 2;
@@ -100,6 +276,15 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     const int tid = threadIdx.x;
     const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
     for (int i = tid; i < N - 1; i += NT) twl[i] = tw[i];
+    typedef typename MfmaSplit<MT == 0 ? 1 : MT>::vec avec;
+    avec *atab = reinterpret_cast<avec *>(twl + N);  // matrix-core A operands (MT != 0)
+    if constexpr (MT != 0) {
+        if (tid < 64) {
+            MfmaDft16<DIR, MT> d0;
+            d0.init(tid);
+            d0.store(atab, tid);
+        }
+    }
 
     const cx<float> *__restrict__ in = reinterpret_cast<const cx<float> *>(a.in);
     cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
@@ -166,7 +351,9 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
         for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
         __syncthreads();
 
-        if constexpr (S == 3) {  // stage 1: radix 16, NS = 16
+        if constexpr (S == 3 && MT != 0) {  // stage 1 on the matrix cores
+            p2_stage1_mfma<N, TC, DIR, MT>(buf, twl + p2_twoff(N, 1), atab, tid);
+        } else if constexpr (S == 3) {  // stage 1: radix 16, NS = 16
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
                 const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
@@ -234,7 +421,7 @@ __device__ __forceinline__ long long x_rowoff(const PassArgs &a, int g) {
     return (((long long)z * a.nkb) * a.ny + y) << 4;
 }
 
-template <int M>
+template <int M, int MT>
 __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
     constexpr int TC = 16;
     constexpr int T = M / 16;
@@ -252,6 +439,15 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
     const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
     for (int i = tid; i < 2 * M + 1; i += NT)
         if (i != M - 1) twl[i] = tw[i];
+    typedef typename MfmaSplit<MT == 0 ? 1 : MT>::vec avec;
+    avec *atab = reinterpret_cast<avec *>(twl + 2 * M + 2);  // matrix-core A operands (MT != 0)
+    if constexpr (MT != 0) {
+        if (tid < 64) {
+            MfmaDft16<-1, MT> d0;
+            d0.init(tid);
+            d0.store(atab, tid);
+        }
+    }
     const float *__restrict__ in = reinterpret_cast<const float *>(a.in);
     cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
     const int lines = (int)a.lines;
@@ -293,7 +489,9 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
         __syncthreads();
-        if constexpr (S == 3) {
+        if constexpr (S == 3 && MT != 0) {
+            p2_stage1_mfma<M, TC, -1, MT>(buf, twl + p2_twoff(M, 1), atab, tid);
+        } else if constexpr (S == 3) {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
                 const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
@@ -361,7 +559,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
     }
 }
 
-template <int M>
+template <int M, int MT>
 __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     constexpr int TC = 16;
     constexpr int T = M / 16;
@@ -380,6 +578,15 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
     for (int i = tid; i < 2 * M + 1; i += NT)
         if (i != M - 1) twl[i] = tw[i];
+    typedef typename MfmaSplit<MT == 0 ? 1 : MT>::vec avec;
+    avec *atab = reinterpret_cast<avec *>(twl + 2 * M + 2);  // matrix-core A operands (MT != 0)
+    if constexpr (MT != 0) {
+        if (tid < 64) {
+            MfmaDft16<1, MT> d0;
+            d0.init(tid);
+            d0.store(atab, tid);
+        }
+    }
     const cx<float> *__restrict__ in = reinterpret_cast<const cx<float> *>(a.in);
     float *__restrict__ out = reinterpret_cast<float *>(a.out);
     const int lines = (int)a.lines;
@@ -484,7 +691,9 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_mid * 16 + r, cp_mid)] = pack2(v0[r], v1[r]);
         __syncthreads();
-        if constexpr (S == 3) {
+        if constexpr (S == 3 && MT != 0) {
+            p2_stage1_mfma<M, TC, 1, MT>(buf, twl + p2_twoff(M, 1), atab, tid);
+        } else if constexpr (S == 3) {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
                 const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
@@ -526,82 +735,104 @@ bool p2x_supported(int nx, int prec) { return prec == 0 && (nx == 512 || nx == 1
 
 int p2x_threads(int nx) { return nx / 2 / 16 * 8; }
 
-size_t p2x_lds_bytes(int nx) {
+size_t p2x_lds_bytes(int nx, int math) {
     const int M = nx / 2;
-    return (size_t)M * 16 * sizeof(float2) + (size_t)(2 * M + 1) * sizeof(float2);
+    return (size_t)M * 16 * sizeof(float2) + (size_t)(2 * M + 2) * sizeof(float2) + (math ? kMfmaTableBytes : 0);
 }
 
-static const void *p2x_pick(int nx, int fwd) {
-    switch (nx) {
-        case 512: return fwd ? (const void *)&k_r2c_p2<256> : (const void *)&k_c2r_p2<256>;
-        case 1024: return fwd ? (const void *)&k_r2c_p2<512> : (const void *)&k_c2r_p2<512>;
-        case 2048: return fwd ? (const void *)&k_r2c_p2<1024> : (const void *)&k_c2r_p2<1024>;
-        default: return nullptr;
+static const void *p2x_pick(int nx, int fwd, int mt) {
+#define PF_X_PICK(NXV, MV)                                                                    \
+    if (nx == NXV) {                                                                          \
+        if (mt == 0) return fwd ? (const void *)&k_r2c_p2<MV, 0> : (const void *)&k_c2r_p2<MV, 0>; \
+        if (MV < 512) return nullptr;                                                         \
+        if (mt == 1) return fwd ? (const void *)&k_r2c_p2<MV, MV < 512 ? 0 : 1>               \
+                                : (const void *)&k_c2r_p2<MV, MV < 512 ? 0 : 1>;              \
+        return fwd ? (const void *)&k_r2c_p2<MV, MV < 512 ? 0 : 2> : (const void *)&k_c2r_p2<MV, MV < 512 ? 0 : 2>; \
     }
+    PF_X_PICK(512, 256)
+    PF_X_PICK(1024, 512)
+    PF_X_PICK(2048, 1024)
+#undef PF_X_PICK
+    return nullptr;
 }
 
 hipError_t p2x_prepare(int nx) {
     hipError_t e = hipSuccess;
-    for (int fwd : {0, 1}) {
-        const void *k = p2x_pick(nx, fwd);
+    for (int fwd : {0, 1})
+        for (int mt = 0; mt < 3; ++mt) {
+        const void *k = p2x_pick(nx, fwd, mt);
         if (!k) continue;
-        hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx));
+        hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, mt));
         if (r != hipSuccess && e == hipSuccess) e = r;
-    }
+        }
     return e;
 }
 
 int p2_tc(int n) { return n <= 1024 ? 16 : 16384 / n; }
 
-size_t p2_lds_bytes(int n) { return ((size_t)n * p2_tc(n) + n) * sizeof(float2); }
+size_t p2_lds_bytes(int n, int math) {
+    return ((size_t)n * p2_tc(n) + n) * sizeof(float2) + (math ? kMfmaTableBytes : 0);
+}
 
 bool p2_supported(int n, int prec) {
     return prec == 0 && (n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096);
 }
 
-template <int N, int TC, int DIR, int INP, int OUTP>
+template <int N, int TC, int DIR, int INP, int OUTP, int MT>
 static const void *p2_kernel() {
-    return reinterpret_cast<const void *>(&k_c2c_p2<N, TC, DIR, INP, OUTP>);
+    return reinterpret_cast<const void *>(&k_c2c_p2<N, TC, DIR, INP, OUTP, MT>);
 }
 
-// kernel symbol for (n, dir, inp, outp); nullptr if not built
-static const void *p2_pick(int n, int dir, int inp, int outp) {
-#define PF_P2_DIRS(NV, TCV)                                                   \
-    if (n == NV) {                                                            \
-        if (dir < 0) {                                                        \
-            if (!inp && !outp) return p2_kernel<NV, TCV, -1, 0, 0>();         \
-            if (!inp && outp) return p2_kernel<NV, TCV, -1, 0, 1>();          \
-            if (inp && !outp) return p2_kernel<NV, TCV, -1, 1, 0>();          \
-        } else {                                                              \
-            if (!inp && !outp) return p2_kernel<NV, TCV, 1, 0, 0>();          \
-            if (!inp && outp) return p2_kernel<NV, TCV, 1, 0, 1>();           \
-            if (inp && !outp) return p2_kernel<NV, TCV, 1, 1, 0>();           \
-        }                                                                     \
-        return nullptr;                                                       \
+template <int N, int TC, int MT>
+static const void *p2_pick_io(int dir, int inp, int outp) {
+    if (dir < 0) {
+        if (!inp && !outp) return p2_kernel<N, TC, -1, 0, 0, MT>();
+        if (!inp && outp) return p2_kernel<N, TC, -1, 0, 1, MT>();
+        if (inp && !outp) return p2_kernel<N, TC, -1, 1, 0, MT>();
+    } else {
+        if (!inp && !outp) return p2_kernel<N, TC, 1, 0, 0, MT>();
+        if (!inp && outp) return p2_kernel<N, TC, 1, 0, 1, MT>();
+        if (inp && !outp) return p2_kernel<N, TC, 1, 1, 0, MT>();
     }
-    PF_P2_DIRS(256, 16)
-    PF_P2_DIRS(512, 16)
-    PF_P2_DIRS(1024, 16)
-    PF_P2_DIRS(2048, 8)
-    PF_P2_DIRS(4096, 4)
-#undef PF_P2_DIRS
     return nullptr;
 }
 
-const void *p2_symbol(const PassDesc &d) {
-    if (d.kind == PASS_R2C_P2) return p2x_pick(2 * d.a.fft.n, 1);
-    if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0);
-    return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
+// kernel symbol for (n, dir, inp, outp, math); nullptr if not built.  The
+// matrix-core variants exist for the 16-column tiles with a middle radix-16
+// stage: n = 512 and 1024.
+static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
+    switch (n) {
+        case 256: return mt == 0 ? p2_pick_io<256, 16, 0>(dir, inp, outp) : nullptr;
+        case 512:
+            return mt == 0 ? p2_pick_io<512, 16, 0>(dir, inp, outp)
+                 : mt == 1 ? p2_pick_io<512, 16, 1>(dir, inp, outp)
+                           : p2_pick_io<512, 16, 2>(dir, inp, outp);
+        case 1024:
+            return mt == 0 ? p2_pick_io<1024, 16, 0>(dir, inp, outp)
+                 : mt == 1 ? p2_pick_io<1024, 16, 1>(dir, inp, outp)
+                           : p2_pick_io<1024, 16, 2>(dir, inp, outp);
+        case 2048: return mt == 0 ? p2_pick_io<2048, 8, 0>(dir, inp, outp) : nullptr;
+        case 4096: return mt == 0 ? p2_pick_io<4096, 4, 0>(dir, inp, outp) : nullptr;
+        default: return nullptr;
+    }
 }
 
+const void *p2_symbol(const PassDesc &d) {
+    if (d.kind == PASS_R2C_P2) return p2x_pick(2 * d.a.fft.n, 1, d.a.math);
+    if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0, d.a.math);
+    return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);
+}
+
+bool p2_has_mfma(int n) { return n == 512 || n == 1024; }
+
 hipError_t p2_prepare(int n) {
-    const size_t lds = p2_lds_bytes(n);
     hipError_t e = hipSuccess;
     for (int dir : {-1, 1})
-        for (int io = 0; io < 3; ++io) {
-            const void *k = p2_pick(n, dir, io == 2, io == 1);
+        for (int io = 0; io < 9; ++io) {
+            const int mt = io / 3;
+            const void *k = p2_pick(n, dir, io % 3 == 2, io % 3 == 1, mt);
             if (!k) continue;
-            hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2_lds_bytes(n, mt));
             if (r != hipSuccess && e == hipSuccess) e = r;
         }
     return e;

@@ -71,6 +71,7 @@ struct PassArgs {
     long long A, CB;  // C2C tile grid: A * CB tiles
     Side in_s, out_s;
     int inp, outp;  // power-of-two C2C pass: 1 if that side's points are contiguous
+    int math;       // power-of-two passes: 0 plain, 1 / 2 middle radix-16 stage on MFMA (FP16 / BF16 hi+lo)
     // X passes: real lines (y, z) flattened as g = z * ny + y
     long long lines;
     long long ld_real;  // elements between consecutive real lines
@@ -98,16 +99,17 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // Power-of-two FP32 C2C pass (kernels_p2.hip).
 bool p2_supported(int n, int prec);
+bool p2_has_mfma(int n);  // a matrix-core variant of the length-n pass exists
 int p2_tc(int n);
 int p2_threads(int n);
-size_t p2_lds_bytes(int n);
+size_t p2_lds_bytes(int n, int math);
 hipError_t p2_prepare(int n);
 int p2_blocks_per_cu(const PassDesc &d);
 hipError_t p2_launch(const PassDesc &d, hipStream_t s);
 // Even power-of-two X stage, FP32 (fft.n of the pass is nx / 2).
 bool p2x_supported(int nx, int prec);
 int p2x_threads(int nx);
-size_t p2x_lds_bytes(int nx);
+size_t p2x_lds_bytes(int nx, int math);
 hipError_t p2x_prepare(int nx);
 
 // LDS index with one pad slot every 16 complex elements (spreads the strided

@@ -4,6 +4,8 @@
   out-of-place: the forward output against the oracle's whole transform, the
   backward of an arbitrary half spectrum against the oracle's staged C2R, the
   round trip (Sec. 4.1) and Parseval.
+  Also the two matrix-core precision variants at their stated bounds
+  (FP16 x 2: 1e-6, BF16 x 2: 1e-5).
 * 512^3 and 480 x 360 x 250 FP32 random fields: the same checks.
 * 32^3 FP64, uniform[-1, 1] from seed 1: forward, backward and round trip at
   1e-12.
@@ -35,7 +37,10 @@ def half_weights(nx):
     return w
 
 
-def check_grid(shape, seed, tol):
+MFMA_BOUND = {pf.PF_MFMA_FP16X2: 1e-6, pf.PF_MFMA_BF16X2: 1e-5}
+
+
+def check_grid(shape, seed, tol, maths=()):
     nz, ny, nx = shape
     print(f"case shape={shape} seed={seed}", flush=True)
     u = synth.grf(seed, shape)
@@ -59,7 +64,20 @@ def check_grid(shape, seed, tol):
         err = rel(got, ref)
         print(f"forward rel L2 {err:.3e}, round trip {rt:.3e}", flush=True)
         assert err < tol
-        del got, ref
+        del got
+        for mth in maths:  # the matrix-core variants against the same oracle result
+            with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F32, stride1=1, math=mth)) as pm:
+                Um = pm.ftran(ud)
+                bm = pm.btran(Um)
+                torch.cuda.synchronize()
+                rtm = (torch.linalg.vector_norm(bm.double() / N - ud.double()) /
+                       torch.linalg.vector_norm(ud.double())).item()
+                del bm
+                em = rel(Um.cpu().numpy(), ref)
+                del Um
+            print(f"math {mth}: forward rel L2 {em:.3e}, round trip {rtm:.3e}", flush=True)
+            assert em < MFMA_BOUND[mth] and rtm < 2 * MFMA_BOUND[mth]
+        del ref
         # backward of an arbitrary half spectrum
         V = synth.complex_half(seed + 1000, (nz, ny, nx // 2 + 1)).astype(np.complex64)
         Vd = torch.from_numpy(oracle.to_stride1(V)).cuda()
@@ -73,7 +91,7 @@ def check_grid(shape, seed, tol):
 
 @pytest.mark.timeout(1200)
 def test_1024_cubed_grf_matches_oracle():
-    check_grid((1024, 1024, 1024), 3, 1e-6)
+    check_grid((1024, 1024, 1024), 3, 1e-6, maths=(pf.PF_MFMA_FP16X2, pf.PF_MFMA_BF16X2))
 
 
 @pytest.mark.timeout(600)
