@@ -300,9 +300,12 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     const long long out_step = a.out_s.sp * T;
 
     // element (column 2 cp, point q) of tile t on a side, and the valid column count
+    const int A = (int)a.A;
     auto side_addr = [&](const Side &sd, int t, int cp, int q, int &ncol) -> long long {
-        const int ta = t / CB;
-        const int cb = t - ta * CB;
+        // tile order 1 walks the outer index fastest: concurrently resident
+        // tiles then touch different lines of a side whose lines are far apart
+        const int ta = a.tile_order ? t % A : t / CB;
+        const int cb = a.tile_order ? t / A : t - ta * CB;
         ncol = min(TC, a.C - cb * TC);
         return (long long)ta * sd.sa + (long long)(cb / sd.cpb) * sd.sblk + (long long)(cb % sd.cpb) * TC * sd.sc +
                (long long)(2 * cp) * sd.sc + (long long)q * sd.sp;
@@ -593,7 +596,6 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     const int ntiles = (lines + 15) / 16;
     const int cp_mid = tid % CP, q_mid = tid / CP;
     const int cp_out = tid / T, q_out = tid % T;
-    const long long kbstride = (long long)a.ny << 4;
 
     // chunk i of this thread: f = tid + NT i -> (kb, pair, mode pair); rows of lines a, b.
     // Addresses: one 64-bit tile base (uniform) plus 32-bit offsets (16 lines

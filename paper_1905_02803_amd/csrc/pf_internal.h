@@ -72,6 +72,7 @@ struct PassArgs {
     Side in_s, out_s;
     int inp, outp;  // power-of-two C2C pass: 1 if that side's points are contiguous
     int math;       // power-of-two passes: 0 plain, 1 / 2 middle radix-16 stage on MFMA (FP16 / BF16 hi+lo)
+    int tile_order; // power-of-two C2C pass: 0 tile t = (t / CB, t % CB), 1 tile t = (t % A, t / A)
     // X passes: real lines (y, z) flattened as g = z * ny + y
     long long lines;
     long long ld_real;  // elements between consecutive real lines
