@@ -571,12 +571,10 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     constexpr int S = p2_stages(M);
     constexpr int RL = p2_radix(M, S - 1);
     constexpr int NSL = p2_ns(M, S - 1);
-    constexpr int NKB = M / 16 + 1;
-    constexpr int NCH = (M / 16) * 64 / NT;  // 16-byte chunk pairs per thread per tile (modes < M)
+    constexpr int NIT = M / 2 * 8 / NT;  // (mode k < M/2, line pair) items per thread per tile
     float4 *buf = reinterpret_cast<float4 *>(pf_smem);
     cx<float> *twl = reinterpret_cast<cx<float> *>(buf + M * CP);
     cx<float> *spl = twl + M;
-    __shared__ float4 nyq[8];  // X[M] of each line pair
     const int tid = threadIdx.x;
     const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
     for (int i = tid; i < 2 * M + 1; i += NT)
@@ -597,10 +595,13 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     const int cp_mid = tid % CP, q_mid = tid / CP;
     const int cp_out = tid / T, q_out = tid % T;
 
-    // chunk i of this thread: f = tid + NT i -> (kb, pair, mode pair); rows of lines a, b.
+    // item i of this thread: f = tid + NT i -> mode k = 16 kb + j (k < M/2) and line
+    // pair pr; it holds X[k] and X[M-k] of both lines (for k = 0 the partner is
+    // X[M], the first slot of the last column block), and threads 0..15 hold
+    // X[M/2] of line tid.  A wave reads whole 128-byte rows of the workspace.
     // Addresses: one 64-bit tile base (uniform) plus 32-bit offsets (16 lines
     // span at most 16 z planes of the workspace).
-    auto load = [&](float4(&ca)[NCH], float4(&cb)[NCH], float2 &nq, int t) {
+    auto load = [&](float4(&xk)[NIT], float4(&xm)[NIT], float2 &xh, int t) {
         const int g0 = 16 * t;
         const int z0 = g0 / a.ny;
         const int y0 = g0 - z0 * a.ny;
@@ -615,69 +616,67 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
             const int y = g - z * a.ny;
             return (z - z0) * zplane + (y - y0) * 16;
         };
+        auto col = [&](int k) { return (k >> 4) * kbs + (k & 15); };
 #pragma unroll
-        for (int i = 0; i < NCH; ++i) {
+        for (int i = 0; i < NIT; ++i) {
             const int f = tid + NT * i;
-            const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
-            const int col = kb * kbs + 2 * kp;
-            if (g0 + 2 * pr < lines) ca[i] = *reinterpret_cast<const float4 *>(tb + rowrel(2 * pr) + col);
-            if (g0 + 2 * pr + 1 < lines) cb[i] = *reinterpret_cast<const float4 *>(tb + rowrel(2 * pr + 1) + col);
-            else cb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int k = ((f >> 7) << 4) + (f & 15), pr = (f >> 4) & 7;
+            const int ck = col(k), cm = col(M - k);
+            float2 ak = make_float2(0.f, 0.f), am = ak, bk = ak, bm = ak;
+            if (g0 + 2 * pr < lines) {
+                const int ra = rowrel(2 * pr);
+                ak = tb[ra + ck];
+                am = tb[ra + cm];
+            }
+            if (g0 + 2 * pr + 1 < lines) {
+                const int rb = rowrel(2 * pr + 1);
+                bk = tb[rb + ck];
+                bm = tb[rb + cm];
+            }
+            xk[i] = make_float4(ak.x, ak.y, bk.x, bk.y);
+            xm[i] = make_float4(am.x, am.y, bm.x, bm.y);
         }
-        // mode M (first slot of the last column block) of line tid
-        if (tid < 16) {
-            if (g0 + tid < lines) nq = tb[rowrel(tid) + (NKB - 1) * kbs];
-            else nq = make_float2(0.f, 0.f);
-        }
+        if (tid < 16) xh = g0 + tid < lines ? tb[rowrel(tid) + col(M / 2)] : make_float2(0.f, 0.f);
+    };
+
+    // Zb[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) W_nx^-k, one line
+    auto zb = [](float2 Xk, float2 Xm, float2 w) {
+        const float2 E = make_float2(Xk.x + Xm.x, Xk.y - Xm.y);
+        const float2 O = cmul(make_float2(Xk.x - Xm.x, Xk.y + Xm.y), w);
+        return make_float2(E.x - O.y, E.y + O.x);
     };
 
     int t = blockIdx.x;
-    float4 pa[NCH], pb[NCH];
-    float2 pq;
-    if (t < ntiles) load(pa, pb, pq, t);
+    float4 pk[NIT], pm[NIT];
+    float2 ph;
+    if (t < ntiles) load(pk, pm, ph, t);
     __syncthreads();
     for (; t < ntiles; t += gridDim.x) {
-        // spectra of the tile into LDS: slot (k, pair) = (X_a[k], X_b[k]); X[M] aside
+        // inverse split from registers into LDS: item (k, pair) writes Zb[k] and
+        // Zb[M-k] of both lines; modes 0 and M contribute their real parts only
 #pragma unroll
-        for (int i = 0; i < NCH; ++i) {
+        for (int i = 0; i < NIT; ++i) {
             const int f = tid + NT * i;
-            const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
-            const int k0 = kb * 16 + 2 * kp;
-            const float4 A = pa[i], Bv = pb[i];
-            buf[p2_slot<TC>(k0, pr)] = make_float4(A.x, A.y, Bv.x, Bv.y);
-            buf[p2_slot<TC>(k0 + 1, pr)] = make_float4(A.z, A.w, Bv.z, Bv.w);
-        }
-        if (tid < 16) reinterpret_cast<float2 *>(nyq)[(tid >> 1) * 2 + (tid & 1)] = pq;
-        const int tn = t + gridDim.x;
-        if (tn < ntiles) load(pa, pb, pq, tn);
-        __syncthreads();
-
-        // inverse split, in place: item (k, pair) for k <= M/2 writes Zb[k] and Zb[M-k]
-        for (int f = tid; f < (M / 2 + 1) * 8; f += NT) {
-            const int k = f >> 3, pr = f & 7;
-            const float4 xk = buf[p2_slot<TC>(k, pr)];
-            float4 xm = k == 0 ? nyq[pr] : buf[p2_slot<TC>(M - k, pr)];
+            const int k = ((f >> 7) << 4) + (f & 15), pr = (f >> 4) & 7;
+            float2 Ak = make_float2(pk[i].x, pk[i].y), Bk = make_float2(pk[i].z, pk[i].w);
+            float2 Am = make_float2(pm[i].x, pm[i].y), Bm = make_float2(pm[i].z, pm[i].w);
+            if (k == 0) Ak.y = Bk.y = Am.y = Bm.y = 0.f;
             const cx<float> w = spl[k];
-            float2 Ak = make_float2(xk.x, xk.y), Bk = make_float2(xk.z, xk.w);
-            float2 Am = make_float2(xm.x, xm.y), Bm = make_float2(xm.z, xm.w);
-            if (k == 0) {  // modes 0 and M: real parts only
-                Ak.y = Bk.y = Am.y = Bm.y = 0.f;
-            }
             const float2 wc = make_float2(w.x, -w.y);  // W_nx^-k
-            // Zb[k] = (Xk + conj Xm) + i (Xk - conj Xm) W^-k, per line
-            auto zb = [&](float2 Xk, float2 Xm, float2 ww) {
-                const float2 E = make_float2(Xk.x + Xm.x, Xk.y - Xm.y);
-                const float2 O = cmul(make_float2(Xk.x - Xm.x, Xk.y + Xm.y), ww);
-                return make_float2(E.x - O.y, E.y + O.x);
-            };
-            const float2 za = zb(Ak, Am, wc), zbv = zb(Bk, Bm, wc);
-            buf[p2_slot<TC>(k, pr)] = pack2(za, zbv);
-            if (k != 0 && 2 * k != M) {
-                // Zb[M-k] uses W^-(M-k) = -W^k
+            buf[p2_slot<TC>(k, pr)] = pack2(zb(Ak, Am, wc), zb(Bk, Bm, wc));
+            if (k != 0) {
+                // Zb[M-k] uses W_nx^-(M-k) = -W_nx^k
                 const float2 wm = make_float2(-w.x, -w.y);
                 buf[p2_slot<TC>(M - k, pr)] = pack2(zb(Am, Ak, wm), zb(Bm, Bk, wm));
             }
         }
+        if (tid < 16) {
+            const cx<float> w = spl[M / 2];
+            reinterpret_cast<float2 *>(buf)[2 * p2_slot<TC>(M / 2, tid >> 1) + (tid & 1)] =
+                zb(ph, ph, make_float2(w.x, -w.y));
+        }
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(pk, pm, ph, tn);
         __syncthreads();
 
         cx<float> v0[16], v1[16];
