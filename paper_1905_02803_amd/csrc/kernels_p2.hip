@@ -23,6 +23,81 @@
 
 namespace pf {
 
+// ---- streaming global accesses ----------------------------------------------
+// Each pass reads and writes every element once.  Access sites may carry the
+// nontemporal hint (no reuse expected in the caches); which sites do is fixed
+// at compile time by the bits of PF_STREAM_MASK.  The default streams every
+// store except the row stores of a pass with a point-major input side, and
+// the row loads of the Y / Z passes: on MI355X at 1024^3 the Y passes gain
+// about 25%, the X passes about 5%; streaming the remaining sites was slower.
+#ifndef PF_STREAM_MASK
+#define PF_STREAM_MASK 0x3Du
+#endif
+enum : unsigned {
+    ST_C2C_ROWS = 1,       // Y / Z pass: 16-byte stores of rows, row-major input side
+    ST_C2C_ROWS_INP = 2,   // Y / Z pass: 16-byte stores of rows, point-major input side
+    ST_C2C_POINTS = 4,     // Y / Z pass: 8-byte stores to a point-major output side
+    ST_R2C = 8,            // forward X pass: stores to the workspace
+    ST_C2R = 16,           // backward X pass: stores of real lines
+    LD_C2C_ROWS = 32,      // Y / Z pass: 16-byte loads of rows
+    LD_R2C = 64,           // forward X pass: loads of real lines
+    LD_C2R = 128,          // backward X pass: loads from the workspace
+    LD_C2C_POINTS = 256,   // Y / Z pass: 8-byte loads from a point-major input side
+};
+template <unsigned BIT>
+constexpr bool streamed() {
+    return (PF_STREAM_MASK & BIT) != 0;
+}
+
+// threadIdx.x passed through an empty asm statement: lane indices and LDS
+// addresses derived from it are then recomputed inside a tile loop instead of
+// being hoisted and held (or spilled) across it
+__device__ __forceinline__ int opaque_tid() {
+    int v = threadIdx.x;
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+typedef float pf_f4 __attribute__((ext_vector_type(4)));
+typedef float pf_f2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ void gst(float4 *p, float4 v) {
+    if constexpr (NT) {
+        const pf_f4 u = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(u, reinterpret_cast<pf_f4 *>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void gst(float2 *p, float2 v) {
+    if constexpr (NT) {
+        const pf_f2 u = {v.x, v.y};
+        __builtin_nontemporal_store(u, reinterpret_cast<pf_f2 *>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ float4 gld(const float4 *p) {
+    if constexpr (NT) {
+        const pf_f4 u = __builtin_nontemporal_load(reinterpret_cast<const pf_f4 *>(p));
+        return make_float4(u.x, u.y, u.z, u.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ float2 gld(const float2 *p) {
+    if constexpr (NT) {
+        const pf_f2 u = __builtin_nontemporal_load(reinterpret_cast<const pf_f2 *>(p));
+        return make_float2(u.x, u.y);
+    } else {
+        return *p;
+    }
+}
+
 extern __shared__ __align__(16) unsigned char pf_smem[];
 
 __host__ __device__ constexpr int p2_stages(int N) { return N <= 256 ? 2 : 3; }
@@ -290,12 +365,6 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
     const int CB = (int)a.CB;
     const int ntiles = (int)(a.A * a.CB);
-    const int cp_in = INP ? tid / T : tid % CP;
-    const int q_in = INP ? tid % T : tid / CP;
-    const int cp_mid = tid % CP;
-    const int q_mid = tid / CP;
-    const int cp_out = OUTP ? tid / T : tid % CP;
-    const int q_out = OUTP ? tid % T : tid / CP;
     const long long in_step = a.in_s.sp * T;
     const long long out_step = a.out_s.sp * T;
 
@@ -311,22 +380,25 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
                (long long)(2 * cp) * sd.sc + (long long)q * sd.sp;
     };
     auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
+        const int tv = opaque_tid();
+        const int cp_in = INP ? tv / T : tv % CP;
+        const int q_in = INP ? tv % T : tv / CP;
         int ncol;
         const long long b = side_addr(a.in_s, t, cp_in, q_in, ncol);
         if (INP) {  // two lines, 8 bytes per lane each
             if (2 * cp_in < ncol) {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) d0[m] = in[b + m * in_step];
+                for (int m = 0; m < 16; ++m) d0[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + m * in_step);
             }
             if (2 * cp_in + 1 < ncol) {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) d1[m] = in[b + a.in_s.sc + m * in_step];
+                for (int m = 0; m < 16; ++m) d1[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + a.in_s.sc + m * in_step);
             }
         } else if (2 * cp_in < ncol) {  // rows: both columns in one 16-byte load
             // a partially valid pair only occurs on a side padded to whole 16-column blocks
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
-                const float4 x = *reinterpret_cast<const float4 *>(in + b + m * in_step);
+                const float4 x = gld<streamed<LD_C2C_ROWS>()>(reinterpret_cast<const float4 *>(in + b + m * in_step));
                 d0[m] = make_float2(x.x, x.y);
                 d1[m] = make_float2(x.z, x.w);
             }
@@ -338,6 +410,13 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     if (t < ntiles) load(p0, p1, t);
     __syncthreads();  // twiddle table in LDS
     for (; t < ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        const int cp_in = INP ? tv / T : tv % CP;
+        const int q_in = INP ? tv % T : tv / CP;
+        const int cp_mid = tv % CP;
+        const int q_mid = tv / CP;
+        const int cp_out = OUTP ? tv / T : tv % CP;
+        const int q_out = OUTP ? tv % T : tv / CP;
         cx<float> v0[16], v1[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
@@ -355,7 +434,7 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
         __syncthreads();
 
         if constexpr (S == 3 && MT != 0) {  // stage 1 on the matrix cores
-            p2_stage1_mfma<N, TC, DIR, MT>(buf, twl + p2_twoff(N, 1), atab, tid);
+            p2_stage1_mfma<N, TC, DIR, MT>(buf, twl + p2_twoff(N, 1), atab, tv);
         } else if constexpr (S == 3) {  // stage 1: radix 16, NS = 16
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
@@ -386,16 +465,17 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
             if (OUTP) {
                 if (2 * cp_out < ncol) {
 #pragma unroll
-                    for (int m = 0; m < 16; ++m) out[b + m * out_step] = v0[m];
+                    for (int m = 0; m < 16; ++m) gst<streamed<ST_C2C_POINTS>()>(out + b + m * out_step, v0[m]);
                 }
                 if (2 * cp_out + 1 < ncol) {
 #pragma unroll
-                    for (int m = 0; m < 16; ++m) out[b + a.out_s.sc + m * out_step] = v1[m];
+                    for (int m = 0; m < 16; ++m) gst<streamed<ST_C2C_POINTS>()>(out + b + a.out_s.sc + m * out_step, v1[m]);
                 }
             } else if (2 * cp_out < ncol) {
 #pragma unroll
                 for (int m = 0; m < 16; ++m)
-                    *reinterpret_cast<float4 *>(out + b + m * out_step) = pack2(v0[m], v1[m]);
+                    gst<streamed<INP ? ST_C2C_ROWS_INP : ST_C2C_ROWS>()>(reinterpret_cast<float4 *>(out + b + m * out_step),
+                                                                   pack2(v0[m], v1[m]));
             }
         }
         __syncthreads();  // the next tile's stage 0 overwrites the LDS tile
@@ -455,20 +535,21 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
     cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
     const int lines = (int)a.lines;
     const int ntiles = (lines + 15) / 16;
-    const int cp_in = tid / T, q_in = tid % T;     // lines: lanes along points
-    const int cp_mid = tid % CP, q_mid = tid / CP; // exchanges: lanes along line pairs
     const long long kbstride = (long long)a.ny << 4;
 
     auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
+        const int tv = opaque_tid();
+        const int cp_in = tv / T, q_in = tv % T;  // lines: lanes along points
         const int ga = 16 * t + 2 * cp_in;
         const float *pa = in + (long long)ga * a.ld_real + 2 * q_in;
         if (ga < lines) {
 #pragma unroll
-            for (int m = 0; m < 16; ++m) d0[m] = *reinterpret_cast<const float2 *>(pa + 2 * T * m);
+            for (int m = 0; m < 16; ++m) d0[m] = gld<streamed<LD_R2C>()>(reinterpret_cast<const float2 *>(pa + 2 * T * m));
         }
         if (ga + 1 < lines) {
 #pragma unroll
-            for (int m = 0; m < 16; ++m) d1[m] = *reinterpret_cast<const float2 *>(pa + a.ld_real + 2 * T * m);
+            for (int m = 0; m < 16; ++m)
+                d1[m] = gld<streamed<LD_R2C>()>(reinterpret_cast<const float2 *>(pa + a.ld_real + 2 * T * m));
         }
     };
 
@@ -477,6 +558,9 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
     if (t < ntiles) load(p0, p1, t);
     __syncthreads();
     for (; t < ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        const int cp_in = tv / T, q_in = tv % T;     // lines: lanes along points
+        const int cp_mid = tv % CP, q_mid = tv / CP; // exchanges: lanes along line pairs
         cx<float> v0[16], v1[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
@@ -493,7 +577,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
         for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
         __syncthreads();
         if constexpr (S == 3 && MT != 0) {
-            p2_stage1_mfma<M, TC, -1, MT>(buf, twl + p2_twoff(M, 1), atab, tid);
+            p2_stage1_mfma<M, TC, -1, MT>(buf, twl + p2_twoff(M, 1), atab, tv);
         } else if constexpr (S == 3) {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
@@ -522,7 +606,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
         __syncthreads();
 
         // split and store: chunk = (column block kb, line pair pr, mode pair kp)
-        for (int f = tid; f < NKB * 64; f += NT) {
+        for (int f = tv; f < NKB * 64; f += NT) {
             const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
             const int ga = 16 * t + 2 * pr;
             const int k0 = kb * 16 + 2 * kp;
@@ -547,15 +631,15 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
             const long long col = (long long)kb * kbstride + 2 * kp;
             cx<float> *oa = out + rowoff[2 * pr] + col;
             if (k0 + 1 <= M)
-                *reinterpret_cast<float4 *>(oa) = pack2(xa[0], xa[1]);
+                gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(oa), pack2(xa[0], xa[1]));
             else
-                *oa = xa[0];
+                gst<streamed<ST_R2C>()>(oa, xa[0]);
             if (ga + 1 < lines) {
                 cx<float> *ob = out + rowoff[2 * pr + 1] + col;
                 if (k0 + 1 <= M)
-                    *reinterpret_cast<float4 *>(ob) = pack2(xb[0], xb[1]);
+                    gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(ob), pack2(xb[0], xb[1]));
                 else
-                    *ob = xb[0];
+                    gst<streamed<ST_R2C>()>(ob, xb[0]);
             }
         }
         __syncthreads();  // LDS tile and row offsets are reused by the next tile
@@ -572,6 +656,7 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     constexpr int RL = p2_radix(M, S - 1);
     constexpr int NSL = p2_ns(M, S - 1);
     constexpr int NIT = M / 2 * 8 / NT;  // (mode k < M/2, line pair) items per thread per tile
+    static_assert(NT % 128 == 0, "an item's line pair depends on tid only");
     float4 *buf = reinterpret_cast<float4 *>(pf_smem);
     cx<float> *twl = reinterpret_cast<cx<float> *>(buf + M * CP);
     cx<float> *spl = twl + M;
@@ -592,8 +677,6 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     float *__restrict__ out = reinterpret_cast<float *>(a.out);
     const int lines = (int)a.lines;
     const int ntiles = (lines + 15) / 16;
-    const int cp_mid = tid % CP, q_mid = tid / CP;
-    const int cp_out = tid / T, q_out = tid % T;
 
     // item i of this thread: f = tid + NT i -> mode k = 16 kb + j (k < M/2) and line
     // pair pr; it holds X[k] and X[M-k] of both lines (for k = 0 the partner is
@@ -617,26 +700,22 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
             return (z - z0) * zplane + (y - y0) * 16;
         };
         auto col = [&](int k) { return (k >> 4) * kbs + (k & 15); };
+        // lines past the end load the last line instead; their results are never stored
+        const int lmax = lines - 1 - g0;
+        const int pr = (tid >> 4) & 7;  // the same line pair for every item (NT is a multiple of 128)
+        const cx<float> *ra = tb + rowrel(min(2 * pr, lmax));
+        const cx<float> *rb = tb + rowrel(min(2 * pr + 1, lmax));
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int f = tid + NT * i;
-            const int k = ((f >> 7) << 4) + (f & 15), pr = (f >> 4) & 7;
+            const int k = ((f >> 7) << 4) + (f & 15);
             const int ck = col(k), cm = col(M - k);
-            float2 ak = make_float2(0.f, 0.f), am = ak, bk = ak, bm = ak;
-            if (g0 + 2 * pr < lines) {
-                const int ra = rowrel(2 * pr);
-                ak = tb[ra + ck];
-                am = tb[ra + cm];
-            }
-            if (g0 + 2 * pr + 1 < lines) {
-                const int rb = rowrel(2 * pr + 1);
-                bk = tb[rb + ck];
-                bm = tb[rb + cm];
-            }
+            const float2 ak = gld<streamed<LD_C2R>()>(ra + ck), am = gld<streamed<LD_C2R>()>(ra + cm);
+            const float2 bk = gld<streamed<LD_C2R>()>(rb + ck), bm = gld<streamed<LD_C2R>()>(rb + cm);
             xk[i] = make_float4(ak.x, ak.y, bk.x, bk.y);
             xm[i] = make_float4(am.x, am.y, bm.x, bm.y);
         }
-        if (tid < 16) xh = g0 + tid < lines ? tb[rowrel(tid) + col(M / 2)] : make_float2(0.f, 0.f);
+        if (tid < 16) xh = gld<streamed<LD_C2R>()>(tb + rowrel(min(tid, lmax)) + col(M / 2));
     };
 
     // Zb[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) W_nx^-k, one line
@@ -652,11 +731,14 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     if (t < ntiles) load(pk, pm, ph, t);
     __syncthreads();
     for (; t < ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        const int cp_mid = tv % CP, q_mid = tv / CP;
+        const int cp_out = tv / T, q_out = tv % T;
         // inverse split from registers into LDS: item (k, pair) writes Zb[k] and
         // Zb[M-k] of both lines; modes 0 and M contribute their real parts only
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
-            const int f = tid + NT * i;
+            const int f = tv + NT * i;
             const int k = ((f >> 7) << 4) + (f & 15), pr = (f >> 4) & 7;
             float2 Ak = make_float2(pk[i].x, pk[i].y), Bk = make_float2(pk[i].z, pk[i].w);
             float2 Am = make_float2(pm[i].x, pm[i].y), Bm = make_float2(pm[i].z, pm[i].w);
@@ -670,9 +752,9 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
                 buf[p2_slot<TC>(M - k, pr)] = pack2(zb(Am, Ak, wm), zb(Bm, Bk, wm));
             }
         }
-        if (tid < 16) {
+        if (tv < 16) {
             const cx<float> w = spl[M / 2];
-            reinterpret_cast<float2 *>(buf)[2 * p2_slot<TC>(M / 2, tid >> 1) + (tid & 1)] =
+            reinterpret_cast<float2 *>(buf)[2 * p2_slot<TC>(M / 2, tv >> 1) + (tv & 1)] =
                 zb(ph, ph, make_float2(w.x, -w.y));
         }
         const int tn = t + gridDim.x;
@@ -693,7 +775,7 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
         for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_mid * 16 + r, cp_mid)] = pack2(v0[r], v1[r]);
         __syncthreads();
         if constexpr (S == 3 && MT != 0) {
-            p2_stage1_mfma<M, TC, 1, MT>(buf, twl + p2_twoff(M, 1), atab, tid);
+            p2_stage1_mfma<M, TC, 1, MT>(buf, twl + p2_twoff(M, 1), atab, tv);
         } else if constexpr (S == 3) {
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
@@ -721,11 +803,12 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
             float *oa = out + (long long)ga * a.ld_real + 2 * q_out;
             if (ga < lines) {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) *reinterpret_cast<float2 *>(oa + 2 * T * m) = v0[m];
+                for (int m = 0; m < 16; ++m) gst<streamed<ST_C2R>()>(reinterpret_cast<float2 *>(oa + 2 * T * m), v0[m]);
             }
             if (ga + 1 < lines) {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) *reinterpret_cast<float2 *>(oa + a.ld_real + 2 * T * m) = v1[m];
+                for (int m = 0; m < 16; ++m)
+                    gst<streamed<ST_C2R>()>(reinterpret_cast<float2 *>(oa + a.ld_real + 2 * T * m), v1[m]);
             }
         }
         __syncthreads();
