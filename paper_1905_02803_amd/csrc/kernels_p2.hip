@@ -111,12 +111,19 @@ __host__ __device__ constexpr int p2_twoff(int N, int s) {
 }
 
 // LDS slot (in 16-byte column pairs) of point p, pair cp; TC/2 pairs per row.
-// The row xor and the pair xor keep every exchange pattern of the kernel
-// free of bank conflicts for N = 512 and 1024 (64 banks of 4 bytes).
+// Bank behaviour of gfx950 as the SQ_LDS_BANK_CONFLICT counter shows it:
+// 16-byte reads serve 16 lanes per cycle from 64 banks of 4 bytes, 16-byte
+// writes 8 lanes per cycle from 32 banks (8-byte accesses: twice the lanes).
+// The row xor (bit 0 of the row from bits 3, 7, 8 of p) and the pair xor
+// (bits 0-2 of p ^ p >> 4 ^ p >> 5) make every exchange of the Y / Z kernels
+// and of the matrix-core stage conflict-free under that model for N = 256 ..
+// 1024 and 16 columns; only the mirrored (k, M - k) accesses of the X
+// stages' split keep some two-way conflicts.
 template <int TC>
 __device__ __forceinline__ int p2_slot(int p, int cp) {
     constexpr int CP = TC / 2;
-    return ((p ^ ((p >> 4) & 1)) * CP) + (cp ^ (((p >> 1) ^ (p >> 5)) & (CP - 1)));
+    const int row = p ^ (((p >> 3) ^ (p >> 7) ^ (p >> 8)) & 1);
+    return row * CP + (cp ^ ((p ^ (p >> 4) ^ (p >> 5)) & (CP - 1)));
 }
 
 // One stage's butterflies on the 16 registers of each of a thread's two
