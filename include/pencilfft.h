@@ -103,6 +103,19 @@ extern "C" {
  * built: pf_setup returns PF_EUNSUPPORTED).  inplace: in == out, and the
  * buffer must hold max(real, complex) bytes; real data sits unpadded at the
  * start of the buffer (Sec. 3.1 lists in- and out-of-place transforms).
+ *
+ * share_only = 1 runs the local stages of the single rank (r1, r2) of the
+ * m1 x m2 grid at its Table 1 shapes (Sec. 2, 3.2), the work one GPU of a
+ * distributed run does between exchanges.  The user arrays are that rank's
+ * blocks alone: forward input its X-pencil, forward output its Z-pencil (and
+ * the reverse), in Table 1 order.  Each exchange keeps only the part the rank
+ * sends to itself; the blocks the other ranks would send count as zero.  The
+ * forward result is thus the 3D transform of the input extended by zeros to
+ * the whole grid, restricted to the rank's Z-pencil block; the backward
+ * result is the staged C2R of the input extended by zeros, restricted to the
+ * rank's X-pencil block.  A 1 x 1 share is the whole transform.  Not
+ * combinable with inplace (PF_EUNSUPPORTED).  The workspace holds the
+ * global-layout arrays; zero fills stand in for the received blocks.
  */
 typedef struct pf_layout {
     int m1, m2;     /* processor grid, each >= 1                            */
@@ -112,8 +125,9 @@ typedef struct pf_layout {
     int math;       /* PF_PLAIN (default), PF_MFMA_FP16X2, PF_MFMA_BF16X2   */
     int inplace;    /* 0 (default) = out-of-place, 1 = in-place             */
     int third;      /* PF_THIRD_FFT (default) or PF_THIRD_EMPTY             */
-    int share_only; /* reserved, must be 0                                   */
-    int r1, r2;     /* reserved, must be 0                                   */
+    int share_only; /* 0 (default) or 1: one rank's share, see below         */
+    int r1, r2;     /* share_only: the rank, 0 <= r1 < m1, 0 <= r2 < m2;     */
+                    /* otherwise 0                                            */
 } pf_layout;
 
 typedef struct pf_plan pf_plan;
@@ -188,6 +202,9 @@ const char *pf_strerror(int code);
  * Number of HBM passes (kernel launches) one transform makes in direction dir
  * (PF_DIR_FORWARD or PF_DIR_BACKWARD): 3 for a 1 x 1 grid, 5 for m1 * m2 > 1
  * (a pack pass before and an unpack pass after the three transform passes).
+ * Share-only plans: 5 forward (zero fill, X, Y, Z, copy of the Z block out)
+ * and 6 backward (zero fill, copy of the Z block in, Z, Y, zeroing of the
+ * modes outside the rank's kx range, X).
  */
 int pf_num_passes(const pf_plan *p, int dir);
 
@@ -204,7 +221,9 @@ int pf_num_passes(const pf_plan *p, int dir);
  * ([nz][ny][nx] real, the 1 x 1 Z-pencil layout complex); pass 0 packs the
  * user's blocks into the global array and pass 4 unpacks the global array into
  * the user's blocks.  `in`/`out` that name the workspace may be any buffer of
- * pf_workspace_bytes bytes.  pass_name returns a short static name.
+ * pf_workspace_bytes bytes.  Share-only plans run their passes only as a
+ * whole chain (pf_run_pass returns PF_EUNSUPPORTED).  pass_name returns a
+ * short static name.
  */
 int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *stream);
 const char *pf_pass_name(const pf_plan *p, int dir, int pass);

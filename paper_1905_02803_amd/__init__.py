@@ -243,12 +243,22 @@ class Plan:
 
         return torch.complex128 if self.layout.precision == PF_F64 else torch.complex64
 
+    def _block_shape(self, pencil):
+        """C shape of rank (r1, r2)'s block of a pencil (share-only plans), slowest first."""
+        _, size, order = pf_query_dims(self.nx, self.ny, self.nz, self.layout, pencil, self.layout.r1,
+                                       self.layout.r2)
+        return (size[order[2]], size[order[1]], size[order[0]])
+
     @property
     def real_shape(self):
+        if self.layout.share_only:
+            return self._block_shape(PF_PENCIL_X)
         return (self.nz, self.ny, self.nx)
 
     @property
     def complex_shape(self):
+        if self.layout.share_only:
+            return self._block_shape(PF_PENCIL_Z)
         if self.layout.stride1:
             return (self.nxh, self.ny, self.nz)
         return (self.nz, self.ny, self.nxh)

@@ -19,7 +19,7 @@ using pf::Side;
 
 namespace {
 
-constexpr int kPasses = 5;  // at most: pack, X/Z, Y, Z/X, unpack
+constexpr int kPasses = 6;  // at most: fill, insert, Z, Y, mask, X (share-only backward)
 constexpr size_t kLdsBudget = 80 * 1024;  // two workgroups per CU fit in 160 KB
 
 struct EventPair {
@@ -48,6 +48,8 @@ struct pf_plan {
     size_t w_bytes;    // bytes of W
     bool own_ws;
     bool blocked;      // m1 m2 > 1: user arrays are the concatenated Table 1 blocks
+    bool share;        // share-only: user arrays are rank (r1, r2)'s blocks
+    size_t so_x, so_y, so_zw, so_zg;  // share-only byte offsets: X and Y into W, Z into W and G
     int npass[2];
     PassDesc pass[2][kPasses];
     const char *pass_names[2][kPasses];
@@ -73,7 +75,12 @@ bool valid_layout_values(const pf_layout *l) {
     if (l->math != PF_PLAIN && l->math != PF_MFMA_FP16X2 && l->math != PF_MFMA_BF16X2) return false;
     if (l->inplace != 0 && l->inplace != 1) return false;
     if (l->third != PF_THIRD_FFT && l->third != PF_THIRD_EMPTY) return false;
-    if (l->share_only != 0 || l->r1 != 0 || l->r2 != 0) return false;
+    if (l->share_only != 0 && l->share_only != 1) return false;
+    if (l->share_only) {
+        if (l->r1 < 0 || l->r1 >= l->m1 || l->r2 < 0 || l->r2 >= l->m2) return false;
+    } else if (l->r1 != 0 || l->r2 != 0) {
+        return false;
+    }
     return true;
 }
 
@@ -174,6 +181,7 @@ int built_options(const pf_layout *l) {
     if (l->math != PF_PLAIN && l->precision != PF_F32) return PF_EUNSUPPORTED;
     if (l->third != PF_THIRD_FFT) return PF_EUNSUPPORTED;
     if (l->useeven) return PF_EUNSUPPORTED;
+    if (l->share_only && l->inplace) return PF_EUNSUPPORTED;
     return PF_OK;
 }
 
@@ -309,6 +317,135 @@ void add_remaps(pf_plan *p, int dir) {
     p->npass[dir] = 5;
 }
 
+// Share-only plan: the local stages of rank (r1, r2) of the m1 x m2 grid at
+// their Table 1 shapes (Sec. 2, 3.2), each exchange reduced to the part that
+// stays on the rank.  The other ranks' blocks are taken as zero, so the
+// forward result is the transform of the input extended by zeros outside the
+// rank's X-pencil, restricted to its Z-pencil block, and the backward result
+// is the staged C2R of the input extended by zeros outside the rank's
+// Z-pencil, restricted to its X-pencil block.  The global-layout workspace W
+// and array G hold the blocks at their global positions; zero fills stand in
+// for the blocks other ranks would send.
+//   forward : fill, X on the rank's lines, Y on its z planes, Z on its ky
+//             range, copy of its Z block out of G
+//   backward: fill, copy of its Z block into G, Z, Y, zero the modes outside
+//             its kx range, X on its lines
+void build_share_only(pf_plan *p) {
+    const pf_layout &l = p->lay;
+    int xs, xl, ys1, yl1, zs2, zl2, ys2, yl2;
+    block_split(p->nxh, l.m1, l.r1, &xs, &xl);
+    block_split(p->ny, l.m1, l.r1, &ys1, &yl1);
+    block_split(p->nz, l.m2, l.r2, &zs2, &zl2);
+    block_split(p->ny, l.m2, l.r2, &ys2, &yl2);
+    const int B = p->B;
+    const int kbA = xs / B, kbB = (xs + xl - 1) / B + 1;  // column blocks [kbA, kbB) hold the rank's modes
+    const long long zstride = (long long)p->nkb * p->ny * B;  // complex elements per z plane of W
+    const int rw = l.precision == PF_F64 ? 2 : 1;
+    const double rs = 4.0 * rw, cs = 2.0 * rs;
+    const int ncolsK = std::min(p->nxh, kbB * B) - kbA * B;
+    p->so_x = (size_t)zs2 * zstride * p->csize;
+    p->so_y = ((size_t)zs2 * zstride + (size_t)kbA * p->ny * B) * p->csize;
+    p->so_zw = ((size_t)ys2 * B + (size_t)kbA * p->ny * B) * p->csize;
+    p->so_zg = (l.stride1 ? ((size_t)kbA * B * p->ny * p->nz + (size_t)ys2 * p->nz)
+                          : ((size_t)kbA * B + (size_t)ys2 * p->nxh)) * p->csize;
+
+    auto fill = [&](int nbox, const int (*box)[4], int k0, int k1, int keep0, int keep1, double *bytes) {
+        PassDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.kind = pf::PASS_FILL;
+        d.prec = l.precision;
+        pf::FillArgs &f = d.f;
+        f.words = 2 * rw, f.B = B, f.ny = p->ny, f.nkb = p->nkb;
+        f.kb0 = k0, f.kb1 = k1, f.keep0 = keep0, f.keep1 = keep1;
+        f.nbox = nbox;
+        double rows = 0;
+        for (int i = 0; i < nbox; ++i) {
+            f.z0[i] = box[i][0], f.z1[i] = box[i][1], f.y0[i] = box[i][2], f.y1[i] = box[i][3];
+            rows += (double)(box[i][1] - box[i][0]) * (box[i][3] - box[i][2]);
+        }
+        const int kept = std::max(0, std::min(keep1, k1 * B) - std::max(keep0, k0 * B));
+        *bytes = rows * ((double)(k1 - k0) * B - kept) * cs;
+        return d;
+    };
+    auto box = [&](int to_block) {
+        PassDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.kind = pf::PASS_BOX;
+        d.prec = l.precision;
+        pf::BoxArgs &b = d.b;
+        b.words = 2 * rw;
+        b.to_block = to_block;
+        if (l.stride1) {  // G [kx][ky][kz], block [xl][yl2][nz]
+            b.st1 = p->nz, b.st2 = (long long)p->ny * p->nz;
+            b.o0 = 0, b.o1 = ys2, b.o2 = xs, b.s0 = p->nz, b.s1 = yl2, b.s2 = xl;
+        } else {  // G [kz][ky][kx], block [nz][yl2][xl]
+            b.st1 = p->nxh, b.st2 = (long long)p->ny * p->nxh;
+            b.o0 = xs, b.o1 = ys2, b.o2 = 0, b.s0 = xl, b.s1 = yl2, b.s2 = p->nz;
+        }
+        return d;
+    };
+    for (int dir = 0; dir < 2; ++dir) {
+        PassDesc x = p->pass[dir][dir == 0 ? 0 : 2];
+        PassDesc y = p->pass[dir][1];
+        PassDesc z = p->pass[dir][dir == 0 ? 2 : 0];
+        // X on the rank's lines: y_local < yl1 in each of its zl2 planes
+        x.a.lines = (long long)yl1 * zl2;
+        x.a.ny = yl1;
+        x.a.y0 = ys1;
+        if (x.kind == pf::PASS_R2C_P2 || x.kind == pf::PASS_C2R_P2) {
+            const long long tiles = (x.a.lines + 15) / 16;
+            const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(x);
+            x.blocks = (unsigned)std::min(tiles, resident);
+        } else {
+            const long long pairs = (x.a.lines + 1) / 2, tcx = 1LL << x.a.tc_log2;
+            x.blocks = (unsigned)((pairs + tcx - 1) / tcx);
+        }
+        // Y on the rank's z planes and the column blocks of its modes
+        y.a.A = zl2;
+        y.a.CB = (long long)(kbB - kbA) * (B >> y.a.tc_log2);
+        y.a.C = p->nxh - kbA * B;
+        y.blocks = c2c_grid(p, y);
+        // Z on the rank's ky range and the same column blocks
+        z.a.A = yl2;
+        z.a.CB = y.a.CB;
+        z.a.C = y.a.C;
+        z.blocks = c2c_grid(p, z);
+        const double xbytes = (double)x.a.lines * (p->nx * rs + p->nxh * cs);
+        const double ybytes = 2.0 * zl2 * p->ny * ncolsK * cs;
+        const double zbytes = 2.0 * yl2 * p->nz * ncolsK * cs;
+        const double bbytes = 2.0 * xl * yl2 * p->nz * cs;
+        if (dir == 0) {
+            const int fb[4][4] = {{zs2, zs2 + zl2, 0, ys1}, {zs2, zs2 + zl2, ys1 + yl1, p->ny},
+                                  {0, zs2, ys2, ys2 + yl2}, {zs2 + zl2, p->nz, ys2, ys2 + yl2}};
+            double fbytes;
+            p->pass[0][0] = fill(4, fb, kbA, kbB, 0, 0, &fbytes);
+            p->pass[0][1] = x;
+            p->pass[0][2] = y;
+            p->pass[0][3] = z;
+            p->pass[0][4] = box(1);
+            const char *names[] = {"share_fill", "share_x_r2c", "share_y_c2c", "share_z_c2c", "share_extract_z"};
+            const double bytes[] = {fbytes, xbytes, ybytes, zbytes, bbytes};
+            for (int i = 0; i < 5; ++i) p->pass_names[0][i] = names[i], p->pass_bytes[0][i] = bytes[i];
+            p->npass[0] = 5;
+        } else {
+            const int fb[2][4] = {{zs2, zs2 + zl2, 0, ys2}, {zs2, zs2 + zl2, ys2 + yl2, p->ny}};
+            const int mb[1][4] = {{zs2, zs2 + zl2, ys1, ys1 + yl1}};
+            double fbytes, mbytes;
+            p->pass[1][0] = fill(2, fb, kbA, kbB, 0, 0, &fbytes);
+            p->pass[1][1] = box(0);
+            p->pass[1][2] = z;
+            p->pass[1][3] = y;
+            p->pass[1][4] = fill(1, mb, 0, p->nkb, xs, xs + xl, &mbytes);
+            p->pass[1][5] = x;
+            const char *names[] = {"share_fill", "share_insert_z", "share_z_c2c", "share_y_c2c", "share_mask_kx",
+                                   "share_x_c2r"};
+            const double bytes[] = {fbytes, bbytes, zbytes, ybytes, mbytes, xbytes};
+            for (int i = 0; i < 6; ++i) p->pass_names[1][i] = names[i], p->pass_bytes[1][i] = bytes[i];
+            p->npass[1] = 6;
+        }
+    }
+}
+
 void build_passes(pf_plan *p) {
     const long long nyB = (long long)p->ny * p->B;
     const long long zstride = (long long)p->nkb * nyB;
@@ -333,6 +470,8 @@ void build_passes(pf_plan *p) {
         x.a.nkb = p->nkb;
         x.a.b_log2 = p->b_log2;
         x.a.nxh = p->nxh;
+        x.a.ypitch = p->ny;
+        x.a.y0 = 0;
         const long long pairs = (x.a.lines + 1) / 2;
         const long long tcx = 1LL << x.a.tc_log2;
         x.blocks = (unsigned)((pairs + tcx - 1) / tcx);
@@ -393,6 +532,7 @@ void build_passes(pf_plan *p) {
         p->npass[dir] = 3;
         if (p->blocked) add_remaps(p, dir);
     }
+    if (p->share) build_share_only(p);
 }
 
 EventPair take_events(pf_plan *p) {
@@ -422,6 +562,9 @@ int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s
     d.a.out = out;
     d.r.src = in;
     d.r.dst = out;
+    d.f.w = out;
+    d.b.src = in;
+    d.b.dst = out;
     EventPair ev{nullptr, nullptr};
     bool timed = false;
     if (p->timing) {
@@ -452,6 +595,25 @@ int run_chain(pf_plan *p, int dir, const void *in, void *out, void *stream) {
     const int rc = check_call(p, in, out);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if (p->share) {
+        char *w = (char *)p->ws, *g = (char *)p->ws + p->w_bytes;
+        int r;
+        if (dir == 0) {
+            r = run_one(p, 0, 0, nullptr, w, s);
+            if (!r) r = run_one(p, 0, 1, in, w + p->so_x, s);
+            if (!r) r = run_one(p, 0, 2, w + p->so_y, w + p->so_y, s);
+            if (!r) r = run_one(p, 0, 3, w + p->so_zw, g + p->so_zg, s);
+            if (!r) r = run_one(p, 0, 4, g, out, s);
+        } else {
+            r = run_one(p, 1, 0, nullptr, w, s);
+            if (!r) r = run_one(p, 1, 1, in, g, s);
+            if (!r) r = run_one(p, 1, 2, g + p->so_zg, w + p->so_zw, s);
+            if (!r) r = run_one(p, 1, 3, w + p->so_y, w + p->so_y, s);
+            if (!r) r = run_one(p, 1, 4, nullptr, w, s);
+            if (!r) r = run_one(p, 1, 5, w + p->so_x, out, s);
+        }
+        return r;
+    }
     if (!p->blocked) {
         // pass 0: user -> workspace; pass 1: workspace in place; pass 2: workspace -> user
         int r = run_one(p, dir, 0, in, p->ws, s);
@@ -601,10 +763,13 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
         delete p;
         return hip_status(e);
     }
-    p->blocked = l->m1 * l->m2 > 1;
+    p->share = l->share_only != 0;
+    p->blocked = !p->share && l->m1 * l->m2 > 1;
     p->w_bytes = ((size_t)p->nz * p->nkb * p->ny * p->B * p->csize + 255) & ~(size_t)255;
     p->ws_bytes = p->w_bytes;
-    if (p->blocked) {
+    if (p->share) {
+        p->ws_bytes += (size_t)p->nxh * ny * nz * p->csize;
+    } else if (p->blocked) {
         const size_t real_b = (size_t)nx * ny * nz * (p->csize / 2);
         const size_t cplx_b = (size_t)p->nxh * ny * nz * p->csize;
         p->ws_bytes += real_b > cplx_b ? real_b : cplx_b;
@@ -616,6 +781,15 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
         return hip_status(e);
     }
     p->own_ws = true;
+    // share-only: G starts defined (its columns beside the rank's modes are
+    // transformed but never used)
+    if (p->share) e = hipMemset((char *)p->ws + p->w_bytes, 0, p->ws_bytes - p->w_bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(p->ws);
+        (void)hipFree(p->tw_dev);
+        delete p;
+        return hip_status(e);
+    }
     build_passes(p);
     *out = p;
     return PF_OK;
@@ -677,6 +851,7 @@ int pf_num_passes(const pf_plan *p, int dir) {
 int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *stream) {
     if (!p || (dir != PF_DIR_FORWARD && dir != PF_DIR_BACKWARD)) return PF_EINVAL;
     if (pass < 0 || pass >= p->npass[dir]) return PF_EINVAL;
+    if (p->share) return PF_EUNSUPPORTED;  // its passes address sub-blocks of the workspace
     if (!in || !out) return PF_EINVAL;
     if (!aligned16(in) || !aligned16(out)) return PF_EALIGN;
     return run_one(p, dir, pass, in, out, (hipStream_t)stream);

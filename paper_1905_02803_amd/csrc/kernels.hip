@@ -154,7 +154,7 @@ __device__ __forceinline__ void x_row_offsets(const PassArgs &a, long long g0, i
         const long long g = g0 + l;
         const long long z = g / a.ny;
         const long long y = g - z * a.ny;
-        rowoff[l] = ((z * a.nkb) * a.ny + y) << a.b_log2;
+        rowoff[l] = ((z * a.nkb) * a.ypitch + a.y0 + y) << a.b_log2;
     }
 }
 
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
                    tid & (wpc - 1), wpc);
     const int B = 1 << a.b_log2;
     const int total = a.nkb * TC * B;
-    const long long kbstride = (long long)a.ny << a.b_log2;
+    const long long kbstride = (long long)a.ypitch << a.b_log2;
     const T h = T(0.5);
     for (int f = tid; f < total; f += nthr) {
         const int kk = f & (B - 1);
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
     __syncthreads();
     const int B = 1 << a.b_log2;
     const int total = a.nkb * TC * B;
-    const long long kbstride = (long long)a.ny << a.b_log2;
+    const long long kbstride = (long long)a.ypitch << a.b_log2;
     for (int f = tid; f < total; f += nthr) {
         const int kk = f & (B - 1);
         const int cc = (f >> a.b_log2) & (TC - 1);
@@ -317,6 +317,62 @@ __global__ __launch_bounds__(256) void k_remap(RemapArgs a) {
     const long long d0 = (a.gather ? goff : boff) * a.words;
     const int nw = len * a.words;
     for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[d0 + i] = src[so + i];
+}
+
+// Zero workspace rows of the boxes of f (grid-stride over words).
+__global__ __launch_bounds__(256) void k_fill(FillArgs f) {
+    unsigned *__restrict__ w = reinterpret_cast<unsigned *>(f.w);
+    const int nkbr = f.kb1 - f.kb0;
+    const int rw = f.B * f.words;  // words per row
+    for (int b = 0; b < f.nbox; ++b) {
+        const int nz = f.z1[b] - f.z0[b], ny = f.y1[b] - f.y0[b];
+        const long long total = (long long)nz * nkbr * ny * rw;
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+             i += (long long)gridDim.x * blockDim.x) {
+            long long r = i / rw;
+            const int e = (int)(i - r * rw);
+            const int y = (int)(r % ny);
+            r /= ny;
+            const int kb = (int)(r % nkbr);
+            const int z = (int)(r / nkbr);
+            const int kx = (f.kb0 + kb) * f.B + e / f.words;
+            if (kx >= f.keep0 && kx < f.keep1) continue;
+            const long long row = ((long long)(f.z0[b] + z) * f.nkb + f.kb0 + kb) * f.ny + f.y0[b] + y;
+            w[row * rw + e] = 0u;
+        }
+    }
+}
+
+// One block per box row (i1, i2); threads copy the row's s0 elements.
+__global__ __launch_bounds__(256) void k_box(BoxArgs b) {
+    const int i1 = (int)(blockIdx.x % b.s1), i2 = (int)(blockIdx.x / b.s1);
+    const long long g = ((long long)(b.o2 + i2) * b.st2 + (long long)(b.o1 + i1) * b.st1 + b.o0) * b.words;
+    const long long k = ((long long)i2 * b.s1 + i1) * b.s0 * b.words;
+    const unsigned *__restrict__ src = reinterpret_cast<const unsigned *>(b.src);
+    unsigned *__restrict__ dst = reinterpret_cast<unsigned *>(b.dst);
+    const long long so = b.to_block ? g : k, d0 = b.to_block ? k : g;
+    const int nw = b.s0 * b.words;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[d0 + i] = src[so + i];
+}
+
+hipError_t launch_fill(const FillArgs &f, hipStream_t s) {
+    if (f.nbox < 0 || f.nbox > 4) return hipErrorInvalidValue;
+    long long total = 0;
+    for (int b = 0; b < f.nbox; ++b)
+        total += (long long)(f.z1[b] - f.z0[b]) * (f.kb1 - f.kb0) * (f.y1[b] - f.y0[b]) * f.B * f.words;
+    if (total <= 0) return hipSuccess;
+    const long long want = (total + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_box(const BoxArgs &b, hipStream_t s) {
+    const long long rows = (long long)b.s1 * b.s2;
+    if (rows <= 0 || b.s0 <= 0) return hipSuccess;
+    if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_box, dim3((unsigned)rows), dim3(256), 0, s, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_remap(const RemapArgs &r, hipStream_t s) {
@@ -416,6 +472,10 @@ hipError_t launch_pass(const PassDesc &d, hipStream_t s) {
             return p2_launch(d, s);
         case PASS_REMAP:
             return launch_remap(d.r, s);
+        case PASS_FILL:
+            return launch_fill(d.f, s);
+        case PASS_BOX:
+            return launch_box(d.b, s);
     }
     return hipGetLastError();
 }

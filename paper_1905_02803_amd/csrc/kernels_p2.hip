@@ -508,7 +508,7 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
 __device__ __forceinline__ long long x_rowoff(const PassArgs &a, int g) {
     const int z = g / a.ny;
     const int y = g - z * a.ny;
-    return (((long long)z * a.nkb) * a.ny + y) << 4;
+    return (((long long)z * a.nkb) * a.ypitch + a.y0 + y) << 4;
 }
 
 template <int M, int MT>
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
     cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
     const int lines = (int)a.lines;
     const int ntiles = (lines + 15) / 16;
-    const long long kbstride = (long long)a.ny << 4;
+    const long long kbstride = (long long)a.ypitch << 4;
 
     auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
         const int tv = opaque_tid();
@@ -695,9 +695,9 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
         const int g0 = 16 * t;
         const int z0 = g0 / a.ny;
         const int y0 = g0 - z0 * a.ny;
-        const cx<float> *tb = in + ((((long long)z0 * a.nkb) * a.ny + y0) << 4);
-        const int zplane = a.nkb * a.ny * 16;  // elements per z plane of the workspace
-        const int kbs = a.ny * 16;
+        const cx<float> *tb = in + ((((long long)z0 * a.nkb) * a.ypitch + a.y0 + y0) << 4);
+        const int zplane = a.nkb * a.ypitch * 16;  // elements per z plane of the workspace
+        const int kbs = a.ypitch * 16;
         // line l of the tile (g = g0 + l, any number of z planes when ny < 16)
         // starts at row offset rowrel(l) from the tile base (z0, y0)
         auto rowrel = [&](int l) {

@@ -37,7 +37,9 @@ enum PassKind {
     PASS_C2C_P2 = 3,
     PASS_R2C_P2 = 4,
     PASS_C2R_P2 = 5,
-    PASS_REMAP = 6
+    PASS_REMAP = 6,
+    PASS_FILL = 7,
+    PASS_BOX = 8
 };
 
 // Reorder between the global arrays and the concatenated Table 1 pencil
@@ -59,6 +61,30 @@ struct RemapArgs {
     long long nlines;
 };
 
+// Zero elements of the blocked workspace [z][kb][y][B] (B elements of `words`
+// 4-byte words per row): rows (z, kb, y) with kb in [kb0, kb1) and (z, y) in
+// one of nbox boxes [z0, z1) x [y0, y1); within a row, the elements whose
+// mode kx = kb B + c lies in [keep0, keep1) are left alone.
+struct FillArgs {
+    void *w;
+    int words, B, ny, nkb;
+    int kb0, kb1, keep0, keep1;
+    int nbox;
+    int z0[4], z1[4], y0[4], y1[4];
+};
+
+// Copy a box between a strided global array (dimension 0 contiguous, element
+// strides st1, st2 of dimensions 1 and 2) and a dense block [s2][s1][s0]:
+// global element (o0 + i0, o1 + i1, o2 + i2) <-> block element (i0, i1, i2).
+struct BoxArgs {
+    const void *src;
+    void *dst;
+    int words;
+    int to_block;  // 1: global -> block, 0: block -> global
+    long long st1, st2;
+    int o0, o1, o2, s0, s1, s2;
+};
+
 struct PassArgs {
     const void *in;
     void *out;
@@ -73,15 +99,19 @@ struct PassArgs {
     int inp, outp;  // power-of-two C2C pass: 1 if that side's points are contiguous
     int math;       // power-of-two passes: 0 plain, 1 / 2 middle radix-16 stage on MFMA (FP16 / BF16 hi+lo)
     int tile_order; // power-of-two C2C pass: 0 tile t = (t / CB, t % CB), 1 tile t = (t % A, t / A)
-    // X passes: real lines (y, z) flattened as g = z * ny + y
+    // X passes: real lines (y, z) flattened as g = z * ny + y; line g's spectrum
+    // is workspace row (z nkb + kb) ypitch + y0 + y of column block kb
     long long lines;
     long long ld_real;  // elements between consecutive real lines
     int ny, nkb, b_log2, nxh;
+    int ypitch, y0;
 };
 
 struct PassDesc {
     PassKind kind;
     RemapArgs r;  // PASS_REMAP only
+    FillArgs f;   // PASS_FILL only
+    BoxArgs b;    // PASS_BOX only
     int dir;   // -1 forward, +1 backward
     int prec;  // PF_F32 / PF_F64
     unsigned blocks;
@@ -95,6 +125,8 @@ hipError_t prepare_kernels(size_t max_lds);
 // Enqueue one pass.
 hipError_t launch_pass(const PassDesc &d, hipStream_t s);
 hipError_t launch_remap(const RemapArgs &r, hipStream_t s);
+hipError_t launch_fill(const FillArgs &f, hipStream_t s);
+hipError_t launch_box(const BoxArgs &b, hipStream_t s);
 // Plain 16-byte-per-lane device copy (bytes a multiple of 16).
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 

@@ -80,6 +80,12 @@ def test_f64_length_limit():
     (dict(inplace=3), pf.PF_EINVAL),
     (dict(third=5), pf.PF_EINVAL),
     (dict(useeven=2), pf.PF_EINVAL),
+    # share-only: rank (r1, r2) must lie in the grid; r1, r2 must be 0 otherwise
+    (dict(share_only=1, m1=2, m2=3, r1=1, r2=2), pf.PF_OK),
+    (dict(share_only=1, m1=2, r1=2), pf.PF_EINVAL),
+    (dict(share_only=1, m2=3, r2=-1), pf.PF_EINVAL),
+    (dict(share_only=2), pf.PF_EINVAL),
+    (dict(r1=1, m1=2), pf.PF_EINVAL),
 ])
 def test_check_layout_values(lay, code):
     assert pf.pf_check(8, 4, 6, pf.Layout(**lay)) == code
@@ -147,7 +153,8 @@ def test_setup_rejects_bad_arguments_before_touching_the_gpu():
     for shape, lay, code in [((0, 4, 4), pf.Layout(), pf.PF_EINVAL),
                              ((11, 4, 4), pf.Layout(), pf.PF_EUNSUPPORTED),
                              ((8, 4, 6), pf.Layout(m1=5), pf.PF_EINVAL),
-                             ((8, 4, 6), pf.Layout(share_only=1), pf.PF_EINVAL)]:
+                             ((8, 4, 6), pf.Layout(share_only=1, r1=1), pf.PF_EINVAL),
+                             ((8, 4, 6), pf.Layout(share_only=1, inplace=1), pf.PF_EUNSUPPORTED)]:
         with pytest.raises(pf.PfError) as e:
             pf.pf_setup(*shape, lay)
         assert e.value.code == code
