@@ -17,6 +17,7 @@ import json
 import math
 import os
 import sys
+import statistics
 import time
 
 import numpy as np
@@ -84,7 +85,6 @@ def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
     (forward X, Y, Z, backward Z, Y, X, repeated).
     """
     import csv
-    import statistics
 
     def read(path):
         rows = list(csv.DictReader(open(path)))
@@ -153,15 +153,34 @@ def cpu_baseline(n: int, u=None, forward_outputs=None):
     dt = time.perf_counter() - t0
     N = float(n) ** 3
     errs = {}
+    shells = {}
+    # |k| shells [1, 2), [2, 4), ... [n/2, inf): the power-law input puts most of
+    # the energy at low |k|, so the global error hides the high-|k| one (mode 0
+    # of the input is zero by construction and is left out of the shells)
+    edges = [2.0 ** j for j in range(0, int(math.log2(n)))] + [math.inf]
+    kyz = np.fft.fftfreq(n, 1.0 / n)
+    k2_yz = kyz[:, None] ** 2 + kyz[None, :] ** 2  # [ky][kz]
     for name, got in (forward_outputs or {}).items():
         if got is None or got.shape != (U.shape[2], U.shape[1], U.shape[0]):
             continue
-        num = den = 0.0
+        num = np.zeros(len(edges) - 1)
+        den = np.zeros(len(edges) - 1)
+        tot_num = tot_den = 0.0
         for kx in range(got.shape[0]):  # plane by plane: got[kx] is [ky][kz], U[:, :, kx] is [kz][ky]
             ref = U[:, :, kx].T
-            num += float(np.sum(np.abs(got[kx].astype(np.complex128) - ref) ** 2))
-            den += float(np.sum(np.abs(ref) ** 2))
-        errs[name] = math.sqrt(num / den)
+            e2 = np.abs(got[kx].astype(np.complex128) - ref) ** 2
+            r2 = np.abs(ref) ** 2
+            tot_num += float(e2.sum())
+            tot_den += float(r2.sum())
+            b = (np.digitize(np.sqrt(kx * kx + k2_yz), edges) - 1).ravel()
+            ok = b >= 0
+            num += np.bincount(b[ok], weights=e2.ravel()[ok], minlength=len(num))[:len(num)]
+            den += np.bincount(b[ok], weights=r2.ravel()[ok], minlength=len(den))[:len(den)]
+        errs[name] = math.sqrt(tot_num / tot_den)
+        shells[name] = [{"k_lo": edges[i], "k_hi": edges[i + 1] if math.isfinite(edges[i + 1]) else None,
+                         "rel_l2": math.sqrt(num[i] / den[i]) if den[i] > 0 else None}
+                        for i in range(len(num))]
+    errs["_shells"] = shells
     return {
         "value": 5.0 * N * math.log2(N) / dt / 1e9,
         "unit": "GFLOP/s",
@@ -169,6 +188,44 @@ def cpu_baseline(n: int, u=None, forward_outputs=None):
         "kind": "oracle",
         "sample": f"one R2C+C2R pair at {n}^3 (FP64, OpenMP over lines), {dt:.2f} s wall",
     }, errs
+
+
+def share_only_timing(pf, nx, ny, nz, args, dev, stream, m2=8, r2=3):
+    """One rank's share of the grid on a 1 x m2 slab grid (share-only plan): per-pass times."""
+    import torch
+
+    lay = pf.Layout(precision=pf.PF_F32, stride1=1, m1=1, m2=m2, share_only=1, r1=0, r2=r2)
+    plan = pf.Plan(nx, ny, nz, lay)
+    ub = torch.randn(plan.real_shape, dtype=torch.float32, device=dev)
+    Ub = plan.empty_complex(dev)
+    rb = plan.empty_real(dev)
+    for _ in range(args.warmup):
+        plan.ftran(ub, Ub)
+        plan.btran(Ub, rb)
+    plan.set_timing(True)
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s0.record(stream)
+    for _ in range(args.steps):
+        plan.ftran(ub, Ub)
+        plan.btran(Ub, rb)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    passes = []
+    for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD):
+        for i in range(plan.num_passes(d)):
+            tot, cnt = plan.get_timing(d, i)
+            avg = tot / max(cnt, 1)
+            nbytes = plan.pass_bytes(d, i)
+            passes.append({"pass": plan.pass_name(d, i), "avg_ms": avg, "alg_bytes": nbytes,
+                           "alg_GBps": nbytes / (avg * 1e-3) / 1e9 if avg > 0 else None})
+    plan.set_timing(False)
+    out = {"grid": f"1x{m2}", "rank": [0, r2], "x_pencil": list(plan.real_shape),
+           "z_pencil": list(plan.complex_shape), "ms_per_step": s0.elapsed_time(s1) / args.steps,
+           "passes": passes}
+    plan.destroy()
+    return out
 
 
 def main():
@@ -222,15 +279,19 @@ def main():
     plan.set_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for i in range(args.steps):
         step()
+        marks[i + 1].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
+    step_ms = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
 
     passes = []
     for d, dname in ((pf.PF_DIR_FORWARD, "fwd"), (pf.PF_DIR_BACKWARD, "bwd")):
@@ -271,6 +332,7 @@ def main():
             fwd_host[name] = Um.cpu().numpy()
         del Um
         pm.destroy()
+    share = share_only_timing(pf, nx, ny, nz, args, dev, stream)
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
     gflops = flops / (ms * 1e-3) / 1e9
@@ -300,8 +362,11 @@ def main():
                    "grid": [nx, ny, nz], "precision": "f32", "math": "plain", "layout": "1x1"},
         "hbm_GBps_alg": alg_bytes / (ms * 1e-3) / 1e9,
         "copy_probe_GBps": copy_GBps,
+        "ms_per_step_median": statistics.median(step_ms),
+        "ms_per_step_min": min(step_ms),
         "round_trip_rel_l2": rt_err,
         "rel_l2_fwd_vs_fp64_oracle": errs.get("plain"),
+        "rel_l2_fwd_by_k_shell": errs.get("_shells", {}).get("plain"),
         "mfma": mfma,
         "roofline": {
             "bound": "hbm",
@@ -314,6 +379,7 @@ def main():
             "traffic": traffic_from_profile(dom["pass"], n),
         },
         "passes": passes,
+        "share_only": share,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
     }

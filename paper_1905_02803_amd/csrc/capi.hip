@@ -349,22 +349,25 @@ void build_share_only(pf_plan *p) {
     p->so_zg = (l.stride1 ? ((size_t)kbA * B * p->ny * p->nz + (size_t)ys2 * p->nz)
                           : ((size_t)kbA * B + (size_t)ys2 * p->nxh)) * p->csize;
 
-    auto fill = [&](int nbox, const int (*box)[4], int k0, int k1, int keep0, int keep1, double *bytes) {
+    // boxes {z0, z1, kb0, kb1, y0, y1}; bytes: the elements actually zeroed
+    auto fill = [&](int nbox, const int (*box)[6], int keep0, int keep1, double *bytes) {
         PassDesc d;
         std::memset(&d, 0, sizeof(d));
         d.kind = pf::PASS_FILL;
         d.prec = l.precision;
         pf::FillArgs &f = d.f;
         f.words = 2 * rw, f.B = B, f.ny = p->ny, f.nkb = p->nkb;
-        f.kb0 = k0, f.kb1 = k1, f.keep0 = keep0, f.keep1 = keep1;
+        f.keep0 = keep0, f.keep1 = keep1;
         f.nbox = nbox;
-        double rows = 0;
+        *bytes = 0;
         for (int i = 0; i < nbox; ++i) {
-            f.z0[i] = box[i][0], f.z1[i] = box[i][1], f.y0[i] = box[i][2], f.y1[i] = box[i][3];
-            rows += (double)(box[i][1] - box[i][0]) * (box[i][3] - box[i][2]);
+            f.z0[i] = box[i][0], f.z1[i] = box[i][1], f.kb0[i] = box[i][2], f.kb1[i] = box[i][3];
+            f.y0[i] = box[i][4], f.y1[i] = box[i][5];
+            const double rows = (double)std::max(0, box[i][1] - box[i][0]) * std::max(0, box[i][5] - box[i][4]);
+            const int cols = std::max(0, box[i][3] - box[i][2]) * B;
+            const int kept = std::max(0, std::min(keep1, box[i][3] * B) - std::max(keep0, box[i][2] * B));
+            *bytes += rows * (cols - kept) * cs;
         }
-        const int kept = std::max(0, std::min(keep1, k1 * B) - std::max(keep0, k0 * B));
-        *bytes = rows * ((double)(k1 - k0) * B - kept) * cs;
         return d;
     };
     auto box = [&](int to_block) {
@@ -415,10 +418,12 @@ void build_share_only(pf_plan *p) {
         const double zbytes = 2.0 * yl2 * p->nz * ncolsK * cs;
         const double bbytes = 2.0 * xl * yl2 * p->nz * cs;
         if (dir == 0) {
-            const int fb[4][4] = {{zs2, zs2 + zl2, 0, ys1}, {zs2, zs2 + zl2, ys1 + yl1, p->ny},
-                                  {0, zs2, ys2, ys2 + yl2}, {zs2 + zl2, p->nz, ys2, ys2 + yl2}};
+            const int fb[4][6] = {{zs2, zs2 + zl2, kbA, kbB, 0, ys1},
+                                  {zs2, zs2 + zl2, kbA, kbB, ys1 + yl1, p->ny},
+                                  {0, zs2, kbA, kbB, ys2, ys2 + yl2},
+                                  {zs2 + zl2, p->nz, kbA, kbB, ys2, ys2 + yl2}};
             double fbytes;
-            p->pass[0][0] = fill(4, fb, kbA, kbB, 0, 0, &fbytes);
+            p->pass[0][0] = fill(4, fb, 0, 0, &fbytes);
             p->pass[0][1] = x;
             p->pass[0][2] = y;
             p->pass[0][3] = z;
@@ -428,14 +433,20 @@ void build_share_only(pf_plan *p) {
             for (int i = 0; i < 5; ++i) p->pass_names[0][i] = names[i], p->pass_bytes[0][i] = bytes[i];
             p->npass[0] = 5;
         } else {
-            const int fb[2][4] = {{zs2, zs2 + zl2, 0, ys2}, {zs2, zs2 + zl2, ys2 + yl2, p->ny}};
-            const int mb[1][4] = {{zs2, zs2 + zl2, ys1, ys1 + yl1}};
+            const int fb[2][6] = {{zs2, zs2 + zl2, kbA, kbB, 0, ys2}, {zs2, zs2 + zl2, kbA, kbB, ys2 + yl2, p->ny}};
+            // modes outside [xs, xs + xl) of the rank's X-pencil rows: whole column
+            // blocks below kbA and from kbB on, and the two partial blocks at the ends
+            const int lastA = kbB - 1;
+            const int mb[4][6] = {{zs2, zs2 + zl2, 0, kbA, ys1, ys1 + yl1},
+                                  {zs2, zs2 + zl2, kbA, kbA + 1, ys1, ys1 + yl1},
+                                  {zs2, zs2 + zl2, lastA > kbA ? lastA : kbA, lastA > kbA ? kbB : kbA, ys1, ys1 + yl1},
+                                  {zs2, zs2 + zl2, kbB, p->nkb, ys1, ys1 + yl1}};
             double fbytes, mbytes;
-            p->pass[1][0] = fill(2, fb, kbA, kbB, 0, 0, &fbytes);
+            p->pass[1][0] = fill(2, fb, 0, 0, &fbytes);
             p->pass[1][1] = box(0);
             p->pass[1][2] = z;
             p->pass[1][3] = y;
-            p->pass[1][4] = fill(1, mb, 0, p->nkb, xs, xs + xl, &mbytes);
+            p->pass[1][4] = fill(4, mb, xs, xs + xl, &mbytes);
             p->pass[1][5] = x;
             const char *names[] = {"share_fill", "share_insert_z", "share_z_c2c", "share_y_c2c", "share_mask_kx",
                                    "share_x_c2r"};

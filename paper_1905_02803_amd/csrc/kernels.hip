@@ -319,26 +319,36 @@ __global__ __launch_bounds__(256) void k_remap(RemapArgs a) {
     for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[d0 + i] = src[so + i];
 }
 
-// Zero workspace rows of the boxes of f (grid-stride over words).
+// Zero the workspace elements of the boxes of f: one thread per 16-byte chunk
+// of a 128-byte row (grid-stride), per-element stores where a chunk meets the
+// kept mode range.
 __global__ __launch_bounds__(256) void k_fill(FillArgs f) {
-    unsigned *__restrict__ w = reinterpret_cast<unsigned *>(f.w);
-    const int nkbr = f.kb1 - f.kb0;
-    const int rw = f.B * f.words;  // words per row
+    float4 *__restrict__ w = reinterpret_cast<float4 *>(f.w);
+    float *__restrict__ wf = reinterpret_cast<float *>(f.w);
+    constexpr int CH = 8;          // 16-byte chunks per row
+    const int epc = 4 / f.words;   // elements per chunk (2 FP32 complex, 1 FP64 complex)
     for (int b = 0; b < f.nbox; ++b) {
-        const int nz = f.z1[b] - f.z0[b], ny = f.y1[b] - f.y0[b];
-        const long long total = (long long)nz * nkbr * ny * rw;
+        const int nz = f.z1[b] - f.z0[b], nk = f.kb1[b] - f.kb0[b], ny = f.y1[b] - f.y0[b];
+        if (nz <= 0 || nk <= 0 || ny <= 0) continue;
+        const long long total = (long long)nz * nk * ny * CH;
         for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
              i += (long long)gridDim.x * blockDim.x) {
-            long long r = i / rw;
-            const int e = (int)(i - r * rw);
+            const int c = (int)(i & (CH - 1));
+            long long r = i >> 3;
             const int y = (int)(r % ny);
             r /= ny;
-            const int kb = (int)(r % nkbr);
-            const int z = (int)(r / nkbr);
-            const int kx = (f.kb0 + kb) * f.B + e / f.words;
-            if (kx >= f.keep0 && kx < f.keep1) continue;
-            const long long row = ((long long)(f.z0[b] + z) * f.nkb + f.kb0 + kb) * f.ny + f.y0[b] + y;
-            w[row * rw + e] = 0u;
+            const int kb = f.kb0[b] + (int)(r % nk);
+            const int z = f.z0[b] + (int)(r / nk);
+            const long long row = ((long long)z * f.nkb + kb) * f.ny + f.y0[b] + y;
+            const int kx0 = kb * f.B + c * epc;  // first mode of the chunk
+            const long long at = row * CH + c;
+            if (kx0 + epc <= f.keep0 || kx0 >= f.keep1) {
+                w[at] = make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                for (int e = 0; e < epc; ++e)
+                    if (kx0 + e < f.keep0 || kx0 + e >= f.keep1)
+                        for (int q = 0; q < f.words; ++q) wf[at * 4 + e * f.words + q] = 0.f;
+            }
         }
     }
 }
@@ -356,10 +366,12 @@ __global__ __launch_bounds__(256) void k_box(BoxArgs b) {
 }
 
 hipError_t launch_fill(const FillArgs &f, hipStream_t s) {
-    if (f.nbox < 0 || f.nbox > 4) return hipErrorInvalidValue;
+    if (f.nbox < 0 || f.nbox > 4 || f.B * f.words != 32) return hipErrorInvalidValue;
     long long total = 0;
-    for (int b = 0; b < f.nbox; ++b)
-        total += (long long)(f.z1[b] - f.z0[b]) * (f.kb1 - f.kb0) * (f.y1[b] - f.y0[b]) * f.B * f.words;
+    for (int b = 0; b < f.nbox; ++b) {
+        const long long nz = f.z1[b] - f.z0[b], nk = f.kb1[b] - f.kb0[b], ny = f.y1[b] - f.y0[b];
+        if (nz > 0 && nk > 0 && ny > 0) total = std::max(total, nz * nk * ny * 8);
+    }
     if (total <= 0) return hipSuccess;
     const long long want = (total + 255) / 256;
     const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);

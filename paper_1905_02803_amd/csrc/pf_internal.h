@@ -61,16 +61,16 @@ struct RemapArgs {
     long long nlines;
 };
 
-// Zero elements of the blocked workspace [z][kb][y][B] (B elements of `words`
-// 4-byte words per row): rows (z, kb, y) with kb in [kb0, kb1) and (z, y) in
-// one of nbox boxes [z0, z1) x [y0, y1); within a row, the elements whose
-// mode kx = kb B + c lies in [keep0, keep1) are left alone.
+// Zero elements of the blocked workspace [z][kb][y][B] (rows of 128 bytes):
+// rows (z, kb, y) of nbox boxes [z0, z1) x [kb0, kb1) x [y0, y1); within a
+// row, the elements whose mode kx = kb B + c lies in [keep0, keep1) are left
+// alone.  `words`: 4-byte words per element (2 for FP32 complex, 4 for FP64).
 struct FillArgs {
     void *w;
     int words, B, ny, nkb;
-    int kb0, kb1, keep0, keep1;
+    int keep0, keep1;
     int nbox;
-    int z0[4], z1[4], y0[4], y1[4];
+    int z0[4], z1[4], kb0[4], kb1[4], y0[4], y1[4];
 };
 
 // Copy a box between a strided global array (dimension 0 contiguous, element
