@@ -82,7 +82,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
     FETCH_SIZE / WRITE_SIZE are read per dispatch (KiB) and scaled by what the
     same counters read for the plain copy kernel k_copy, whose bytes are known.
     The transform's own kernels are assigned to passes in launch order
-    (forward X, Y, Z, backward Z, Y, X, repeated).
+    (forward X, Y, Z, backward Z, Y, X, repeated), over the leading run of
+    dispatches that repeats the first pair's six kernels: the plain 1024^3
+    plan; the matrix-core variants and the share-only leg come later.
     """
     import csv
 
@@ -96,6 +98,11 @@ def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
         rows = [r for r in read(path) if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) * 1024.0 for r in rows if "k_copy" in r["Kernel_Name"]]
         ours = [r for r in rows if "pf::k_" in r["Kernel_Name"] and "k_copy" not in r["Kernel_Name"]]
+        period = [r["Kernel_Name"] for r in ours[:len(PASS_ORDER)]]
+        run = 0
+        while run < len(ours) and ours[run]["Kernel_Name"] == period[run % len(PASS_ORDER)]:
+            run += 1
+        ours = ours[:run - run % len(PASS_ORDER)]
         copy_bytes = COPY_BYTES(n)
         factor = copy_bytes / statistics.mean(copies) if copies else None
         out[counter] = {"copy_bytes_per_dispatch": copy_bytes,
