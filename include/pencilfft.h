@@ -99,8 +99,13 @@ extern "C" {
  * is the ranks' X-pencils, the forward output their Z-pencils (and the reverse
  * for the backward transform).  The results equal the corresponding slices of
  * the 1 x 1 transform bit for bit.  stride1 selects the Table 1 storage orders
- * (Sec. 3.2, 3.3).  useeven pads exchange blocks to equal size (Sec. 3.4; not
- * built: pf_setup returns PF_EUNSUPPORTED).  inplace: in == out, and the
+ * (Sec. 3.2, 3.3).  useeven asks for exchange blocks padded to equal size
+ * (Sec. 3.4), a property of the message buffers of an all-to-all; on one GPU
+ * the exchanges are on-device permutations without message buffers, so the
+ * flag is accepted and changes no result and no layout.  third =
+ * PF_THIRD_EMPTY skips the transform along Z (Sec. 3.1): the forward output
+ * is the Z-pencil of the X-then-Y transformed data, z untransformed, and the
+ * backward transform starts from such an array.  inplace: in == out, and the
  * buffer must hold max(real, complex) bytes; real data sits unpadded at the
  * start of the buffer (Sec. 3.1 lists in- and out-of-place transforms).
  *

@@ -188,6 +188,19 @@ def stage_x_c2r(U: np.ndarray, nx: int) -> np.ndarray:
     return u
 
 
+def r2c3d_third_empty(u: np.ndarray) -> np.ndarray:
+    """Forward transform with an empty third transform (Sec. 3.1): the X stage
+    (R2C) then the Y stage (C2C, sign -1), z left untransformed -> [nz][ny][nxh]."""
+    nx = np.asarray(u).shape[2]
+    return stage_c2c(stage_x_r2c(u), nx, "y", -1)
+
+
+def c2r3d_third_empty(U: np.ndarray, nx: int) -> np.ndarray:
+    """Backward transform with an empty third transform: the Y stage (C2C,
+    sign +1) then the staged 1D C2R along X -> real [nz][ny][nx]."""
+    return stage_x_c2r(stage_c2c(U, nx, "y", +1), nx)
+
+
 def to_stride1(U: np.ndarray) -> np.ndarray:
     """[nz][ny][nxh] (Fortran XYZ) -> [nxh][ny][nz] (Fortran ZYX), Table 1."""
     return np.ascontiguousarray(np.asarray(U).transpose(2, 1, 0))

@@ -179,8 +179,6 @@ int check_impl(int nx, int ny, int nz, const pf_layout *l) {
 // Options accepted by pf_check but not built into the transform yet.
 int built_options(const pf_layout *l) {
     if (l->math != PF_PLAIN && l->precision != PF_F32) return PF_EUNSUPPORTED;
-    if (l->third != PF_THIRD_FFT) return PF_EUNSUPPORTED;
-    if (l->useeven) return PF_EUNSUPPORTED;
     if (l->share_only && l->inplace) return PF_EUNSUPPORTED;
     return PF_OK;
 }
@@ -506,9 +504,13 @@ void build_passes(pf_plan *p) {
         y.a.CB = (long long)p->nkb * (p->B >> y.a.tc_log2);
         y.a.tile_order = PF_TILE_ORDER_Y;
         y.blocks = c2c_grid(p, y);
-        // Z stage: tile (y, column block)
+        // Z stage: tile (y, column block); with the empty third transform
+        // (Sec. 3.1) a zero-stage plan, so the pass is the reorder alone
         PassDesc z;
-        set_c2c_common(z, p, p->fz, p->tw_off[2], sgn, p->B, p->lay.stride1 != 0);
+        const bool empty = p->lay.third == PF_THIRD_EMPTY;
+        FftSpec fz = p->fz;
+        if (empty) fz.nstages = 0;
+        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->lay.stride1 != 0 && !empty);
         z.a.A = p->ny;
         z.a.CB = (long long)p->nkb * (p->B >> z.a.tc_log2);
         const Side wsz = ws_side(p, p->B, zstride, z.a.tc_log2);

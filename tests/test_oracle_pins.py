@@ -114,6 +114,24 @@ def test_backward_vs_numpy_irfftn(shape):
     assert rel(oracle.c2r3d(U, nx), ref) < 1e-13
 
 
+@pytest.mark.parametrize("shape", SMALL + [(6, 20, 15)])
+def test_empty_third_transform_vs_numpy_2d(shape):
+    """Empty third transform (Sec. 3.1): every z plane gets the 2D R2C over (y, x)
+    and, backward, numpy's 2D inverse (C2C along y, C2R along x); z is untouched."""
+    nz, ny, nx = shape
+    u = synth.uniform(15, shape)
+    assert rel(oracle.r2c3d_third_empty(u), np.fft.rfftn(u, axes=(1, 2))) < 1e-13
+    U = synth.complex_half(16, (nz, ny, nx // 2 + 1))
+    ref = np.fft.irfftn(U, s=(ny, nx), axes=(1, 2)) * (nx * ny)
+    assert rel(oracle.c2r3d_third_empty(U, nx), ref) < 1e-13
+    # a z-dependent input stays z-dependent in the same way: no mixing across planes
+    v = np.zeros(shape)
+    v[nz // 2, 0, 0] = 1.0
+    V = oracle.r2c3d_third_empty(v)
+    assert np.max(np.abs(V[nz // 2] - 1.0)) < 1e-14
+    assert np.max(np.abs(np.delete(V, nz // 2, axis=0))) == 0.0
+
+
 @pytest.mark.parametrize("shape", SMALL)
 def test_delta_at_origin_gives_constant_spectrum(shape):
     u = np.zeros(shape)
