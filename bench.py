@@ -197,6 +197,55 @@ def cpu_baseline(n: int, u=None, forward_outputs=None):
     }, errs
 
 
+def layout_timings(pf, nx, ny, nz, args, dev, stream, u):
+    """Pair time and per-pass times of the layout variants off the measured one:
+    Z-pencil without STRIDE1, in-place, and the empty third transform."""
+    import torch
+
+    out = {}
+    for name, lay in (("stride1_undefined", pf.Layout(stride1=0)),
+                      ("inplace", pf.Layout(inplace=1)),
+                      ("third_empty", pf.Layout(third=pf.PF_THIRD_EMPTY))):
+        plan = pf.Plan(nx, ny, nz, lay)
+        nb = max(nx * ny * nz * 4, (nx // 2 + 1) * ny * nz * 8)
+        if lay.inplace:
+            buf = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+
+            def step():
+                buf[: u.numel()].copy_(u.reshape(-1))  # the input is consumed in place
+                pf.pf_ftran_r2c(plan.handle, buf.data_ptr(), buf.data_ptr(), stream.cuda_stream)
+                pf.pf_btran_c2r(plan.handle, buf.data_ptr(), buf.data_ptr(), stream.cuda_stream)
+        else:
+            U = plan.empty_complex(dev)
+            r = plan.empty_real(dev)
+
+            def step():
+                plan.ftran(u, U)
+                plan.btran(U, r)
+        for _ in range(args.warmup):
+            step()
+        plan.set_timing(True)
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s0.record(stream)
+        for _ in range(args.steps):
+            step()
+        s1.record(stream)
+        torch.cuda.synchronize()
+        passes = {}
+        for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD):
+            for i in range(plan.num_passes(d)):
+                tot, cnt = plan.get_timing(d, i)
+                passes[plan.pass_name(d, i)] = tot / max(cnt, 1)
+        plan.set_timing(False)
+        out[name] = {"ms_per_step": s0.elapsed_time(s1) / args.steps, "pass_ms": passes}
+        if lay.inplace:
+            out[name]["note"] = "includes one device copy of the input per step (the input is overwritten)"
+        plan.destroy()
+    return out
+
+
 def share_only_timing(pf, nx, ny, nz, args, dev, stream, m2=8, r2=3):
     """One rank's share of the grid on a 1 x m2 slab grid (share-only plan): per-pass times."""
     import torch
@@ -339,6 +388,7 @@ def main():
             fwd_host[name] = Um.cpu().numpy()
         del Um
         pm.destroy()
+    layouts = layout_timings(pf, nx, ny, nz, args, dev, stream, u)
     share = share_only_timing(pf, nx, ny, nz, args, dev, stream)
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
@@ -387,6 +437,7 @@ def main():
         },
         "passes": passes,
         "share_only": share,
+        "layouts": layouts,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
     }

@@ -183,11 +183,10 @@ int built_options(const pf_layout *l) {
     return PF_OK;
 }
 
-// vec_ok: both sides are either the padded workspace (whole 16-column blocks,
-// 16-byte aligned rows) or whole contiguous lines -- what the power-of-two
-// kernel's 16-byte column-pair accesses need.
-void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc,
-                    bool vec_ok) {
+// The power-of-two kernel serves every side: the padded workspace (whole
+// 16-column blocks, 16-byte aligned rows), contiguous lines, and unaligned
+// rows (Side::v8).
+void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc) {
     d.dir = dir;
     d.prec = p->lay.precision;
     PassArgs &a = d.a;
@@ -195,7 +194,7 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
     a.fft = fs;
     a.tw = (const char *)p->tw_dev + twoff;
     a.C = p->nxh;
-    if (vec_ok && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
+    if (pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
         // compile-time radix plan, persistent blocks (grid set once the tile count is known)
         d.kind = pf::PASS_C2C_P2;
         a.math = pf::p2_has_mfma(fs.n) ? p->lay.math : 0;
@@ -226,12 +225,19 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
 #ifndef PF_TILE_ORDER_Y
 #define PF_TILE_ORDER_Y 0
 #endif
+#ifndef PF_XCD_UROWS
+#define PF_XCD_UROWS 1
+#endif
 
 unsigned c2c_grid(const pf_plan *p, PassDesc &d) {
     const long long tiles = d.a.A * d.a.CB;
     if (d.kind != pf::PASS_C2C_P2) return (unsigned)tiles;
-    d.a.inp = (d.a.in_s.sp == 1 && d.a.in_s.sc != 1) ? 1 : 0;
-    d.a.outp = (d.a.out_s.sp == 1 && d.a.out_s.sc != 1) ? 1 : 0;
+    // side kinds: 1 lines, 0 aligned rows, 2 rows read / written a column at a time
+    d.a.inp = (d.a.in_s.sp == 1 && d.a.in_s.sc != 1) ? 1 : d.a.in_s.v8 ? 2 : 0;
+    d.a.outp = (d.a.out_s.sp == 1 && d.a.out_s.sc != 1) ? 1 : d.a.out_s.v8 ? 2 : 0;
+    // unaligned rows: neighbouring column-block tiles read / write the two
+    // halves of shared cache lines; keep them on one XCD (one L2)
+    d.a.xcd = d.a.outp == 2 || d.a.inp == 2 ? PF_XCD_UROWS : 0;
     const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(d);
     return (unsigned)(tiles < resident ? tiles : resident);
 }
@@ -245,6 +251,7 @@ Side ws_side(const pf_plan *p, long long sa, long long sp, int tc_log2) {
     s.sc = 1;
     s.sp = sp;
     s.cpb = p->B >> tc_log2;
+    s.v8 = 0;
     return s;
 }
 
@@ -262,6 +269,10 @@ Side user_side(const pf_plan *p, long long CB) {
     }
     s.sblk = 0;
     s.cpb = CB;
+    // [nz][ny][nxh] rows of nxh modes: neither 16-byte aligned nor whole column
+    // pairs in general, so the power-of-two kernel reads / writes them one column
+    // (8 or 16 bytes) at a time
+    s.v8 = p->lay.stride1 ? 0 : 1;
     return s;
 }
 
@@ -497,7 +508,7 @@ void build_passes(pf_plan *p) {
         }
         // Y stage: in place on the workspace, tile (z, column block)
         PassDesc y;
-        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B, true);
+        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B);
         y.a.in_s = ws_side(p, zstride, p->B, y.a.tc_log2);
         y.a.out_s = y.a.in_s;
         y.a.A = p->nz;
@@ -510,14 +521,18 @@ void build_passes(pf_plan *p) {
         const bool empty = p->lay.third == PF_THIRD_EMPTY;
         FftSpec fz = p->fz;
         if (empty) fz.nstages = 0;
-        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->lay.stride1 != 0 && !empty);
+        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B);
+        if (empty && z.kind == pf::PASS_C2C_P2) z.a.math = 3;  // the power-of-two kernel's reorder-only form
         z.a.A = p->ny;
         z.a.CB = (long long)p->nkb * (p->B >> z.a.tc_log2);
         const Side wsz = ws_side(p, p->B, zstride, z.a.tc_log2);
         const Side usr = user_side(p, z.a.CB);
         z.a.in_s = dir == 0 ? wsz : usr;
         z.a.out_s = dir == 0 ? usr : wsz;
-        z.a.tile_order = dir == 0 ? PF_TILE_ORDER_FZ : PF_TILE_ORDER_BZ;
+        // a backward Z pass reading the unaligned [nz][ny][nxh] rows does best
+        // walking column blocks first, so that neighbouring tiles (on one XCD)
+        // share the cache lines the rows straddle
+        z.a.tile_order = dir == 0 ? PF_TILE_ORDER_FZ : (p->lay.stride1 ? PF_TILE_ORDER_BZ : 0);
         z.blocks = c2c_grid(p, z);
 
         const double cbytes = M * 2 * rs;

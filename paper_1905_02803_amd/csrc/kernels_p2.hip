@@ -43,10 +43,25 @@ enum : unsigned {
     LD_R2C = 64,           // forward X pass: loads of real lines
     LD_C2R = 128,          // backward X pass: loads from the workspace
     LD_C2C_POINTS = 256,   // Y / Z pass: 8-byte loads from a point-major input side
+    ST_C2C_UROWS = 512,    // Z pass: 8-byte stores to rows that are not 16-byte aligned
 };
 template <unsigned BIT>
 constexpr bool streamed() {
     return (PF_STREAM_MASK & BIT) != 0;
+}
+
+// XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round-robin
+// (block b on XCD b % 8); with it on, each full round of G = gridDim.x tiles
+// is permuted so that XCD x works on the G / 8 consecutive tiles x G/8 ..
+// (x+1) G/8 - 1.  Neighbouring tiles then share one L2, which merges the
+// partial cache lines they both write when rows are not line aligned.  The
+// last, partial round keeps the identity order.
+__device__ __forceinline__ int xcd_tile(int t, int ntiles, int on) {
+    const int G = (int)gridDim.x;
+    if (!on || (G & 7)) return t;
+    const int k = t / G, b = t - k * G;
+    if ((k + 1) * G > ntiles) return t;
+    return k * G + (b & 7) * (G >> 3) + (b >> 3);
 }
 
 // threadIdx.x passed through an empty asm statement: lane indices and LDS
@@ -342,9 +357,27 @@ __device__ __forceinline__ void p2_stage1_mfma(float4 *buf, const cx<float> *tws
     __syncthreads();
 }
 
+// Trade values between the lanes of points q (even) and q + 1 (odd), which are
+// cp_lanes apart in the wave, so that the row-major layout (v0, v1) = (column
+// 2 cp, column 2 cp + 1) of the lane's own point and the column-major layout
+// (v0, v1) = (row q & ~1, row q | 1) of the lane's own column are exchanged;
+// the map is its own inverse.  Even lane: keeps v0, swaps v1; odd lane: keeps
+// v1, swaps v0.
+__device__ __forceinline__ void pair_swap(cx<float> (&v0)[16], cx<float> (&v1)[16], bool odd, int cp_lanes) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const float2 a0 = v0[m], a1 = v1[m];
+        const float2 give = make_float2(odd ? a0.x : a1.x, odd ? a0.y : a1.y);
+        const float2 got = make_float2(__shfl_xor(give.x, cp_lanes), __shfl_xor(give.y, cp_lanes));
+        v0[m] = make_float2(odd ? got.x : a0.x, odd ? got.y : a0.y);
+        v1[m] = make_float2(odd ? a1.x : got.x, odd ? a1.y : got.y);
+    }
+}
+
 // Each thread owns a pair of adjacent columns (2 cp, 2 cp + 1) and 16 points
-// q + (N/16) m of both.  INP / OUTP: 1 if that side's points are contiguous
-// (lines), 0 if its columns are contiguous (rows, loaded 16 bytes at a time).
+// q + (N/16) m of both.  INP / OUTP, the kind of that side: 1 if its points
+// are contiguous (lines), 0 if its columns are (rows, 16-byte column-pair
+// accesses), 2 for rows that are not 16-byte aligned (8-byte accesses).
 template <int N, int TC, int DIR, int INP, int OUTP, int MT>
 __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     constexpr int T = N / 16;
@@ -358,9 +391,10 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     const int tid = threadIdx.x;
     const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
     for (int i = tid; i < N - 1; i += NT) twl[i] = tw[i];
-    typedef typename MfmaSplit<MT == 0 ? 1 : MT>::vec avec;
-    avec *atab = reinterpret_cast<avec *>(twl + N);  // matrix-core A operands (MT != 0)
-    if constexpr (MT != 0) {
+    constexpr bool MC = MT == 1 || MT == 2;  // middle stage on the matrix cores
+    typedef typename MfmaSplit<MC ? MT : 1>::vec avec;
+    avec *atab = reinterpret_cast<avec *>(twl + N);  // matrix-core A operands (MC)
+    if constexpr (MC) {
         if (tid < 64) {
             MfmaDft16<DIR, MT> d0;
             d0.init(tid);
@@ -388,11 +422,11 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     };
     auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
         const int tv = opaque_tid();
-        const int cp_in = INP ? tv / T : tv % CP;
-        const int q_in = INP ? tv % T : tv / CP;
+        const int cp_in = INP == 1 ? tv / T : tv % CP;
+        const int q_in = INP == 1 ? tv % T : tv / CP;
         int ncol;
         const long long b = side_addr(a.in_s, t, cp_in, q_in, ncol);
-        if (INP) {  // two lines, 8 bytes per lane each
+        if constexpr (INP == 1) {  // two lines, 8 bytes per lane each
             if (2 * cp_in < ncol) {
 #pragma unroll
                 for (int m = 0; m < 16; ++m) d0[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + m * in_step);
@@ -400,6 +434,22 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
             if (2 * cp_in + 1 < ncol) {
 #pragma unroll
                 for (int m = 0; m < 16; ++m) d1[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + a.in_s.sc + m * in_step);
+            }
+        } else if constexpr (INP == 2) {
+            // rows not 16-byte aligned: 8-byte column accesses, each instruction
+            // covering 16 adjacent columns of one row -- the lane of point q even
+            // takes column 2 cp of rows q and q + 1, its partner (q odd, CP lanes
+            // away) column 2 cp + 1 of the same rows; swapped into place in the
+            // tile loop (pair_swap)
+            const bool odd = q_in & 1;
+            const int col = 2 * cp_in + (odd ? 1 : 0);
+            if (col < ncol) {
+                const long long e = b + (odd ? a.in_s.sc - a.in_s.sp : 0);  // column col, row q & ~1
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    d0[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + m * in_step);
+                    d1[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + a.in_s.sp + m * in_step);
+                }
             }
         } else if (2 * cp_in < ncol) {  // rows: both columns in one 16-byte load
             // a partially valid pair only occurs on a side padded to whole 16-column blocks
@@ -414,16 +464,16 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
 
     int t = blockIdx.x;
     cx<float> p0[16], p1[16];
-    if (t < ntiles) load(p0, p1, t);
+    if (t < ntiles) load(p0, p1, xcd_tile(t, ntiles, a.xcd));
     __syncthreads();  // twiddle table in LDS
     for (; t < ntiles; t += gridDim.x) {
         const int tv = opaque_tid();
-        const int cp_in = INP ? tv / T : tv % CP;
-        const int q_in = INP ? tv % T : tv / CP;
+        const int cp_in = INP == 1 ? tv / T : tv % CP;
+        const int q_in = INP == 1 ? tv % T : tv / CP;
         const int cp_mid = tv % CP;
         const int q_mid = tv / CP;
-        const int cp_out = OUTP ? tv / T : tv % CP;
-        const int q_out = OUTP ? tv % T : tv / CP;
+        const int cp_out = OUTP == 1 ? tv / T : tv % CP;
+        const int q_out = OUTP == 1 ? tv % T : tv / CP;
         cx<float> v0[16], v1[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
@@ -431,16 +481,24 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
             v1[m] = p1[m];
         }
         const int tn = t + gridDim.x;
-        if (tn < ntiles) load(p0, p1, tn);
+        if (tn < ntiles) load(p0, p1, xcd_tile(tn, ntiles, a.xcd));
+        if constexpr (INP == 2) pair_swap(v0, v1, q_in & 1, CP);
 
-        // stage 0: radix 16 on x[q + T r], outputs to points 16 q + r
-        Dft<float, 16, DIR>::run(v0);
-        Dft<float, 16, DIR>::run(v1);
+        if constexpr (MT == 3) {  // no transform (the empty third transform): points keep their index
 #pragma unroll
-        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
-        __syncthreads();
+            for (int m = 0; m < 16; ++m) buf[p2_slot<TC>(q_in + T * m, cp_in)] = pack2(v0[m], v1[m]);
+            __syncthreads();
+        } else {
+            // stage 0: radix 16 on x[q + T r], outputs to points 16 q + r
+            Dft<float, 16, DIR>::run(v0);
+            Dft<float, 16, DIR>::run(v1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
+            __syncthreads();
+        }
 
-        if constexpr (S == 3 && MT != 0) {  // stage 1 on the matrix cores
+        if constexpr (MT == 3) {
+        } else if constexpr (S == 3 && MC) {  // stage 1 on the matrix cores
             p2_stage1_mfma<N, TC, DIR, MT>(buf, twl + p2_twoff(N, 1), atab, tv);
         } else if constexpr (S == 3) {  // stage 1: radix 16, NS = 16
 #pragma unroll
@@ -465,11 +523,11 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
             v0[m] = make_float2(x.x, x.y);
             v1[m] = make_float2(x.z, x.w);
         }
-        p2_butterflies2<N, RL, NSL, DIR>(v0, v1, q_out, twl + p2_twoff(N, S - 1));
+        if constexpr (MT != 3) p2_butterflies2<N, RL, NSL, DIR>(v0, v1, q_out, twl + p2_twoff(N, S - 1));
         {
             int ncol;
-            const long long b = side_addr(a.out_s, t, cp_out, q_out, ncol);
-            if (OUTP) {
+            const long long b = side_addr(a.out_s, xcd_tile(t, ntiles, a.xcd), cp_out, q_out, ncol);
+            if constexpr (OUTP == 1) {
                 if (2 * cp_out < ncol) {
 #pragma unroll
                     for (int m = 0; m < 16; ++m) gst<streamed<ST_C2C_POINTS>()>(out + b + m * out_step, v0[m]);
@@ -478,10 +536,22 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
 #pragma unroll
                     for (int m = 0; m < 16; ++m) gst<streamed<ST_C2C_POINTS>()>(out + b + a.out_s.sc + m * out_step, v1[m]);
                 }
+            } else if constexpr (OUTP == 2) {  // rows not 16-byte aligned: as the loads, in reverse
+                const bool odd = q_out & 1;
+                pair_swap(v0, v1, odd, CP);
+                const int col = 2 * cp_out + (odd ? 1 : 0);
+                if (col < ncol) {
+                    const long long e = b + (odd ? a.out_s.sc - a.out_s.sp : 0);
+#pragma unroll
+                    for (int m = 0; m < 16; ++m) {
+                        gst<streamed<ST_C2C_UROWS>()>(out + e + m * out_step, v0[m]);
+                        gst<streamed<ST_C2C_UROWS>()>(out + e + a.out_s.sp + m * out_step, v1[m]);
+                    }
+                }
             } else if (2 * cp_out < ncol) {
 #pragma unroll
                 for (int m = 0; m < 16; ++m)
-                    gst<streamed<INP ? ST_C2C_ROWS_INP : ST_C2C_ROWS>()>(reinterpret_cast<float4 *>(out + b + m * out_step),
+                    gst<streamed<INP == 1 ? ST_C2C_ROWS_INP : ST_C2C_ROWS>()>(reinterpret_cast<float4 *>(out + b + m * out_step),
                                                                    pack2(v0[m], v1[m]));
             }
         }
@@ -862,7 +932,7 @@ hipError_t p2x_prepare(int nx) {
 int p2_tc(int n) { return n <= 1024 ? 16 : 16384 / n; }
 
 size_t p2_lds_bytes(int n, int math) {
-    return ((size_t)n * p2_tc(n) + n) * sizeof(float2) + (math ? kMfmaTableBytes : 0);
+    return ((size_t)n * p2_tc(n) + n) * sizeof(float2) + (math == 1 || math == 2 ? kMfmaTableBytes : 0);
 }
 
 bool p2_supported(int n, int prec) {
@@ -874,36 +944,46 @@ static const void *p2_kernel() {
     return reinterpret_cast<const void *>(&k_c2c_p2<N, TC, DIR, INP, OUTP, MT>);
 }
 
+template <int N, int TC, int DIR, int MT>
+static const void *p2_pick_io_dir(int inp, int outp) {
+    if (inp == 0 && outp == 0) return p2_kernel<N, TC, DIR, 0, 0, MT>();
+    if (inp == 0 && outp == 1) return p2_kernel<N, TC, DIR, 0, 1, MT>();
+    if (inp == 1 && outp == 0) return p2_kernel<N, TC, DIR, 1, 0, MT>();
+    if (inp == 0 && outp == 2) return p2_kernel<N, TC, DIR, 0, 2, MT>();
+    if (inp == 2 && outp == 0) return p2_kernel<N, TC, DIR, 2, 0, MT>();
+    return nullptr;
+}
+
 template <int N, int TC, int MT>
 static const void *p2_pick_io(int dir, int inp, int outp) {
-    if (dir < 0) {
-        if (!inp && !outp) return p2_kernel<N, TC, -1, 0, 0, MT>();
-        if (!inp && outp) return p2_kernel<N, TC, -1, 0, 1, MT>();
-        if (inp && !outp) return p2_kernel<N, TC, -1, 1, 0, MT>();
-    } else {
-        if (!inp && !outp) return p2_kernel<N, TC, 1, 0, 0, MT>();
-        if (!inp && outp) return p2_kernel<N, TC, 1, 0, 1, MT>();
-        if (inp && !outp) return p2_kernel<N, TC, 1, 1, 0, MT>();
-    }
-    return nullptr;
+    return dir < 0 ? p2_pick_io_dir<N, TC, -1, MT>(inp, outp) : p2_pick_io_dir<N, TC, 1, MT>(inp, outp);
 }
 
 // kernel symbol for (n, dir, inp, outp, math); nullptr if not built.  The
 // matrix-core variants exist for the 16-column tiles with a middle radix-16
 // stage: n = 512 and 1024.
+// mt: 0 plain, 1 / 2 matrix-core middle stage (512 and 1024 only), 3 no transform
 static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
     switch (n) {
-        case 256: return mt == 0 ? p2_pick_io<256, 16, 0>(dir, inp, outp) : nullptr;
+        case 256:
+            return mt == 0 ? p2_pick_io<256, 16, 0>(dir, inp, outp)
+                 : mt == 3 ? p2_pick_io<256, 16, 3>(dir, inp, outp) : nullptr;
         case 512:
             return mt == 0 ? p2_pick_io<512, 16, 0>(dir, inp, outp)
                  : mt == 1 ? p2_pick_io<512, 16, 1>(dir, inp, outp)
-                           : p2_pick_io<512, 16, 2>(dir, inp, outp);
+                 : mt == 2 ? p2_pick_io<512, 16, 2>(dir, inp, outp)
+                           : p2_pick_io<512, 16, 3>(dir, inp, outp);
         case 1024:
             return mt == 0 ? p2_pick_io<1024, 16, 0>(dir, inp, outp)
                  : mt == 1 ? p2_pick_io<1024, 16, 1>(dir, inp, outp)
-                           : p2_pick_io<1024, 16, 2>(dir, inp, outp);
-        case 2048: return mt == 0 ? p2_pick_io<2048, 8, 0>(dir, inp, outp) : nullptr;
-        case 4096: return mt == 0 ? p2_pick_io<4096, 4, 0>(dir, inp, outp) : nullptr;
+                 : mt == 2 ? p2_pick_io<1024, 16, 2>(dir, inp, outp)
+                           : p2_pick_io<1024, 16, 3>(dir, inp, outp);
+        case 2048:
+            return mt == 0 ? p2_pick_io<2048, 8, 0>(dir, inp, outp)
+                 : mt == 3 ? p2_pick_io<2048, 8, 3>(dir, inp, outp) : nullptr;
+        case 4096:
+            return mt == 0 ? p2_pick_io<4096, 4, 0>(dir, inp, outp)
+                 : mt == 3 ? p2_pick_io<4096, 4, 3>(dir, inp, outp) : nullptr;
         default: return nullptr;
     }
 }
@@ -919,9 +999,10 @@ bool p2_has_mfma(int n) { return n == 512 || n == 1024; }
 hipError_t p2_prepare(int n) {
     hipError_t e = hipSuccess;
     for (int dir : {-1, 1})
-        for (int io = 0; io < 9; ++io) {
-            const int mt = io / 3;
-            const void *k = p2_pick(n, dir, io % 3 == 2, io % 3 == 1, mt);
+        for (int io = 0; io < 20; ++io) {
+            const int mt = io / 5, k5 = io % 5;  // (inp, outp): (0,0) (0,1) (1,0) (0,2) (2,0)
+            const int inp = k5 == 2 ? 1 : k5 == 4 ? 2 : 0, outp = k5 == 1 ? 1 : k5 == 3 ? 2 : 0;
+            const void *k = p2_pick(n, dir, inp, outp, mt);
             if (!k) continue;
             hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2_lds_bytes(n, mt));
             if (r != hipSuccess && e == hipSuccess) e = r;

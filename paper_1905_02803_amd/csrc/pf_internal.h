@@ -28,6 +28,7 @@ struct FftSpec {
 // Blocked workspace sides use cpb = B / TC; linear sides use cpb = CB, sblk = 0.
 struct Side {
     long long sa, sblk, sc, sp, cpb;
+    int v8;  // power-of-two C2C pass, row side: rows not 16-byte aligned, 8-byte column accesses
 };
 
 enum PassKind {
@@ -96,9 +97,11 @@ struct PassArgs {
     int C;         // valid columns (C2C passes)
     long long A, CB;  // C2C tile grid: A * CB tiles
     Side in_s, out_s;
-    int inp, outp;  // power-of-two C2C pass: 1 if that side's points are contiguous
-    int math;       // power-of-two passes: 0 plain, 1 / 2 middle radix-16 stage on MFMA (FP16 / BF16 hi+lo)
+    int inp, outp;  // power-of-two C2C pass, kind of side: 1 lines, 0 aligned rows, 2 unaligned rows
+    int math;       // power-of-two passes: 0 plain, 1 / 2 middle radix-16 stage on MFMA (FP16 / BF16 hi+lo),
+                    // 3 (C2C pass) no transform: the reorder alone
     int tile_order; // power-of-two C2C pass: 0 tile t = (t / CB, t % CB), 1 tile t = (t % A, t / A)
+    int xcd;        // power-of-two C2C pass: 1 to give each XCD runs of consecutive tiles
     // X passes: real lines (y, z) flattened as g = z * ny + y; line g's spectrum
     // is workspace row (z nkb + kb) ypitch + y0 + y of column block kb
     long long lines;

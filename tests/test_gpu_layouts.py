@@ -25,7 +25,8 @@ def rel(a, b):
     return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
 
 
-SHAPES = [(12, 10, 16), (9, 7, 15), (16, 32, 1024), (32, 64, 512), (5, 256, 48)]
+SHAPES = [(12, 10, 16), (9, 7, 15), (16, 32, 1024), (32, 64, 512), (5, 256, 48),
+          (256, 12, 36), (1024, 6, 40), (2048, 3, 10)]  # the last three: power-of-two Z, reorder-only kernel
 
 
 @pytest.mark.parametrize("stride1", [1, 0])
