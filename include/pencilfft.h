@@ -267,6 +267,70 @@ int pf_set_timing(pf_plan *p, int enable);
  */
 int pf_get_timing(pf_plan *p, int dir, int pass, double *total_ms, long long *count);
 
+/* ---- batched transforms ------------------------------------------------ */
+
+/*
+ * Many independent 3D transforms of different sizes run together (the same
+ * method per transform, Sec. 2; the paper's "any grid dimensions", Sec. 3.1).
+ * Each transform uses the generic kernels (runtime mixed-radix plans); a
+ * fused pass is ONE kernel launch over the tiles of every transform's pass
+ * (a device table maps each workgroup to its transform), so a direction is
+ * three launches whatever the count.
+ *
+ * pf_tune: per axis (x, y, z) a radix order (0: radix 16 first, then 8, 4, 2,
+ * 3, 5, 7; 1: 8, 4, 2, 3, 5, 7; 2: 4, 2, 3, 5, 7; 3: 3, 5, 7 first, then 16,
+ * 8, 4, 2) and a tile width (0: the default, else at most that many line
+ * pairs per X tile or columns per Y / Z tile).  Chosen per transform by the
+ * package's autotuner; NULL means defaults.
+ */
+typedef struct pf_tune {
+    int radix_order[3];
+    int tile[3];
+} pf_tune;
+
+typedef struct pf_batch pf_batch;
+
+#define PF_BATCH_SERIAL 0  /* transform after transform, three launches each   */
+#define PF_BATCH_FUSED 1   /* one launch per pass over all transforms (default) */
+#define PF_BATCH_GRAPH 2   /* flag: replay the direction from a captured hipGraph */
+
+/*
+ * dims: count triples (nx, ny, nz).  l: precision, stride1 and third as for
+ * pf_setup; m1 = m2 = 1, out-of-place, plain math only (else
+ * PF_EUNSUPPORTED).  tune: NULL or count entries.  The batch owns its
+ * plans, tables and workspace.  Errors as pf_setup, for the first transform
+ * that fails.
+ */
+int pf_batch_setup(int count, const int *dims, const pf_layout *l, const pf_tune *tune, pf_batch **out);
+
+/*
+ * The user arrays of a batch are two device buffers: REAL holds every
+ * transform's X-pencil [nz][ny][nx] and COMPLEX every transform's Z-pencil
+ * (layout as pf_setup's), each at a 256-byte aligned offset.  which = 0:
+ * real, 1: complex.  pf_batch_offset returns transform i's byte offset
+ * ((size_t)-1 on bad arguments), pf_batch_bytes the buffer's total size.
+ */
+size_t pf_batch_offset(const pf_batch *b, int which, int i);
+size_t pf_batch_bytes(const pf_batch *b, int which);
+
+/*
+ * mode: PF_BATCH_SERIAL or PF_BATCH_FUSED, optionally | PF_BATCH_GRAPH: the
+ * first call of a direction with given buffers captures its launches into a
+ * hipGraph (on a stream of the batch's own) and every call replays it on the
+ * caller's stream; new buffers are captured again (after the caller's stream
+ * has drained the old graph).  Returns PF_EINVAL for other values.
+ */
+int pf_batch_set_mode(pf_batch *b, int mode);
+
+/*
+ * Forward: in = REAL buffer (read only), out = COMPLEX buffer; backward the
+ * reverse.  Both 256-byte aligned (PF_EALIGN), distinct (PF_EALIAS).
+ * Asynchronous on `stream`; one batch must not run on two streams at once.
+ */
+int pf_batch_ftran_r2c(pf_batch *b, const void *in, void *out, void *stream);
+int pf_batch_btran_c2r(pf_batch *b, const void *in, void *out, void *stream);
+int pf_batch_destroy(pf_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,11 +35,14 @@ PF_PLAIN, PF_MFMA_FP16X2, PF_MFMA_BF16X2 = 0, 1, 2
 PF_THIRD_FFT, PF_THIRD_EMPTY = 0, 1
 PF_PENCIL_X, PF_PENCIL_Y, PF_PENCIL_Z = 0, 1, 2
 PF_DIR_FORWARD, PF_DIR_BACKWARD = 0, 1
+PF_BATCH_SERIAL, PF_BATCH_FUSED, PF_BATCH_GRAPH = 0, 1, 2
 
 EXPORTED = (
     "pf_layout_init", "pf_check", "pf_query_dims", "pf_setup", "pf_get_dims", "pf_workspace_bytes",
     "pf_set_workspace", "pf_ftran_r2c", "pf_btran_c2r", "pf_destroy", "pf_strerror", "pf_num_passes",
     "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
+    "pf_batch_setup", "pf_batch_offset", "pf_batch_bytes", "pf_batch_set_mode", "pf_batch_ftran_r2c",
+    "pf_batch_btran_c2r", "pf_batch_destroy",
 )
 
 
@@ -52,6 +55,10 @@ class PfError(RuntimeError):
 class pf_layout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int) for name in (
         "m1", "m2", "stride1", "useeven", "precision", "math", "inplace", "third", "share_only", "r1", "r2")]
+
+
+class pf_tune(ctypes.Structure):
+    _fields_ = [("radix_order", ctypes.c_int * 3), ("tile", ctypes.c_int * 3)]
 
 
 @dataclass
@@ -106,6 +113,13 @@ def lib():
             "pf_set_timing": (i, [vp, i]),
             "pf_copy": (i, [vp, vp, sz, vp]),
             "pf_get_timing": (i, [vp, i, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+            "pf_batch_setup": (i, [i, ip, lp, ctypes.POINTER(pf_tune), ctypes.POINTER(vp)]),
+            "pf_batch_offset": (sz, [vp, i, i]),
+            "pf_batch_bytes": (sz, [vp, i]),
+            "pf_batch_set_mode": (i, [vp, i]),
+            "pf_batch_ftran_r2c": (i, [vp, vp, vp, vp]),
+            "pf_batch_btran_c2r": (i, [vp, vp, vp, vp]),
+            "pf_batch_destroy": (i, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -334,6 +348,119 @@ class Plan:
     def destroy(self) -> None:
         if getattr(self, "handle", None):
             pf_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def pf_batch_setup(dims, layout: Layout | None = None, tune=None) -> int:
+    """dims: sequence of (nx, ny, nz); tune: None or a sequence of ((rx, ry, rz), (tx, ty, tz)) per transform."""
+    n = len(dims)
+    flat = (ctypes.c_int * (3 * n))(*[int(v) for d in dims for v in d])
+    c = (layout or Layout()).c()
+    tp = None
+    if tune is not None:
+        arr = (pf_tune * n)()
+        for i, (ro, tl) in enumerate(tune):
+            arr[i].radix_order[:] = [int(v) for v in ro]
+            arr[i].tile[:] = [int(v) for v in tl]
+        tp = arr
+    h = ctypes.c_void_p()
+    _raise(lib().pf_batch_setup(n, flat, ctypes.byref(c), tp, ctypes.byref(h)), "pf_batch_setup")
+    return h.value
+
+
+def pf_batch_offset(h, which: int, i: int) -> int:
+    v = lib().pf_batch_offset(h, which, i)
+    if v == ctypes.c_size_t(-1).value:
+        raise PfError(PF_EINVAL, "pf_batch_offset")
+    return v
+
+
+def pf_batch_bytes(h, which: int) -> int:
+    return lib().pf_batch_bytes(h, which)
+
+
+def pf_batch_set_mode(h, mode: int) -> None:
+    _raise(lib().pf_batch_set_mode(h, mode), "pf_batch_set_mode")
+
+
+def pf_batch_ftran_r2c(h, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _raise(lib().pf_batch_ftran_r2c(h, in_ptr, out_ptr, stream), "pf_batch_ftran_r2c")
+
+
+def pf_batch_btran_c2r(h, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _raise(lib().pf_batch_btran_c2r(h, in_ptr, out_ptr, stream), "pf_batch_btran_c2r")
+
+
+def pf_batch_destroy(h) -> None:
+    _raise(lib().pf_batch_destroy(h), "pf_batch_destroy")
+
+
+class Batch:
+    """Many 3D transforms of different sizes; user arrays are two flat device buffers (REAL, COMPLEX)."""
+
+    def __init__(self, dims, layout: Layout | None = None, tune=None, mode: int = PF_BATCH_FUSED):
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.layout = layout or Layout()
+        self.handle = pf_batch_setup(self.dims, self.layout, tune)
+        self.set_mode(mode)
+
+    def set_mode(self, mode: int) -> None:
+        pf_batch_set_mode(self.handle, mode)
+        self.mode = mode
+
+    @property
+    def real_dtype(self):
+        import torch
+
+        return torch.float64 if self.layout.precision == PF_F64 else torch.float32
+
+    @property
+    def complex_dtype(self):
+        import torch
+
+        return torch.complex128 if self.layout.precision == PF_F64 else torch.complex64
+
+    def empty(self, which: int, device="cuda"):
+        """A flat byte-sized buffer for REAL (0) or COMPLEX (1) data, 256-byte aligned by torch's allocator."""
+        import torch
+
+        return torch.empty(pf_batch_bytes(self.handle, which), dtype=torch.uint8, device=device)
+
+    def view(self, buf, which: int, i: int):
+        """Transform i's array inside a batch buffer: [nz][ny][nx] real or its Z-pencil complex."""
+        nx, ny, nz = self.dims[i]
+        off = pf_batch_offset(self.handle, which, i)
+        if which == 0:
+            shape, dt = (nz, ny, nx), self.real_dtype
+        else:
+            nxh = nx // 2 + 1
+            shape, dt = ((nxh, ny, nz) if self.layout.stride1 else (nz, ny, nxh)), self.complex_dtype
+        n = shape[0] * shape[1] * shape[2] * dt.itemsize
+        return buf[off:off + n].view(dt).view(shape)
+
+    def ftran(self, real_buf, complex_buf, stream=None):
+        pf_batch_ftran_r2c(self.handle, real_buf.data_ptr(), complex_buf.data_ptr(), _stream_handle(stream))
+        return complex_buf
+
+    def btran(self, complex_buf, real_buf, stream=None):
+        pf_batch_btran_c2r(self.handle, complex_buf.data_ptr(), real_buf.data_ptr(), _stream_handle(stream))
+        return real_buf
+
+    def destroy(self) -> None:
+        if getattr(self, "handle", None):
+            pf_batch_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):

@@ -30,6 +30,19 @@ struct PassTiming {
     std::vector<EventPair> used;
 };
 
+// Plan choices beyond the layout: the batched transforms use the generic
+// kernels only (one kernel kind per pass type across the batch), take their
+// workspace from the batch, and may carry tuned radix orders and tile widths
+// per axis (x, y, z): radix_order 0 = 16, 8, 4, 2, 3, 5, 7; 1 = 8, 4, 2, 3, 5,
+// 7; 2 = 4, 2, 3, 5, 7; 3 = 3, 5, 7, 16, 8, 4, 2; tile 0 = the default widest
+// tile, else at most `tile` line pairs (x) or columns (y, z) per tile.
+struct PlanOpts {
+    bool generic_only = false;
+    bool external_ws = false;
+    int radix_order[3] = {0, 0, 0};
+    int tile[3] = {0, 0, 0};
+};
+
 }  // namespace
 
 struct pf_plan {
@@ -57,6 +70,7 @@ struct pf_plan {
     bool timing;
     PassTiming tim[2][kPasses];
     std::vector<EventPair> pool;
+    PlanOpts opt;
 };
 
 namespace {
@@ -84,13 +98,18 @@ bool valid_layout_values(const pf_layout *l) {
     return true;
 }
 
-// Radix plan: 16s first, then 8, 4, 2, then 3, 5, 7 (returns false for other primes).
-bool factor_length(int n, FftSpec *fs) {
+// Radix plan: by default 16s first, then 8, 4, 2, then 3, 5, 7 (PlanOpts
+// lists the other orders); returns false for other primes.
+bool factor_length(int n, FftSpec *fs, int order_code = 0) {
     std::memset(fs, 0, sizeof(*fs));
     fs->n = n;
     int m = n, s = 0;
-    const int order[] = {16, 8, 4, 2, 3, 5, 7};
-    for (int r : order) {
+    static const int orders[4][7] = {{16, 8, 4, 2, 3, 5, 7}, {8, 4, 2, 3, 5, 7, 0}, {4, 2, 3, 5, 7, 0, 0},
+                                     {3, 5, 7, 16, 8, 4, 2}};
+    const int *order = orders[order_code >= 0 && order_code < 4 ? order_code : 0];
+    for (int oi = 0; oi < 7; ++oi) {
+        const int r = order[oi];
+        if (r == 0) break;
         while (m % r == 0 && m > 1) {
             if (s >= pf::kMaxStages) return false;
             fs->radix[s++] = r;
@@ -186,7 +205,9 @@ int built_options(const pf_layout *l) {
 // The power-of-two kernel serves every side: the padded workspace (whole
 // 16-column blocks, 16-byte aligned rows), contiguous lines, and unaligned
 // rows (Side::v8).
-void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc) {
+void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc,
+                    int tuned_tc = 0) {
+    if (tuned_tc > 0 && tuned_tc < max_tc) max_tc = tuned_tc;
     d.dir = dir;
     d.prec = p->lay.precision;
     PassArgs &a = d.a;
@@ -194,7 +215,7 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
     a.fft = fs;
     a.tw = (const char *)p->tw_dev + twoff;
     a.C = p->nxh;
-    if (pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
+    if (!p->opt.generic_only && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
         // compile-time radix plan, persistent blocks (grid set once the tile count is known)
         d.kind = pf::PASS_C2C_P2;
         a.math = pf::p2_has_mfma(fs.n) ? p->lay.math : 0;
@@ -482,7 +503,8 @@ void build_passes(pf_plan *p) {
         x.prec = p->lay.precision;
         x.a.fft = p->fx;
         x.a.tw = (const char *)p->tw_dev + p->tw_off[0];
-        choose_tile(p->nx, p->csize, 64, &x.a.tc_log2, &x.a.wpc_log2, &x.a.pitch, &x.lds);
+        const int xmax = p->opt.tile[0] > 0 && p->opt.tile[0] < 64 ? p->opt.tile[0] : 64;
+        choose_tile(p->nx, p->csize, xmax, &x.a.tc_log2, &x.a.wpc_log2, &x.a.pitch, &x.lds);
         x.threads = 1u << (x.a.tc_log2 + x.a.wpc_log2);
         x.a.lines = (long long)p->ny * p->nz;
         x.a.ld_real = p->nx;
@@ -508,7 +530,7 @@ void build_passes(pf_plan *p) {
         }
         // Y stage: in place on the workspace, tile (z, column block)
         PassDesc y;
-        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B);
+        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B, p->opt.tile[1]);
         y.a.in_s = ws_side(p, zstride, p->B, y.a.tc_log2);
         y.a.out_s = y.a.in_s;
         y.a.A = p->nz;
@@ -521,7 +543,7 @@ void build_passes(pf_plan *p) {
         const bool empty = p->lay.third == PF_THIRD_EMPTY;
         FftSpec fz = p->fz;
         if (empty) fz.nstages = 0;
-        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B);
+        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2]);
         if (empty && z.kind == pf::PASS_C2C_P2) z.a.math = 3;  // the power-of-two kernel's reorder-only form
         z.a.A = p->ny;
         z.a.CB = (long long)p->nkb * (p->B >> z.a.tc_log2);
@@ -717,7 +739,7 @@ int pf_query_dims(int nx, int ny, int nz, const pf_layout *l, int pencil, int r1
     return PF_OK;
 }
 
-int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
+static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpts &o, pf_plan **out) {
     if (!out) return PF_EINVAL;
     *out = nullptr;
     int rc = check_impl(nx, ny, nz, l);
@@ -728,13 +750,14 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
     if (!p) return PF_ENOMEM;
     p->nx = nx, p->ny = ny, p->nz = nz, p->nxh = nx / 2 + 1;
     p->lay = *l;
+    p->opt = o;
     p->csize = l->precision == PF_F64 ? 16 : 8;
     p->B = 128 / p->csize;
     p->b_log2 = ilog2(p->B);
     p->nkb = (p->nxh + p->B - 1) / p->B;
-    factor_length(nx, &p->fx);
-    factor_length(ny, &p->fy);
-    factor_length(nz, &p->fz);
+    factor_length(nx, &p->fx, o.radix_order[0]);
+    factor_length(ny, &p->fy, o.radix_order[1]);
+    factor_length(nz, &p->fz, o.radix_order[2]);
 
     // twiddle tables, one allocation, each table 256-byte aligned
     std::vector<unsigned char> host;
@@ -754,7 +777,7 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
         }
         host.resize((host.size() + 255) & ~(size_t)255, 0);
     }
-    p->fast_x = pf::p2x_supported(nx, l->precision);
+    p->fast_x = !o.generic_only && pf::p2x_supported(nx, l->precision);
     p->tw_off[3] = host.size();
     if (p->fast_x) {
         // [M-point stage table (M - 1)][pad][W_nx^k, k = 0 .. M], M = nx / 2
@@ -802,6 +825,13 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
         const size_t cplx_b = (size_t)p->nxh * ny * nz * p->csize;
         p->ws_bytes += real_b > cplx_b ? real_b : cplx_b;
     }
+    if (o.external_ws) {  // the owner supplies the workspace (pf_set_workspace)
+        p->ws = nullptr;
+        p->own_ws = false;
+        build_passes(p);
+        *out = p;
+        return PF_OK;
+    }
     e = hipMalloc(&p->ws, p->ws_bytes);
     if (e != hipSuccess) {
         (void)hipFree(p->tw_dev);
@@ -821,6 +851,10 @@ int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
     build_passes(p);
     *out = p;
     return PF_OK;
+}
+
+int pf_setup(int nx, int ny, int nz, const pf_layout *l, pf_plan **out) {
+    return plan_create(nx, ny, nz, l, PlanOpts(), out);
 }
 
 int pf_get_dims(const pf_plan *p, int pencil, int r1, int r2, int start[3], int size[3], int order[3]) {
@@ -921,6 +955,237 @@ int pf_get_timing(pf_plan *p, int dir, int pass, double *total_ms, long long *co
     }
     *total_ms = tot;
     *count = n;
+    return PF_OK;
+}
+
+}  // extern "C"
+
+struct pf_batch {
+    int count = 0;
+    int prec = PF_F32;
+    std::vector<pf_plan *> plans;
+    std::vector<size_t> roff, coff;  // byte offsets of each transform in the real / complex buffers
+    size_t rbytes = 0, cbytes = 0;
+    void *ws = nullptr;
+    void *tables = nullptr;  // device PassArgs tables and block prefixes of the fused passes
+    pf::BatchLaunch launch[2][3];
+    int mode = PF_BATCH_FUSED;
+    hipStream_t cap = nullptr;  // capture stream for the graph modes
+    struct Graph {
+        const void *in = nullptr;
+        void *out = nullptr;
+        hipGraphExec_t exec = nullptr;
+    } graph[2];
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void batch_free(pf_batch *b) {
+    if (!b) return;
+    for (auto &g : b->graph)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (pf_plan *p : b->plans) pf_destroy(p);
+    if (b->tables) (void)hipFree(b->tables);
+    if (b->ws) (void)hipFree(b->ws);
+    delete b;
+}
+
+// Enqueue one direction of the batch on stream s in the current mode (graphs aside).
+int batch_issue(pf_batch *b, int dir, const void *in, void *out, hipStream_t s) {
+    if (b->mode & PF_BATCH_FUSED) {
+        for (int k = 0; k < 3; ++k) {
+            pf::BatchLaunch L = b->launch[dir][k];
+            L.b.user_in = (const char *)in;
+            L.b.user_out = (char *)out;
+            const hipError_t e = pf::launch_batch(L, s);
+            if (e != hipSuccess) return hip_status(e);
+        }
+        return PF_OK;
+    }
+    const bool fwd = dir == 0;
+    for (int i = 0; i < b->count; ++i) {
+        const char *src = (const char *)in + (fwd ? b->roff[i] : b->coff[i]);
+        char *dst = (char *)out + (fwd ? b->coff[i] : b->roff[i]);
+        const int r = run_chain(b->plans[i], dir, src, dst, s);
+        if (r) return r;
+    }
+    return PF_OK;
+}
+
+int batch_run(pf_batch *b, int dir, const void *in, void *out, void *stream) {
+    if (!b || !in || !out) return PF_EINVAL;
+    if (((uintptr_t)in & 255u) || ((uintptr_t)out & 255u)) return PF_EALIGN;
+    if (in == out) return PF_EALIAS;
+    hipStream_t s = (hipStream_t)stream;
+    if (!(b->mode & PF_BATCH_GRAPH)) return batch_issue(b, dir, in, out, s);
+    pf_batch::Graph &g = b->graph[dir];
+    if (!g.exec || g.in != in || g.out != out) {
+        if (g.exec) {  // buffers changed: capture again once the old graph has finished
+            if (hipStreamSynchronize(s) != hipSuccess) return PF_EHIP;
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PF_EHIP;
+        const int r = batch_issue(b, dir, in, out, b->cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &graph);
+        if (r) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return r;
+        }
+        if (e != hipSuccess) return PF_EHIP;
+        const hipError_t e2 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) {
+            g.exec = nullptr;
+            return PF_EHIP;
+        }
+        g.in = in;
+        g.out = out;
+    }
+    return hip_status(hipGraphLaunch(g.exec, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_batch_setup(int count, const int *dims, const pf_layout *l, const pf_tune *tune, pf_batch **out) {
+    if (!out) return PF_EINVAL;
+    *out = nullptr;
+    if (count < 1 || !dims || !l) return PF_EINVAL;
+    if (l->m1 != 1 || l->m2 != 1 || l->share_only || l->inplace || l->math != PF_PLAIN) return PF_EUNSUPPORTED;
+    for (int i = 0; i < count; ++i) {
+        const int rc = check_impl(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], l);
+        if (rc) return rc;
+        if (tune)
+            for (int a = 0; a < 3; ++a)
+                if (tune[i].radix_order[a] < 0 || tune[i].radix_order[a] > 3 || tune[i].tile[a] < 0) return PF_EINVAL;
+    }
+    pf_batch *b = new (std::nothrow) pf_batch();
+    if (!b) return PF_ENOMEM;
+    b->count = count;
+    b->prec = l->precision;
+    const size_t rs = l->precision == PF_F64 ? 8 : 4;
+    size_t wsum = 0;
+    std::vector<size_t> woff;
+    for (int i = 0; i < count; ++i) {
+        PlanOpts o;
+        o.generic_only = true;
+        o.external_ws = true;
+        if (tune)
+            for (int a = 0; a < 3; ++a) o.radix_order[a] = tune[i].radix_order[a], o.tile[a] = tune[i].tile[a];
+        pf_plan *p = nullptr;
+        const int rc = plan_create(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], l, o, &p);
+        if (rc) {
+            batch_free(b);
+            return rc;
+        }
+        b->plans.push_back(p);
+        woff.push_back(wsum);
+        wsum += align256(p->ws_bytes);
+        const size_t nr = (size_t)p->nx * p->ny * p->nz, nc = (size_t)p->nxh * p->ny * p->nz;
+        b->roff.push_back(b->rbytes);
+        b->coff.push_back(b->cbytes);
+        b->rbytes += align256(nr * rs);
+        b->cbytes += align256(nc * 2 * rs);
+    }
+    if (hipMalloc(&b->ws, wsum) != hipSuccess) {
+        b->ws = nullptr;
+        batch_free(b);
+        return PF_ENOMEM;
+    }
+    for (int i = 0; i < count; ++i) {
+        b->plans[i]->ws = (char *)b->ws + woff[i];
+        b->plans[i]->own_ws = false;
+    }
+    // fused passes: per (direction, pass) a PassArgs table and the block prefix
+    const size_t tab = align256(count * sizeof(PassArgs)), pre = align256((count + 1) * sizeof(long long));
+    if (hipMalloc(&b->tables, 6 * (tab + pre)) != hipSuccess) {
+        b->tables = nullptr;
+        batch_free(b);
+        return PF_ENOMEM;
+    }
+    std::vector<unsigned char> host(6 * (tab + pre), 0);
+    for (int dir = 0; dir < 2; ++dir)
+        for (int k = 0; k < 3; ++k) {
+            const size_t at = (size_t)(dir * 3 + k) * (tab + pre);
+            PassArgs *A = reinterpret_cast<PassArgs *>(host.data() + at);
+            long long *F = reinterpret_cast<long long *>(host.data() + at + tab);
+            pf::BatchLaunch &L = b->launch[dir][k];
+            std::memset(&L, 0, sizeof(L));
+            // user side of this pass: forward X reads / backward X writes the real
+            // arrays; forward Z writes / backward Z reads the complex arrays
+            const bool xpass = (dir == 0 && k == 0) || (dir == 1 && k == 2);
+            const bool zpass = (dir == 0 && k == 2) || (dir == 1 && k == 0);
+            L.b.in_user = (dir == 0 && k == 0) || (dir == 1 && k == 0);
+            L.b.out_user = (dir == 0 && k == 2) || (dir == 1 && k == 2);
+            long long blocks = 0;
+            for (int i = 0; i < count; ++i) {
+                const PassDesc &d = b->plans[i]->pass[dir][k];
+                if (i == 0) {
+                    L.kind = d.kind;
+                    L.dir = d.dir;
+                    L.prec = d.prec;
+                } else if (d.kind != L.kind) {
+                    batch_free(b);
+                    return PF_EUNSUPPORTED;
+                }
+                A[i] = d.a;
+                char *w = (char *)b->plans[i]->ws;
+                const size_t uoff = xpass ? b->roff[i] : b->coff[i];
+                A[i].in = L.b.in_user ? (const void *)uoff : (const void *)w;
+                A[i].out = L.b.out_user ? (void *)uoff : (void *)w;
+                (void)zpass;
+                F[i] = blocks;
+                blocks += d.blocks;
+                L.threads = std::max(L.threads, d.threads);
+                L.lds = std::max(L.lds, d.lds);
+            }
+            F[count] = blocks;
+            if (blocks > 0x7fffffffLL) {
+                batch_free(b);
+                return PF_EUNSUPPORTED;
+            }
+            L.blocks = (unsigned)blocks;
+            L.b.args = reinterpret_cast<const PassArgs *>((char *)b->tables + at);
+            L.b.first = reinterpret_cast<const long long *>((char *)b->tables + at + tab);
+            L.b.count = count;
+        }
+    if (hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        batch_free(b);
+        return PF_EHIP;
+    }
+    *out = b;
+    return PF_OK;
+}
+
+size_t pf_batch_offset(const pf_batch *b, int which, int i) {
+    if (!b || i < 0 || i >= b->count || (which != 0 && which != 1)) return (size_t)-1;
+    return which == 0 ? b->roff[i] : b->coff[i];
+}
+
+size_t pf_batch_bytes(const pf_batch *b, int which) {
+    if (!b || (which != 0 && which != 1)) return 0;
+    return which == 0 ? b->rbytes : b->cbytes;
+}
+
+int pf_batch_set_mode(pf_batch *b, int mode) {
+    if (!b || mode < 0 || mode > 3) return PF_EINVAL;
+    b->mode = mode;
+    return PF_OK;
+}
+
+int pf_batch_ftran_r2c(pf_batch *b, const void *in, void *out, void *stream) { return batch_run(b, 0, in, out, stream); }
+
+int pf_batch_btran_c2r(pf_batch *b, const void *in, void *out, void *stream) { return batch_run(b, 1, in, out, stream); }
+
+int pf_batch_destroy(pf_batch *b) {
+    batch_free(b);
     return PF_OK;
 }
 

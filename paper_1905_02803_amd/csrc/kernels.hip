@@ -101,14 +101,17 @@ __device__ __forceinline__ long long side_base(const Side &s, long long a, long 
 }
 
 // ---- C2C along a strided axis, TC columns per workgroup -------------------
+// Tile `tile` of the pass a, reading `inp` and writing `outp` (the pass's own
+// buffers, or the batch's).  The workgroup may have more threads than the
+// tile's TC x wpc (a batched launch sized for its largest transform): the
+// surplus threads help with the loads and stores and sit out the stages.
 template <typename T, int DIR>
-__global__ __launch_bounds__(1024) void k_c2c_tile(PassArgs a) {
+__device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp, void *outp, long long tile) {
     cx<T> *lds = reinterpret_cast<cx<T> *>(pf_smem);
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int TC = 1 << a.tc_log2;
     const int wpc = 1 << a.wpc_log2;
-    const long long tile = blockIdx.x;
     const long long ta = tile / a.CB;
     const long long cb = tile - ta * a.CB;
     const long long ib = side_base(a.in_s, ta, cb, TC);
@@ -117,13 +120,14 @@ __global__ __launch_bounds__(1024) void k_c2c_tile(PassArgs a) {
     const int ncol = left < TC ? (int)left : TC;
     const int n = a.fft.n;
     const int pitch = a.pitch;
-    const cx<T> *__restrict__ in = reinterpret_cast<const cx<T> *>(a.in);
-    cx<T> *__restrict__ out = reinterpret_cast<cx<T> *>(a.out);
+    const cx<T> *__restrict__ in = reinterpret_cast<const cx<T> *>(inp);
+    cx<T> *__restrict__ out = reinterpret_cast<cx<T> *>(outp);
+    const int rows_per = (nthr >> a.tc_log2) > 0 ? (nthr >> a.tc_log2) : 1;
 
     if (a.in_s.sc == 1) {  // rows of the tile are contiguous: column fastest
         const int c = tid & (TC - 1);
         if (c < ncol)
-            for (int p = tid >> a.tc_log2; p < n; p += nthr >> a.tc_log2)
+            for (int p = tid >> a.tc_log2; p < n; p += rows_per)
                 lds[c * pitch + pidx(p)] = in[ib + c + (long long)p * a.in_s.sp];
     } else {  // columns are contiguous lines: point fastest
         const int c = tid >> a.wpc_log2;
@@ -132,12 +136,14 @@ __global__ __launch_bounds__(1024) void k_c2c_tile(PassArgs a) {
                 lds[c * pitch + pidx(p)] = in[ib + (long long)c * a.in_s.sc + (long long)p * a.in_s.sp];
     }
     __syncthreads();
-    fft_lds<T, DIR>(lds + (tid >> a.wpc_log2) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
-                    tid & (wpc - 1), wpc);
+    const int col = tid >> a.wpc_log2;
+    const bool act = col < TC;
+    fft_lds<T, DIR>(lds + (act ? col : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+                    act ? (tid & (wpc - 1)) : n, wpc);
     if (a.out_s.sc == 1) {
         const int c = tid & (TC - 1);
         if (c < ncol)
-            for (int p = tid >> a.tc_log2; p < n; p += nthr >> a.tc_log2)
+            for (int p = tid >> a.tc_log2; p < n; p += rows_per)
                 out[ob + c + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
     } else {
         const int c = tid >> a.wpc_log2;
@@ -145,6 +151,11 @@ __global__ __launch_bounds__(1024) void k_c2c_tile(PassArgs a) {
             for (int p = tid & (wpc - 1); p < n; p += wpc)
                 out[ob + (long long)c * a.out_s.sc + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
     }
+}
+
+template <typename T, int DIR>
+__global__ __launch_bounds__(1024) void k_c2c_tile(PassArgs a) {
+    c2c_tile_body<T, DIR>(a, a.in, a.out, blockIdx.x);
 }
 
 // Row offsets in the blocked workspace of the 2 TC real lines of an X tile:
@@ -160,7 +171,7 @@ __device__ __forceinline__ void x_row_offsets(const PassArgs &a, long long g0, i
 
 // ---- X stage, forward: real lines -> half spectra in the blocked workspace
 template <typename T>
-__global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
+__device__ __forceinline__ void r2c_x_body(const PassArgs &a, const void *inp, void *outp, long long tile) {
     __shared__ long long rowoff[128];
     cx<T> *lds = reinterpret_cast<cx<T> *>(pf_smem);
     const int tid = threadIdx.x;
@@ -169,12 +180,13 @@ __global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
     const int wpc = 1 << a.wpc_log2;
     const int n = a.fft.n;
     const int pitch = a.pitch;
-    const long long g0 = (long long)blockIdx.x * (2 * TC);
-    const T *__restrict__ in = reinterpret_cast<const T *>(a.in);
-    cx<T> *__restrict__ out = reinterpret_cast<cx<T> *>(a.out);
+    const long long g0 = tile * (2 * TC);
+    const T *__restrict__ in = reinterpret_cast<const T *>(inp);
+    cx<T> *__restrict__ out = reinterpret_cast<cx<T> *>(outp);
     x_row_offsets(a, g0, 2 * TC, rowoff);
-    {
-        const int c = tid >> a.wpc_log2;
+    const int c = tid >> a.wpc_log2;
+    const bool act = c < TC;  // surplus threads of a batched launch only help with the stores
+    if (act) {
         const long long ga = g0 + 2 * c, gb = ga + 1;
         const bool va = ga < a.lines, vb = gb < a.lines;
         const T *pa = in + ga * a.ld_real;
@@ -186,8 +198,8 @@ __global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
         }
     }
     __syncthreads();
-    fft_lds<T, -1>(lds + (tid >> a.wpc_log2) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
-                   tid & (wpc - 1), wpc);
+    fft_lds<T, -1>(lds + (act ? c : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+                   act ? (tid & (wpc - 1)) : n, wpc);
     const int B = 1 << a.b_log2;
     const int total = a.nkb * TC * B;
     const long long kbstride = (long long)a.ypitch << a.b_log2;
@@ -207,9 +219,14 @@ __global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
+    r2c_x_body<T>(a, a.in, a.out, blockIdx.x);
+}
+
 // ---- X stage, backward: blocked half spectra -> real lines ---------------
 template <typename T>
-__global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
+__device__ __forceinline__ void c2r_x_body(const PassArgs &a, const void *inp, void *outp, long long tile) {
     __shared__ long long rowoff[128];
     cx<T> *lds = reinterpret_cast<cx<T> *>(pf_smem);
     const int tid = threadIdx.x;
@@ -218,9 +235,9 @@ __global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
     const int wpc = 1 << a.wpc_log2;
     const int n = a.fft.n;
     const int pitch = a.pitch;
-    const long long g0 = (long long)blockIdx.x * (2 * TC);
-    const cx<T> *__restrict__ in = reinterpret_cast<const cx<T> *>(a.in);
-    T *__restrict__ out = reinterpret_cast<T *>(a.out);
+    const long long g0 = tile * (2 * TC);
+    const cx<T> *__restrict__ in = reinterpret_cast<const cx<T> *>(inp);
+    T *__restrict__ out = reinterpret_cast<T *>(outp);
     x_row_offsets(a, g0, 2 * TC, rowoff);
     __syncthreads();
     const int B = 1 << a.b_log2;
@@ -244,10 +261,11 @@ __global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
         }
     }
     __syncthreads();
-    fft_lds<T, 1>(lds + (tid >> a.wpc_log2) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
-                  tid & (wpc - 1), wpc);
-    {
-        const int c = tid >> a.wpc_log2;
+    const int c = tid >> a.wpc_log2;
+    const bool act = c < TC;
+    fft_lds<T, 1>(lds + (act ? c : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+                  act ? (tid & (wpc - 1)) : n, wpc);
+    if (act) {
         const long long ga = g0 + 2 * c, gb = ga + 1;
         const bool va = ga < a.lines, vb = gb < a.lines;
         T *pa = out + ga * a.ld_real;
@@ -259,6 +277,85 @@ __global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
             if (vb) pb[p] = z.y;
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
+    c2r_x_body<T>(a, a.in, a.out, blockIdx.x);
+}
+
+// ---- batched passes: one launch over the tiles of many transforms --------
+// Block b belongs to the transform i with first[i] <= b < first[i + 1] (a
+// binary search over the table, uniform per block) and works on its tile
+// b - first[i] with that transform's arguments args[i].  A pointer of
+// args[i] that names a user array holds a byte offset from the call's base.
+__device__ __forceinline__ int batch_find(const BatchArgs &b, long long blk) {
+    int lo = 0, hi = b.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.first[mid] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const void *batch_in(const BatchArgs &b, const PassArgs &a) {
+    return b.in_user ? (const void *)(b.user_in + (size_t)a.in) : a.in;
+}
+__device__ __forceinline__ void *batch_out(const BatchArgs &b, const PassArgs &a) {
+    return b.out_user ? (void *)(b.user_out + (size_t)a.out) : a.out;
+}
+
+template <typename T, int DIR>
+__global__ __launch_bounds__(1024) void k_c2c_tile_b(BatchArgs b) {
+    const long long blk = blockIdx.x;
+    const int i = batch_find(b, blk);
+    const PassArgs &a = b.args[i];
+    c2c_tile_body<T, DIR>(a, batch_in(b, a), batch_out(b, a), blk - b.first[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_r2c_x_b(BatchArgs b) {
+    const long long blk = blockIdx.x;
+    const int i = batch_find(b, blk);
+    const PassArgs &a = b.args[i];
+    r2c_x_body<T>(a, batch_in(b, a), batch_out(b, a), blk - b.first[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_c2r_x_b(BatchArgs b) {
+    const long long blk = blockIdx.x;
+    const int i = batch_find(b, blk);
+    const PassArgs &a = b.args[i];
+    c2r_x_body<T>(a, batch_in(b, a), batch_out(b, a), blk - b.first[i]);
+}
+
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t s) {
+    if (L.blocks == 0) return hipSuccess;
+    const dim3 g(L.blocks), bl(L.threads);
+    const bool f64 = L.prec != 0;
+    switch (L.kind) {
+        case PASS_C2C:
+            if (f64) {
+                if (L.dir < 0) hipLaunchKernelGGL((k_c2c_tile_b<double, -1>), g, bl, L.lds, s, L.b);
+                else hipLaunchKernelGGL((k_c2c_tile_b<double, 1>), g, bl, L.lds, s, L.b);
+            } else {
+                if (L.dir < 0) hipLaunchKernelGGL((k_c2c_tile_b<float, -1>), g, bl, L.lds, s, L.b);
+                else hipLaunchKernelGGL((k_c2c_tile_b<float, 1>), g, bl, L.lds, s, L.b);
+            }
+            break;
+        case PASS_R2C_X:
+            if (f64) hipLaunchKernelGGL(k_r2c_x_b<double>, g, bl, L.lds, s, L.b);
+            else hipLaunchKernelGGL(k_r2c_x_b<float>, g, bl, L.lds, s, L.b);
+            break;
+        case PASS_C2R_X:
+            if (f64) hipLaunchKernelGGL(k_c2r_x_b<double>, g, bl, L.lds, s, L.b);
+            else hipLaunchKernelGGL(k_c2r_x_b<float>, g, bl, L.lds, s, L.b);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // ---- pack / unpack between the global arrays and the Table 1 blocks ------
@@ -445,6 +542,14 @@ hipError_t prepare_kernels(size_t max_lds) {
     PF_ALLOW(k_r2c_x<double>);
     PF_ALLOW(k_c2r_x<float>);
     PF_ALLOW(k_c2r_x<double>);
+    PF_ALLOW((k_c2c_tile_b<float, -1>));
+    PF_ALLOW((k_c2c_tile_b<float, 1>));
+    PF_ALLOW((k_c2c_tile_b<double, -1>));
+    PF_ALLOW((k_c2c_tile_b<double, 1>));
+    PF_ALLOW(k_r2c_x_b<float>);
+    PF_ALLOW(k_r2c_x_b<double>);
+    PF_ALLOW(k_c2r_x_b<float>);
+    PF_ALLOW(k_c2r_x_b<double>);
 #undef PF_ALLOW
     return e;
 }

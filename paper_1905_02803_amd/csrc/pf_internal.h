@@ -123,6 +123,29 @@ struct PassDesc {
     PassArgs a;
 };
 
+// Work list of one batched pass (generic kernels): transform i owns blocks
+// first[i] .. first[i+1] - 1 and runs with args[i] (device tables).  in_user /
+// out_user: the pass reads / writes the caller's arrays, and args[i].in /
+// .out hold byte offsets from user_in / user_out.
+struct BatchArgs {
+    const PassArgs *args;
+    const long long *first;
+    int count;
+    int in_user, out_user;
+    const char *user_in;
+    char *user_out;
+};
+
+struct BatchLaunch {
+    PassKind kind;
+    int dir, prec;
+    unsigned blocks, threads;
+    size_t lds;
+    BatchArgs b;
+};
+
+hipError_t launch_batch(const BatchLaunch &L, hipStream_t s);
+
 // Allow every kernel instantiation up to max_lds bytes of dynamic LDS.
 hipError_t prepare_kernels(size_t max_lds);
 // Enqueue one pass.

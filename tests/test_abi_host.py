@@ -165,3 +165,22 @@ def test_null_handles():
     pf.pf_destroy(None)
     assert pf.lib().pf_num_passes(None, 0) == pf.PF_EINVAL
     assert pf.lib().pf_copy(None, None, 16, None) == pf.PF_EINVAL
+
+
+def test_batch_setup_rejects_bad_arguments_before_touching_the_gpu():
+    for dims, lay, tune, code in [
+        ([], pf.Layout(), None, pf.PF_EINVAL),
+        ([(16, 8, 8), (0, 8, 8)], pf.Layout(), None, pf.PF_EINVAL),
+        ([(16, 8, 8), (22, 8, 8)], pf.Layout(), None, pf.PF_EUNSUPPORTED),  # factor 11
+        ([(16, 8, 8)], pf.Layout(m1=2), None, pf.PF_EUNSUPPORTED),
+        ([(16, 8, 8)], pf.Layout(inplace=1), None, pf.PF_EUNSUPPORTED),
+        ([(16, 8, 8)], pf.Layout(math=pf.PF_MFMA_FP16X2), None, pf.PF_EUNSUPPORTED),
+        ([(16, 8, 8)], pf.Layout(), [((0, 4, 0), (0, 0, 0))], pf.PF_EINVAL),  # radix order 4
+        ([(16, 8, 8)], pf.Layout(), [((0, 0, 0), (0, -1, 0))], pf.PF_EINVAL),
+    ]:
+        with pytest.raises(pf.PfError) as e:
+            pf.pf_batch_setup(dims, lay, tune)
+        assert e.value.code == code, (dims, lay, tune)
+    assert pf.pf_batch_bytes(None, 0) == 0
+    assert pf.lib().pf_batch_set_mode(None, 1) == pf.PF_EINVAL
+    assert pf.lib().pf_batch_ftran_r2c(None, None, None, None) == pf.PF_EINVAL

@@ -1,0 +1,134 @@
+"""Batched transforms of many uneven grids (each dimension a 7-smooth length
+in [48, 320], odd ones included; the paper's arbitrary grid sizes, Sec. 3.1).
+
+Every transform of a batch must match the oracle (FP32 1e-6, FP64 1e-12),
+in every execution mode (one transform at a time, one fused launch per pass,
+and both replayed from a captured hipGraph) and with tuned radix orders and
+tile widths; the modes run the same arithmetic and must agree bit for bit.
+Graph replays are checked one by one, with eager work between them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1905_02803_amd as pf  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def small_dims(count, seed, cap=96):
+    """count triples from the batch generator, each length folded below cap (still 7-smooth)."""
+    out = []
+    for d in synth.batch_sizes(seed, count):
+        t = []
+        for v in d:
+            while v > cap:
+                v //= 2 if v % 2 == 0 else (3 if v % 3 == 0 else (5 if v % 5 == 0 else 7))
+            t.append(max(v, 1))
+        out.append(tuple(t))
+    return out
+
+
+def fill(batch, buf, which, seed, dt):
+    for i, (nx, ny, nz) in enumerate(batch.dims):
+        v = batch.view(buf, which, i)
+        if which == 0:
+            v.copy_(torch.from_numpy(synth.uniform(seed + i, (nz, ny, nx)).astype(dt)))
+        else:
+            V = synth.complex_half(seed + i, (nz, ny, nx // 2 + 1)).astype(dt)
+            v.copy_(torch.from_numpy(oracle.to_stride1(V) if batch.layout.stride1 else V))
+
+
+def check_batch(batch, tol, seed=40):
+    rdt = np.float64 if batch.layout.precision == pf.PF_F64 else np.float32
+    cdt = np.complex128 if batch.layout.precision == pf.PF_F64 else np.complex64
+    # buffers start zeroed so that the padding between transforms compares equal
+    R = batch.empty(0).zero_()
+    C = batch.empty(1).zero_()
+    fill(batch, R, 0, seed, rdt)
+    batch.ftran(R, C)
+    Cin = batch.empty(1).zero_()
+    fill(batch, Cin, 1, seed + 500, cdt)
+    Rout = batch.empty(0).zero_()
+    batch.btran(Cin, Rout)
+    torch.cuda.synchronize()
+    for i, (nx, ny, nz) in enumerate(batch.dims):
+        u = batch.view(R, 0, i).cpu().numpy()
+        ref = oracle.r2c3d(u)
+        got = batch.view(C, 1, i).cpu().numpy()
+        assert rel(got, oracle.to_stride1(ref) if batch.layout.stride1 else ref) < tol, (i, (nx, ny, nz))
+        V = batch.view(Cin, 1, i).cpu().numpy()
+        V = oracle.from_stride1(V) if batch.layout.stride1 else V
+        assert rel(batch.view(Rout, 0, i).cpu().numpy(), oracle.c2r3d(V, nx)) < tol, (i, (nx, ny, nz))
+    return R, C, Cin, Rout
+
+
+@pytest.mark.parametrize("stride1", [1, 0])
+@pytest.mark.parametrize("prec", [pf.PF_F32, pf.PF_F64])
+def test_fused_batch_matches_oracle(prec, stride1):
+    dims = small_dims(12, 4)
+    print(f"case batch dims={dims} prec={prec} stride1={stride1}", flush=True)
+    with pf.Batch(dims, pf.Layout(precision=prec, stride1=stride1)) as b:
+        check_batch(b, 1e-12 if prec == pf.PF_F64 else 1e-6)
+
+
+def test_all_modes_agree_bitwise_and_graph_replays():
+    dims = small_dims(10, 7)
+    print(f"case batch dims={dims}", flush=True)
+    with pf.Batch(dims, mode=pf.PF_BATCH_FUSED) as b:
+        R, C, Cin, Rout = check_batch(b, 1e-6)
+        ref_c, ref_r = C.clone(), Rout.clone()
+        for mode in (pf.PF_BATCH_SERIAL, pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH,
+                     pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH):
+            b.set_mode(mode)
+            for rep in range(3):  # replays of the captured graph, eager work in between
+                C2 = torch.zeros_like(C)
+                R2 = torch.zeros_like(Rout)
+                b.ftran(R, C2)
+                b.btran(Cin, R2)
+                junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+                torch.cuda.synchronize()
+                assert junk.isfinite()
+                assert torch.equal(C2, ref_c), (mode, rep)
+                assert torch.equal(R2, ref_r), (mode, rep)
+        # new buffers: the graph is captured again
+        b.set_mode(pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH)
+        R3 = R.clone()
+        C3 = torch.zeros_like(C)
+        b.ftran(R3, C3)
+        torch.cuda.synchronize()
+        assert torch.equal(C3, ref_c)
+
+
+def test_tuned_plans_match_oracle():
+    """Every radix order and a spread of tile widths, drawn per transform."""
+    dims = small_dims(12, 11)
+    rng = np.random.default_rng(5)
+    tune = [(tuple(int(v) for v in rng.integers(0, 4, 3)), tuple(int(v) for v in rng.choice([0, 1, 2, 4, 8, 16], 3)))
+            for _ in dims]
+    print(f"case batch dims={dims} tune={tune}", flush=True)
+    with pf.Batch(dims, tune=tune) as b:
+        check_batch(b, 1e-6)
+    with pf.Batch(dims, pf.Layout(precision=pf.PF_F64), tune=tune) as b:
+        check_batch(b, 1e-12)
+
+
+def test_batch_argument_errors():
+    with pytest.raises(pf.PfError) as e:
+        pf.Batch([(16, 8, 8)], pf.Layout(inplace=1))
+    assert e.value.code == pf.PF_EUNSUPPORTED
+    with pf.Batch([(16, 8, 8), (12, 10, 6)]) as b:
+        R = b.empty(0)
+        with pytest.raises(pf.PfError) as e:
+            b.ftran(R, R)
+        assert e.value.code == pf.PF_EALIAS
+        with pytest.raises(pf.PfError) as e:
+            b.set_mode(9)
+        assert e.value.code == pf.PF_EINVAL
