@@ -246,6 +246,71 @@ def layout_timings(pf, nx, ny, nz, args, dev, stream, u):
     return out
 
 
+def batch_timing(pf, args, dev, stream, count=64, seed=4, check=True):
+    """64 independent R2C+C2R FP32 transforms of 7-smooth sizes in [48, 320] (uniform[-1, 1] data):
+    ms per batch pair in each execution mode, default and autotuned plans, and the forward error of a
+    sample of transforms against the FP64 oracle."""
+    import torch
+
+    import synth
+    from paper_1905_02803_amd import autotune
+
+    dims = synth.batch_sizes(seed, count)
+    Ns = [float(nx) * ny * nz for nx, ny, nz in dims]
+    flops = sum(5.0 * N * math.log2(N) for N in Ns)
+    nbytes = sum(2 * (N * 4 + (nx // 2 + 1) * ny * nz * 8) + 8 * (nx // 2 + 1) * ny * nz * 8
+                 for N, (nx, ny, nz) in zip(Ns, dims))  # both directions: X, Y, Z passes
+    tuned = autotune.tune_for(dims)
+    out = {"count": count, "sizes": f"synth.batch_sizes({seed}, {count}): 7-smooth, each dimension in [48, 320]",
+           "points": sum(Ns), "gflop_per_pair": flops / 1e9, "alg_bytes_per_pair": nbytes, "modes": {}}
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    for tname, tune in (("default", None), ("tuned", tuned)):
+        if tname == "tuned" and tune is None:
+            out["modes"]["tuned"] = "no cached plans for these sizes"
+            continue
+        b = pf.Batch(dims, tune=tune)
+        R = b.empty(0).zero_()
+        C = b.empty(1).zero_()
+        R2 = b.empty(0)
+        for i in range(count):
+            v = b.view(R, 0, i)
+            v.copy_(torch.rand(v.shape, generator=g, device=dev) * 2 - 1)
+        for mname, mode in (("serial", pf.PF_BATCH_SERIAL), ("serial_graph", pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH),
+                            ("fused", pf.PF_BATCH_FUSED), ("fused_graph", pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH)):
+            b.set_mode(mode)
+            for _ in range(args.warmup):
+                b.ftran(R, C)
+                b.btran(C, R2)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                b.ftran(R, C)
+                b.btran(C, R2)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            out["modes"][f"{tname}_{mname}"] = {"ms_per_pair": ms, "gflops": flops / (ms * 1e-3) / 1e9,
+                                                "alg_GBps": nbytes / (ms * 1e-3) / 1e9,
+                                                "transforms_per_s": count / (ms * 1e-3)}
+        if check and tname == "default":
+            import oracle
+
+            b.set_mode(pf.PF_BATCH_FUSED)
+            b.ftran(R, C)
+            torch.cuda.synchronize()
+            errs = {}
+            for i in sorted(set([0, 1, 2, int(max(range(count), key=lambda j: Ns[j]))])):
+                ref = oracle.to_stride1(oracle.r2c3d(b.view(R, 0, i).cpu().numpy()))
+                got = b.view(C, 1, i).cpu().numpy()
+                errs["x".join(map(str, dims[i]))] = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+            out["rel_l2_fwd_vs_fp64_oracle"] = errs
+        b.destroy()
+    return out
+
+
 def share_only_timing(pf, nx, ny, nz, args, dev, stream, m2=8, r2=3):
     """One rank's share of the grid on a 1 x m2 slab grid (share-only plan): per-pass times."""
     import torch
@@ -389,6 +454,7 @@ def main():
         del Um
         pm.destroy()
     layouts = layout_timings(pf, nx, ny, nz, args, dev, stream, u)
+    batched = batch_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
     share = share_only_timing(pf, nx, ny, nz, args, dev, stream)
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
@@ -438,6 +504,7 @@ def main():
         "passes": passes,
         "share_only": share,
         "layouts": layouts,
+        "batched": batched,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
     }

@@ -80,6 +80,8 @@ def bind(lib):
         f.restype = ctypes.c_int
     lib.oracle_stage_c2c.argtypes = [ctypes.c_int] * 3 + [_dp, ctypes.c_int, ctypes.c_int]
     lib.oracle_stage_c2c.restype = ctypes.c_int
+    lib.oracle_stage_dct1_z.argtypes = [ctypes.c_int] * 3 + [_dp]
+    lib.oracle_stage_dct1_z.restype = ctypes.c_int
     return lib
 
 
@@ -199,6 +201,27 @@ def c2r3d_third_empty(U: np.ndarray, nx: int) -> np.ndarray:
     """Backward transform with an empty third transform: the Y stage (C2C,
     sign +1) then the staged 1D C2R along X -> real [nz][ny][nx]."""
     return stage_x_c2r(stage_c2c(U, nx, "y", +1), nx)
+
+
+def stage_dct1_z(U: np.ndarray, nx: int) -> np.ndarray:
+    """Type-I DCT (unnormalised, Gauss-Lobatto points) along z of a copy of U[nz][ny][nxh]."""
+    V = _c128(U).copy()
+    nz, ny, _ = V.shape
+    _check(_load().oracle_stage_dct1_z(nx, ny, nz, V.view(np.float64).ctypes.data_as(_dp)), "stage_dct1_z")
+    return V
+
+
+def r2c3d_cheb(u: np.ndarray) -> np.ndarray:
+    """Forward transform with the Chebyshev third transform (Sec. 3.1): X R2C,
+    Y C2C (sign -1), then the type-I DCT along z -> [nz][ny][nxh]."""
+    nx = np.asarray(u).shape[2]
+    return stage_dct1_z(stage_c2c(stage_x_r2c(u), nx, "y", -1), nx)
+
+
+def c2r3d_cheb(U: np.ndarray, nx: int) -> np.ndarray:
+    """Backward transform with the Chebyshev third transform: type-I DCT along
+    z (its own inverse up to 2 (nz - 1)), Y C2C (sign +1), staged C2R along X."""
+    return stage_x_c2r(stage_c2c(stage_dct1_z(U, nx), nx, "y", +1), nx)
 
 
 def to_stride1(U: np.ndarray) -> np.ndarray:

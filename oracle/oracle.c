@@ -312,6 +312,56 @@ int oracle_stage_c2c(int nx, int ny, int nz, double *U, int axis, int sign) {
 }
 
 /*
+ * Chebyshev (cosine) third transform along z (Sec. 3.1 allows a Chebyshev
+ * transform in place of the third FFT): the type-I discrete cosine transform
+ * on the nz Gauss-Lobatto points, unnormalised, written out from its
+ * definition,
+ *   Y[k] = x[0] + (-1)^k x[nz-1] + 2 sum_{j=1}^{nz-2} x[j] cos(pi j k / (nz-1)),
+ * applied to the real and imaginary parts of every z line of U[nz][ny][nxh]
+ * (the matrix is real, so complex lines go through unchanged in type).  The
+ * angle pi j k / (nz-1) is reduced exactly as (j k mod 2(nz-1)) / (2(nz-1)).
+ */
+int oracle_stage_dct1_z(int nx, int ny, int nz, double *Uio) {
+    if (nx < 1 || ny < 1 || nz < 2) return -1;
+    const int nxh = nx / 2 + 1;
+    const long L = 2L * (nz - 1);
+    double *c = (double *)malloc(sizeof(double) * (size_t)L);
+    cplx *pool = (cplx *)malloc(sizeof(cplx) * (size_t)nz * 2 * (size_t)oracle_num_threads());
+    if (!c || !pool) {
+        free(c);
+        free(pool);
+        return -2;
+    }
+    for (long m = 0; m < L; ++m) c[m] = cos(TWO_PI * (double)m / (double)L);
+    cplx *U = (cplx *)Uio;
+    const long lines = (long)nxh * ny, zs = (long)nxh * ny;
+#pragma omp parallel
+    {
+        cplx *x = pool + (size_t)nz * 2 * (size_t)omp_thread_id();
+        cplx *y = x + nz;
+#pragma omp for schedule(static)
+        for (long ln = 0; ln < lines; ++ln) {
+            for (int j = 0; j < nz; ++j) x[j] = U[ln + j * zs];
+            for (int k = 0; k < nz; ++k) {
+                const double sg = (k % 2 == 0) ? 1.0 : -1.0;
+                double re = x[0].re + sg * x[nz - 1].re, im = x[0].im + sg * x[nz - 1].im;
+                for (int j = 1; j < nz - 1; ++j) {
+                    const double w = 2.0 * c[((long)j * k) % L];
+                    re += w * x[j].re;
+                    im += w * x[j].im;
+                }
+                y[k].re = re;
+                y[k].im = im;
+            }
+            for (int k = 0; k < nz; ++k) U[ln + k * zs] = y[k];
+        }
+    }
+    free(pool);
+    free(c);
+    return 0;
+}
+
+/*
  * 1D complex-to-real of one line c[0..nxh): the inverse DFT of the Hermitian
  * extension F, with F[0] = Re c[0], F[k] = c[k] and F[nx-k] = conj(c[k]) for
  * 0 < k <= (nx-1)/2, and F[nx/2] = Re c[nx/2] for even nx; out = Re(IDFT F).

@@ -36,6 +36,8 @@ MUTANTS = {
     "forward_keeps_too_few": ("memcpy(U + L * nxh, b, sizeof(cplx) * (size_t)nxh);",
                               "memcpy(U + L * nxh, b, sizeof(cplx) * (size_t)(nxh - 1));"),
     "backward_y_sign": ("if (!err) err = pass_y(engine, nxh, ny, nz, T, +1);", "if (!err) err = pass_y(engine, nxh, ny, nz, T, -1);"),
+    "dct_end_node_sign": ("const double sg = (k % 2 == 0) ? 1.0 : -1.0;", "const double sg = 1.0;"),
+    "dct_interior_weight": ("const double w = 2.0 * c[((long)j * k) % L];", "const double w = c[((long)j * k) % L];"),
 }
 
 
@@ -57,6 +59,13 @@ def pins_pass() -> bool:
             return False
         u = synth.uniform(33, (12, 10, 16))
         if rel(oracle.c2r3d(oracle.r2c3d(u), 16), u.size * u) > 1e-12:
+            return False
+        # Chebyshev third transform: its own inverse up to 2 (nz - 1); constant -> one spike
+        U = synth.complex_half(34, (9, 3, 4))
+        if rel(oracle.stage_dct1_z(oracle.stage_dct1_z(U, 6), 6), 16 * U) > 1e-12:
+            return False
+        D = oracle.stage_dct1_z(np.ones((9, 3, 4), dtype=np.complex128), 6)
+        if np.max(np.abs(D[0] - 16)) > 1e-12 or np.max(np.abs(D[1:])) > 1e-12:
             return False
     except Exception:
         return False

@@ -132,6 +132,41 @@ def test_empty_third_transform_vs_numpy_2d(shape):
     assert np.max(np.abs(np.delete(V, nz // 2, axis=0))) == 0.0
 
 
+@pytest.mark.parametrize("nz", [2, 3, 5, 17, 33, 40])
+def test_dct1_along_z_pins(nz):
+    """Chebyshev third transform: scipy's type-1 DCT as an independent library;
+    its own inverse up to 2 (nz - 1); a constant gives a single spike 2 (nz - 1)
+    at k = 0; a point at the last Gauss-Lobatto node gives (-1)^k."""
+    import scipy.fft as sf
+
+    ny, nxh = 3, 4
+    U = synth.complex_half(31 + nz, (nz, ny, nxh))
+    V = oracle.stage_dct1_z(U, 2 * (nxh - 1))
+    ref = sf.dct(U.real, type=1, axis=0) + 1j * sf.dct(U.imag, type=1, axis=0)
+    assert rel(V, ref) < 1e-13
+    assert rel(oracle.stage_dct1_z(V, 2 * (nxh - 1)), 2 * (nz - 1) * U) < 1e-13
+    C = np.ones((nz, ny, nxh), dtype=np.complex128)
+    D = oracle.stage_dct1_z(C, 2 * (nxh - 1))
+    assert np.max(np.abs(D[0] - 2 * (nz - 1))) < 1e-12 and np.max(np.abs(D[1:])) < 1e-12
+    E = np.zeros((nz, ny, nxh), dtype=np.complex128)
+    E[nz - 1] = 1.0
+    F = oracle.stage_dct1_z(E, 2 * (nxh - 1))
+    assert np.max(np.abs(F - ((-1.0) ** np.arange(nz))[:, None, None])) < 1e-13
+
+
+def test_cheb_transforms_compose_the_stages():
+    """The Chebyshev-third 3D transforms are the X and Y stages followed / preceded by the DCT."""
+    nz, ny, nx = 9, 6, 10
+    u = synth.uniform(41, (nz, ny, nx))
+    import scipy.fft as sf
+
+    W = np.fft.rfftn(u, axes=(1, 2))
+    ref = sf.dct(W.real, type=1, axis=0) + 1j * sf.dct(W.imag, type=1, axis=0)
+    assert rel(oracle.r2c3d_cheb(u), ref) < 1e-13
+    back = oracle.c2r3d_cheb(oracle.r2c3d_cheb(u), nx)
+    assert rel(back, u * nx * ny * 2 * (nz - 1)) < 1e-13
+
+
 @pytest.mark.parametrize("shape", SMALL)
 def test_delta_at_origin_gives_constant_spectrum(shape):
     u = np.zeros(shape)
