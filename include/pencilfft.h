@@ -81,6 +81,8 @@ extern "C" {
 
 #define PF_THIRD_FFT 0   /* Fourier transform along Z (default)                 */
 #define PF_THIRD_EMPTY 1 /* no transform along Z (Sec. 3.1: empty transform)   */
+#define PF_THIRD_CHEB 2  /* type-I DCT along Z on nz Gauss-Lobatto points     */
+                         /* (Sec. 3.1: Chebyshev third transform), unnormalised */
 
 #define PF_PENCIL_X 0
 #define PF_PENCIL_Y 1
@@ -105,7 +107,11 @@ extern "C" {
  * flag is accepted and changes no result and no layout.  third =
  * PF_THIRD_EMPTY skips the transform along Z (Sec. 3.1): the forward output
  * is the Z-pencil of the X-then-Y transformed data, z untransformed, and the
- * backward transform starts from such an array.  inplace: in == out, and the
+ * backward transform starts from such an array.  third = PF_THIRD_CHEB
+ * replaces the Z FFT by the type-I DCT Y[k] = x[0] + (-1)^k x[nz-1] + 2
+ * sum_{j=1}^{nz-2} x[j] cos(pi j k / (nz - 1)) in both directions (it is its
+ * own inverse up to 2 (nz - 1), so the round trip returns nx ny 2 (nz - 1) u);
+ * needs nz >= 2 and 2 (nz - 1) with no prime factor above 7.  inplace: in == out, and the
  * buffer must hold max(real, complex) bytes; real data sits unpadded at the
  * start of the buffer (Sec. 3.1 lists in- and out-of-place transforms).
  *
@@ -129,7 +135,7 @@ typedef struct pf_layout {
     int precision;  /* PF_F32 (default) or PF_F64                           */
     int math;       /* PF_PLAIN (default), PF_MFMA_FP16X2, PF_MFMA_BF16X2   */
     int inplace;    /* 0 (default) = out-of-place, 1 = in-place             */
-    int third;      /* PF_THIRD_FFT (default) or PF_THIRD_EMPTY             */
+    int third;      /* PF_THIRD_FFT (default), PF_THIRD_EMPTY, PF_THIRD_CHEB */
     int share_only; /* 0 (default) or 1: one rank's share, see below         */
     int r1, r2;     /* share_only: the rank, 0 <= r1 < m1, 0 <= r2 < m2;     */
                     /* otherwise 0                                            */
@@ -266,6 +272,26 @@ int pf_set_timing(pf_plan *p, int enable);
  * direction `dir` since timing was enabled.
  */
 int pf_get_timing(pf_plan *p, int dir, int pass, double *total_ms, long long *count);
+
+/* ---- differentiable spectral step (Chebyshev third transform) ------------ */
+
+/*
+ * For a plan with third = PF_THIRD_CHEB (1 x 1, out-of-place): out = L in with
+ *   L u = s B( m * F(u) ),  F = pf_ftran_r2c, B = pf_btran_c2r,
+ *   m(kx, ky, kz) = i kx' * (-1 / (kx'^2 + ky'^2 + kz'^2)), m(0) = 0,
+ *   kx' = 2 pi kx / nx, ky' = 2 pi ky / ny (ky taken in -ny/2 .. ny/2),
+ *   kz' = pi kz / (nz - 1) (the DCT index read as a cosine-series wavenumber),
+ *   s = 1 / (nx ny 2 (nz - 1)),
+ * i.e. the x derivative of the inverse Laplacian in spectral space.  With
+ * adjoint = 1, out = L^T in for the real inner product, computed as
+ * s W B( conj(m) * F(W^-1 in) ) with W the DCT end-node weights along z
+ * (1 at z = 0 and nz - 1, 2 inside): the adjoint of the type-I DCT is
+ * W C W^-1, and the interior-mode factors of the R2C / C2R adjoints cancel.
+ * in, out: real [nz][ny][nx]; spec: complex Z-pencil buffer of the plan
+ * (caller-owned scratch, overwritten).  All distinct (PF_EALIAS), 16-byte
+ * aligned.  PF_EUNSUPPORTED for other plans.
+ */
+int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjoint, void *stream);
 
 /* ---- batched transforms ------------------------------------------------ */
 

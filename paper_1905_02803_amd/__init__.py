@@ -32,7 +32,7 @@ PF_EHIP = -7
 
 PF_F32, PF_F64 = 0, 1
 PF_PLAIN, PF_MFMA_FP16X2, PF_MFMA_BF16X2 = 0, 1, 2
-PF_THIRD_FFT, PF_THIRD_EMPTY = 0, 1
+PF_THIRD_FFT, PF_THIRD_EMPTY, PF_THIRD_CHEB = 0, 1, 2
 PF_PENCIL_X, PF_PENCIL_Y, PF_PENCIL_Z = 0, 1, 2
 PF_DIR_FORWARD, PF_DIR_BACKWARD = 0, 1
 PF_BATCH_SERIAL, PF_BATCH_FUSED, PF_BATCH_GRAPH = 0, 1, 2
@@ -42,7 +42,7 @@ EXPORTED = (
     "pf_set_workspace", "pf_ftran_r2c", "pf_btran_c2r", "pf_destroy", "pf_strerror", "pf_num_passes",
     "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
     "pf_batch_setup", "pf_batch_offset", "pf_batch_bytes", "pf_batch_set_mode", "pf_batch_ftran_r2c",
-    "pf_batch_btran_c2r", "pf_batch_destroy",
+    "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step",
 )
 
 
@@ -120,6 +120,7 @@ def lib():
             "pf_batch_ftran_r2c": (i, [vp, vp, vp, vp]),
             "pf_batch_btran_c2r": (i, [vp, vp, vp, vp]),
             "pf_batch_destroy": (i, [vp]),
+            "pf_spectral_step": (i, [vp, vp, vp, vp, i, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -361,6 +362,52 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def pf_spectral_step(h, in_ptr: int, spec_ptr: int, out_ptr: int, adjoint: int = 0, stream: int = 0) -> None:
+    _raise(lib().pf_spectral_step(h, in_ptr, spec_ptr, out_ptr, int(adjoint), stream), "pf_spectral_step")
+
+
+def spectral_step(plan, u, spec=None, adjoint: bool = False, stream=None):
+    """The plan's spectral step L (or its adjoint) on a real [nz][ny][nx] CUDA tensor (not differentiable;
+    see SpectralStep)."""
+    import torch
+
+    plan._check_tensor(u, plan.real_shape, plan.real_dtype, "input")
+    if spec is None:
+        spec = plan.empty_complex(u.device)
+    out = torch.empty_like(u)
+    pf_spectral_step(plan.handle, u.data_ptr(), spec.data_ptr(), out.data_ptr(), int(adjoint), _stream_handle(stream))
+    return out
+
+
+def _spectral_function():
+    import torch
+
+    class SpectralStep(torch.autograd.Function):
+        """Differentiable spectral step: forward L u, backward L^T g (both hand-written GPU passes)."""
+
+        @staticmethod
+        def forward(ctx, u, plan):
+            ctx.plan = plan
+            return spectral_step(plan, u.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            return spectral_step(ctx.plan, g.contiguous(), adjoint=True), None
+
+    return SpectralStep
+
+
+def spectral_step_autograd(u, plan):
+    """L u with gradients through the hand-written adjoint."""
+    global _SPEC_FN
+    if _SPEC_FN is None:
+        _SPEC_FN = _spectral_function()
+    return _SPEC_FN.apply(u, plan)
+
+
+_SPEC_FN = None
 
 
 def pf_batch_setup(dims, layout: Layout | None = None, tune=None) -> int:

@@ -88,7 +88,7 @@ bool valid_layout_values(const pf_layout *l) {
     if (l->precision != PF_F32 && l->precision != PF_F64) return false;
     if (l->math != PF_PLAIN && l->math != PF_MFMA_FP16X2 && l->math != PF_MFMA_BF16X2) return false;
     if (l->inplace != 0 && l->inplace != 1) return false;
-    if (l->third != PF_THIRD_FFT && l->third != PF_THIRD_EMPTY) return false;
+    if (l->third != PF_THIRD_FFT && l->third != PF_THIRD_EMPTY && l->third != PF_THIRD_CHEB) return false;
     if (l->share_only != 0 && l->share_only != 1) return false;
     if (l->share_only) {
         if (l->r1 < 0 || l->r1 >= l->m1 || l->r2 < 0 || l->r2 >= l->m2) return false;
@@ -189,9 +189,15 @@ int check_impl(int nx, int ny, int nz, const pf_layout *l) {
     // Eq. 2 read as: every rank's block of every pencil is non-empty.
     if (l->m1 > nxh || l->m1 > ny || l->m2 > ny || l->m2 > nz) return PF_EINVAL;
     FftSpec f;
-    if (!factor_length(nx, &f) || !factor_length(ny, &f) || !factor_length(nz, &f)) return PF_EUNSUPPORTED;
+    // under the Chebyshev third transform the z length transformed is 2 (nz - 1), checked below
+    const bool cheb = l->third == PF_THIRD_CHEB;
+    if (!factor_length(nx, &f) || !factor_length(ny, &f) || (!cheb && !factor_length(nz, &f))) return PF_EUNSUPPORTED;
     const int maxn = l->precision == PF_F64 ? 4096 : 8192;
     if (nx > maxn || ny > maxn || nz > maxn) return PF_EUNSUPPORTED;
+    if (cheb) {  // the DCT runs as a length 2 (nz - 1) transform
+        if (nz < 2) return PF_EINVAL;
+        if (!factor_length(2 * (nz - 1), &f) || 2 * (nz - 1) > maxn) return PF_EUNSUPPORTED;
+    }
     return PF_OK;
 }
 
@@ -206,7 +212,7 @@ int built_options(const pf_layout *l) {
 // 16-column blocks, 16-byte aligned rows), contiguous lines, and unaligned
 // rows (Side::v8).
 void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc,
-                    int tuned_tc = 0) {
+                    int tuned_tc = 0, bool p2_ok = true) {
     if (tuned_tc > 0 && tuned_tc < max_tc) max_tc = tuned_tc;
     d.dir = dir;
     d.prec = p->lay.precision;
@@ -215,7 +221,7 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
     a.fft = fs;
     a.tw = (const char *)p->tw_dev + twoff;
     a.C = p->nxh;
-    if (!p->opt.generic_only && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
+    if (p2_ok && !p->opt.generic_only && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
         // compile-time radix plan, persistent blocks (grid set once the tile count is known)
         d.kind = pf::PASS_C2C_P2;
         a.math = pf::p2_has_mfma(fs.n) ? p->lay.math : 0;
@@ -543,7 +549,9 @@ void build_passes(pf_plan *p) {
         const bool empty = p->lay.third == PF_THIRD_EMPTY;
         FftSpec fz = p->fz;
         if (empty) fz.nstages = 0;
-        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2]);
+        const bool cheb = p->lay.third == PF_THIRD_CHEB;  // type-I DCT by the even extension (generic kernel)
+        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], !cheb);
+        if (cheb) z.a.cheb = p->nz;
         if (empty && z.kind == pf::PASS_C2C_P2) z.a.math = 3;  // the power-of-two kernel's reorder-only form
         z.a.A = p->ny;
         z.a.CB = (long long)p->nkb * (p->B >> z.a.tc_log2);
@@ -757,7 +765,7 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     p->nkb = (p->nxh + p->B - 1) / p->B;
     factor_length(nx, &p->fx, o.radix_order[0]);
     factor_length(ny, &p->fy, o.radix_order[1]);
-    factor_length(nz, &p->fz, o.radix_order[2]);
+    factor_length(l->third == PF_THIRD_CHEB ? 2 * (nz - 1) : nz, &p->fz, o.radix_order[2]);
 
     // twiddle tables, one allocation, each table 256-byte aligned
     std::vector<unsigned char> host;
@@ -933,6 +941,31 @@ int pf_copy(void *dst, const void *src, size_t bytes, void *stream) {
     if (!dst || !src) return PF_EINVAL;
     if (!aligned16(dst) || !aligned16(src) || (bytes & 15u)) return PF_EALIGN;
     return hip_status(pf::launch_copy(src, dst, bytes, (hipStream_t)stream));
+}
+
+int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjoint, void *stream) {
+    if (!p || !in || !spec || !out || (adjoint != 0 && adjoint != 1)) return PF_EINVAL;
+    if (p->lay.third != PF_THIRD_CHEB || p->blocked || p->share || p->lay.inplace) return PF_EUNSUPPORTED;
+    if (!aligned16(in) || !aligned16(spec) || !aligned16(out)) return PF_EALIGN;
+    if (in == spec || spec == out || in == out) return PF_EALIAS;
+    hipStream_t s = (hipStream_t)stream;
+    const int f64 = p->lay.precision == PF_F64;
+    pf::SpecArgs a;
+    a.U = spec;
+    a.nx = p->nx, a.ny = p->ny, a.nz = p->nz, a.nxh = p->nxh, a.stride1 = p->lay.stride1, a.f64 = f64;
+    a.conj = adjoint;
+    a.scale = 1.0 / ((double)p->nx * p->ny * 2.0 * (p->nz - 1));
+    const void *src = in;
+    if (adjoint) {  // out = in / w(z): the adjoint of the type-I DCT is w C w^-1
+        const hipError_t e = pf::launch_zweight(in, out, p->nx, p->ny, p->nz, f64, -1, s);
+        if (e != hipSuccess) return hip_status(e);
+        src = out;
+    }
+    int r = run_chain(p, 0, src, spec, stream);
+    if (!r) r = hip_status(pf::launch_spec_mul(a, s));
+    if (!r) r = run_chain(p, 1, spec, out, stream);
+    if (!r && adjoint) r = hip_status(pf::launch_zweight(out, out, p->nx, p->ny, p->nz, f64, +1, s));
+    return r;
 }
 
 int pf_set_timing(pf_plan *p, int enable) {

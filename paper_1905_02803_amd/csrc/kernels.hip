@@ -124,31 +124,35 @@ __device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp
     cx<T> *__restrict__ out = reinterpret_cast<cx<T> *>(outp);
     const int rows_per = (nthr >> a.tc_log2) > 0 ? (nthr >> a.tc_log2) : 1;
 
+    // type-I DCT (a.cheb > 0): point p of the even extension is source point p or n - p
+    const int cheb = a.cheb;
+    auto src = [cheb, n](int p) { return cheb > 0 && p >= cheb ? n - p : p; };
     if (a.in_s.sc == 1) {  // rows of the tile are contiguous: column fastest
         const int c = tid & (TC - 1);
         if (c < ncol)
             for (int p = tid >> a.tc_log2; p < n; p += rows_per)
-                lds[c * pitch + pidx(p)] = in[ib + c + (long long)p * a.in_s.sp];
+                lds[c * pitch + pidx(p)] = in[ib + c + (long long)src(p) * a.in_s.sp];
     } else {  // columns are contiguous lines: point fastest
         const int c = tid >> a.wpc_log2;
         if (c < ncol)
             for (int p = tid & (wpc - 1); p < n; p += wpc)
-                lds[c * pitch + pidx(p)] = in[ib + (long long)c * a.in_s.sc + (long long)p * a.in_s.sp];
+                lds[c * pitch + pidx(p)] = in[ib + (long long)c * a.in_s.sc + (long long)src(p) * a.in_s.sp];
     }
     __syncthreads();
     const int col = tid >> a.wpc_log2;
     const bool act = col < TC;
     fft_lds<T, DIR>(lds + (act ? col : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
                     act ? (tid & (wpc - 1)) : n, wpc);
+    const int nout = cheb > 0 ? cheb : n;  // the DCT keeps outputs 0 .. cheb - 1
     if (a.out_s.sc == 1) {
         const int c = tid & (TC - 1);
         if (c < ncol)
-            for (int p = tid >> a.tc_log2; p < n; p += rows_per)
+            for (int p = tid >> a.tc_log2; p < nout; p += rows_per)
                 out[ob + c + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
     } else {
         const int c = tid >> a.wpc_log2;
         if (c < ncol)
-            for (int p = tid & (wpc - 1); p < n; p += wpc)
+            for (int p = tid & (wpc - 1); p < nout; p += wpc)
                 out[ob + (long long)c * a.out_s.sc + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
     }
 }
@@ -481,6 +485,74 @@ hipError_t launch_box(const BoxArgs &b, hipStream_t s) {
     if (rows <= 0 || b.s0 <= 0) return hipSuccess;
     if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_box, dim3((unsigned)rows), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// ---- spectral step: the diagonal multiplier and the DCT end-node weights ---
+template <typename T>
+__global__ __launch_bounds__(256) void k_spec_mul(SpecArgs a) {
+    const long long total = (long long)a.nxh * a.ny * a.nz;
+    cx<T> *U = reinterpret_cast<cx<T> *>(a.U);
+    const double two_pi = 6.283185307179586476925286766559;
+    const double pi = 3.1415926535897932384626433832795;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        int kx, ky, kz;
+        if (a.stride1) {  // [kx][ky][kz]
+            kz = (int)(e % a.nz);
+            const long long r = e / a.nz;
+            ky = (int)(r % a.ny);
+            kx = (int)(r / a.ny);
+        } else {  // [kz][ky][kx]
+            kx = (int)(e % a.nxh);
+            const long long r = e / a.nxh;
+            ky = (int)(r % a.ny);
+            kz = (int)(r / a.ny);
+        }
+        const int kys = 2 * ky <= a.ny ? ky : ky - a.ny;
+        const double kxr = two_pi * kx / a.nx, kyr = two_pi * kys / a.ny, kzr = pi * kz / (a.nz - 1);
+        const double k2 = kxr * kxr + kyr * kyr + kzr * kzr;
+        const double mu = k2 > 0.0 ? -a.scale * kxr / k2 : 0.0;  // m = i mu
+        const double sg = a.conj ? -1.0 : 1.0;
+        const cx<T> u = U[e];
+        // u * (i sg mu) = (-sg mu u.y, sg mu u.x)
+        U[e] = cmk<T>((T)(-sg * mu * (double)u.y), (T)(sg * mu * (double)u.x));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zweight(const T *__restrict__ src, T *__restrict__ dst, int plane, int nz,
+                                                 int e) {
+    const long long total = (long long)plane * nz;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(i / plane);
+        const T w = (z == 0 || z == nz - 1) ? T(1) : (e > 0 ? T(2) : T(0.5));
+        dst[i] = src[i] * w;
+    }
+}
+
+static unsigned grid_for(long long total) {
+    const long long b = (total + 255) / 256;
+    return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+hipError_t launch_spec_mul(const SpecArgs &a, hipStream_t s) {
+    const long long total = (long long)a.nxh * a.ny * a.nz;
+    if (a.f64) hipLaunchKernelGGL(k_spec_mul<double>, dim3(grid_for(total)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_spec_mul<float>, dim3(grid_for(total)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zweight(const void *src, void *dst, int nx, int ny, int nz, int f64, int e, hipStream_t s) {
+    const int plane = nx * ny;
+    const long long total = (long long)plane * nz;
+    if (f64)
+        hipLaunchKernelGGL(k_zweight<double>, dim3(grid_for(total)), dim3(256), 0, s,
+                           reinterpret_cast<const double *>(src), reinterpret_cast<double *>(dst), plane, nz, e);
+    else
+        hipLaunchKernelGGL(k_zweight<float>, dim3(grid_for(total)), dim3(256), 0, s,
+                           reinterpret_cast<const float *>(src), reinterpret_cast<float *>(dst), plane, nz, e);
     return hipGetLastError();
 }
 

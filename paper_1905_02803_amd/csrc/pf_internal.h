@@ -102,6 +102,8 @@ struct PassArgs {
                     // 3 (C2C pass) no transform: the reorder alone
     int tile_order; // power-of-two C2C pass: 0 tile t = (t / CB, t % CB), 1 tile t = (t % A, t / A)
     int xcd;        // power-of-two C2C pass: 1 to give each XCD runs of consecutive tiles
+    int cheb;       // generic C2C pass: > 0 = lines of cheb points, transformed as their even
+                    // extension of length fft.n = 2 (cheb - 1) (type-I DCT); 0 = plain
     // X passes: real lines (y, z) flattened as g = z * ny + y; line g's spectrum
     // is workspace row (z nkb + kb) ypitch + y0 + y of column block kb
     long long lines;
@@ -145,6 +147,19 @@ struct BatchLaunch {
 };
 
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t s);
+
+// Spectral step on a Chebyshev-third Z-pencil half spectrum U (layout of the
+// plan): U *= m or conj(m), m = scale * i kx' (-1 / (kx'^2 + ky'^2 + kz'^2)),
+// kx' = 2 pi kx / nx, ky' = 2 pi ky / ny (ky signed), kz' = pi kz / (nz - 1);
+// m = 0 at k = 0.
+struct SpecArgs {
+    void *U;
+    int nx, ny, nz, nxh, stride1, f64, conj;
+    double scale;
+};
+hipError_t launch_spec_mul(const SpecArgs &a, hipStream_t s);
+// dst[z][y][x] = src[z][y][x] * w(z)^e, w = 1 at z = 0 and nz - 1, else 2; e = +1 or -1
+hipError_t launch_zweight(const void *src, void *dst, int nx, int ny, int nz, int f64, int e, hipStream_t s);
 
 // Allow every kernel instantiation up to max_lds bytes of dynamic LDS.
 hipError_t prepare_kernels(size_t max_lds);

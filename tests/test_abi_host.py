@@ -184,3 +184,13 @@ def test_batch_setup_rejects_bad_arguments_before_touching_the_gpu():
     assert pf.pf_batch_bytes(None, 0) == 0
     assert pf.lib().pf_batch_set_mode(None, 1) == pf.PF_EINVAL
     assert pf.lib().pf_batch_ftran_r2c(None, None, None, None) == pf.PF_EINVAL
+
+
+def test_cheb_third_transform_lengths():
+    """Under the Chebyshev third transform z is transformed at length 2 (nz - 1): nz itself may be prime."""
+    cheb = pf.Layout(third=pf.PF_THIRD_CHEB)
+    assert pf.pf_check(16, 16, 17, cheb) == pf.PF_OK
+    assert pf.pf_check(16, 16, 257, cheb) == pf.PF_OK
+    assert pf.pf_check(16, 16, 17) == pf.PF_EUNSUPPORTED
+    assert pf.pf_check(16, 16, 1, cheb) == pf.PF_EINVAL
+    assert pf.pf_check(16, 16, 12, cheb) == pf.PF_EUNSUPPORTED  # 2 * 11

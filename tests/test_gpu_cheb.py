@@ -1,0 +1,123 @@
+"""Chebyshev third transform (type-I DCT along z on nz Gauss-Lobatto points,
+Sec. 3.1) and the differentiable spectral step built on it.
+
+* The transforms match the oracle's X-Y-DCT composition (itself pinned to
+  scipy and closed forms on the CPU) in FP32 and FP64, both Z-pencil layouts.
+* The step L u = s B(m F(u)) matches the same composition with the
+  multiplier applied in numpy.
+* Its hand-written adjoint satisfies <L u, g> = <u, L^T g> to rounding, equals
+  the transpose of the explicitly assembled matrix on a tiny grid, and passes
+  torch.autograd.gradcheck (finite differences) on the 16 x 16 x 17 grid.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1905_02803_amd as pf  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+SHAPES = [(17, 16, 16), (9, 7, 15), (33, 20, 24), (257, 8, 12), (65, 30, 1024), (5, 256, 32), (2, 6, 10)]
+
+
+@pytest.mark.parametrize("stride1", [1, 0])
+@pytest.mark.parametrize("prec", [pf.PF_F32, pf.PF_F64])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda v: "x".join(map(str, v)))
+def test_cheb_transform_matches_oracle(shape, prec, stride1):
+    nz, ny, nx = shape
+    print(f"case shape={shape} prec={prec} stride1={stride1}", flush=True)
+    tol = 1e-12 if prec == pf.PF_F64 else 1e-6
+    rdt = np.float64 if prec == pf.PF_F64 else np.float32
+    cdt = np.complex128 if prec == pf.PF_F64 else np.complex64
+    u = synth.uniform(60 + nz, shape).astype(rdt)
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=prec, stride1=stride1, third=pf.PF_THIRD_CHEB)) as plan:
+        got = plan.ftran(torch.from_numpy(u).cuda()).cpu().numpy()
+        ref = oracle.r2c3d_cheb(u)
+        assert rel(got, oracle.to_stride1(ref) if stride1 else ref) < tol
+        V = synth.complex_half(61 + nz, (nz, ny, nx // 2 + 1)).astype(cdt)
+        back = plan.btran(torch.from_numpy(oracle.to_stride1(V) if stride1 else V).cuda()).cpu().numpy()
+        assert rel(back, oracle.c2r3d_cheb(V, nx)) < tol
+        # round trip: nx ny 2 (nz - 1) u
+        rt = plan.btran(plan.ftran(torch.from_numpy(u).cuda())).cpu().numpy()
+        assert rel(rt, u * nx * ny * 2 * (nz - 1)) < tol
+
+
+def multiplier(nx, ny, nz):
+    """m on [nz][ny][nxh] (numpy), s folded in."""
+    kx = 2 * np.pi * np.arange(nx // 2 + 1) / nx
+    ky = 2 * np.pi * np.fft.fftfreq(ny, 1.0 / ny) / ny
+    kz = np.pi * np.arange(nz) / (nz - 1)
+    k2 = kx[None, None, :] ** 2 + ky[None, :, None] ** 2 + kz[:, None, None] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mu = np.where(k2 > 0, -kx[None, None, :] / k2, 0.0)
+    return 1j * mu / (nx * ny * 2.0 * (nz - 1))
+
+
+@pytest.mark.parametrize("stride1", [1, 0])
+@pytest.mark.parametrize("shape", [(17, 16, 16), (33, 24, 20), (9, 12, 64)])
+def test_spectral_step_matches_oracle(shape, stride1):
+    nz, ny, nx = shape
+    u = synth.uniform(70, shape)
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F64, stride1=stride1, third=pf.PF_THIRD_CHEB)) as plan:
+        got = pf.spectral_step(plan, torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = oracle.c2r3d_cheb(oracle.r2c3d_cheb(u) * multiplier(nx, ny, nz), nx)
+    assert rel(got, ref) < 1e-12
+
+
+def test_adjoint_dot_product_and_explicit_transpose():
+    nz, ny, nx = 9, 8, 10
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F64, third=pf.PF_THIRD_CHEB)) as plan:
+        rng = np.random.default_rng(3)
+        for _ in range(3):
+            u = torch.from_numpy(rng.standard_normal((nz, ny, nx))).cuda()
+            g = torch.from_numpy(rng.standard_normal((nz, ny, nx))).cuda()
+            Lu = pf.spectral_step(plan, u)
+            Ltg = pf.spectral_step(plan, g, adjoint=True)
+            a, b = float((Lu * g).sum()), float((u * Ltg).sum())
+            assert abs(a - b) <= 1e-12 * max(abs(a), abs(b), float(Lu.norm() * g.norm()))
+    nz, ny, nx = 5, 4, 4
+    n = nz * ny * nx
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F64, third=pf.PF_THIRD_CHEB)) as plan:
+        E = torch.eye(n, dtype=torch.float64, device="cuda")
+        A = torch.stack([pf.spectral_step(plan, E[i].reshape(nz, ny, nx)).reshape(-1) for i in range(n)], 1)
+        At = torch.stack([pf.spectral_step(plan, E[i].reshape(nz, ny, nx), adjoint=True).reshape(-1)
+                          for i in range(n)], 1)
+        assert float((At - A.T).abs().max()) <= 1e-13 * float(A.abs().max())
+        assert float(A.abs().max()) > 0
+
+
+def test_gradcheck_16x16x17():
+    nz, ny, nx = 17, 16, 16
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F64, third=pf.PF_THIRD_CHEB)) as plan:
+        u = torch.from_numpy(synth.uniform(80, (nz, ny, nx))).cuda().requires_grad_(True)
+        assert torch.autograd.gradcheck(lambda v: pf.spectral_step_autograd(v, plan), (u,), eps=1e-6, atol=1e-9,
+                                        rtol=1e-7, fast_mode=True)
+        # the gradient of a scalar loss equals L^T of its seed
+        y = pf.spectral_step_autograd(u, plan)
+        w = torch.randn_like(y)
+        (y * w).sum().backward()
+        assert torch.allclose(u.grad, pf.spectral_step(plan, w, adjoint=True), rtol=0, atol=1e-14 * float(w.norm()))
+
+
+@pytest.mark.timeout(600)
+def test_512x512x257_config_matches_oracle():
+    """The benchmark's own Chebyshev grid (FP32, GRF-like data): forward transform and the step."""
+    nz, ny, nx = 257, 512, 512
+    print("case 512x512x257 FP32", flush=True)
+    u = synth.uniform(90, (nz, ny, nx)).astype(np.float32)
+    with pf.Plan(nx, ny, nz, pf.Layout(third=pf.PF_THIRD_CHEB)) as plan:
+        ud = torch.from_numpy(u).cuda()
+        got = plan.ftran(ud).cpu().numpy()
+        step = pf.spectral_step(plan, ud).cpu().numpy()
+    U = oracle.r2c3d_cheb(u)
+    assert rel(got, oracle.to_stride1(U)) < 1e-6
+    ref = oracle.c2r3d_cheb(U * multiplier(nx, ny, nz), nx)
+    assert rel(step, ref) < 1e-6
