@@ -311,6 +311,63 @@ def batch_timing(pf, args, dev, stream, count=64, seed=4, check=True):
     return out
 
 
+def spectral_timing(pf, args, dev, stream, nx=512, ny=512, nz=257):
+    """The differentiable spectral step on the 512 x 512 x 257 Chebyshev grid (FP32): L u, L^T g and one
+    autograd forward + backward; per-pass times of the plan's transforms (the type-I DCT runs as the generic
+    kernel on the even extension, length 2 (nz - 1) = 512)."""
+    import torch
+
+    plan = pf.Plan(nx, ny, nz, pf.Layout(third=pf.PF_THIRD_CHEB))
+    u = (torch.rand((nz, ny, nx), generator=torch.Generator(device=dev).manual_seed(5), device=dev) * 2 - 1)
+    spec = plan.empty_complex(dev)
+    out = {"grid": [nx, ny, nz], "third": "type-I DCT (Chebyshev) along z"}
+
+    def timeit(fn):
+        for _ in range(args.warmup):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    out["ms_step"] = timeit(lambda: pf.spectral_step(plan, u, spec))
+    out["ms_adjoint"] = timeit(lambda: pf.spectral_step(plan, u, spec, adjoint=True))
+    ug = u.clone().requires_grad_(True)
+
+    def fb():
+        ug.grad = None
+        pf.spectral_step_autograd(ug, plan).sum().backward()
+
+    out["ms_autograd_fwd_bwd"] = timeit(fb)
+    U = plan.empty_complex(dev)
+    r = plan.empty_real(dev)
+    for _ in range(args.warmup):
+        plan.ftran(u, U)
+        plan.btran(U, r)
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        plan.ftran(u, U)
+        plan.btran(U, r)
+    torch.cuda.synchronize()
+    passes = []
+    for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD):
+        for i in range(plan.num_passes(d)):
+            tot, cnt = plan.get_timing(d, i)
+            avg = tot / max(cnt, 1)
+            nbytes = plan.pass_bytes(d, i)
+            passes.append({"pass": plan.pass_name(d, i), "avg_ms": avg, "alg_GBps": nbytes / (avg * 1e-3) / 1e9})
+    plan.set_timing(False)
+    out["passes"] = passes
+    plan.destroy()
+    return out
+
+
 def share_only_timing(pf, nx, ny, nz, args, dev, stream, m2=8, r2=3):
     """One rank's share of the grid on a 1 x m2 slab grid (share-only plan): per-pass times."""
     import torch
@@ -455,6 +512,7 @@ def main():
         pm.destroy()
     layouts = layout_timings(pf, nx, ny, nz, args, dev, stream, u)
     batched = batch_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
+    spectral = spectral_timing(pf, args, dev, stream)
     share = share_only_timing(pf, nx, ny, nz, args, dev, stream)
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
@@ -505,6 +563,7 @@ def main():
         "share_only": share,
         "layouts": layouts,
         "batched": batched,
+        "spectral_step": spectral,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
     }

@@ -343,8 +343,9 @@ size_t pf_batch_bytes(const pf_batch *b, int which);
  * mode: PF_BATCH_SERIAL or PF_BATCH_FUSED, optionally | PF_BATCH_GRAPH: the
  * first call of a direction with given buffers captures its launches into a
  * hipGraph (on a stream of the batch's own) and every call replays it on the
- * caller's stream; new buffers are captured again (after the caller's stream
- * has drained the old graph).  Returns PF_EINVAL for other values.
+ * caller's stream; new buffers or a new mode are captured again (after the
+ * caller's stream has drained the old graph).  Returns PF_EINVAL for other
+ * values.
  */
 int pf_batch_set_mode(pf_batch *b, int mode);
 

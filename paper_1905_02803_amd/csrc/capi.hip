@@ -3,6 +3,7 @@
 // chain behind the C ABI of include/pencilfft.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -1001,12 +1002,14 @@ struct pf_batch {
     size_t rbytes = 0, cbytes = 0;
     void *ws = nullptr;
     void *tables = nullptr;  // device PassArgs tables and block prefixes of the fused passes
-    pf::BatchLaunch launch[2][3];
+    // fused passes: per (direction, pass) one launch per block size (threads) in the batch
+    std::vector<pf::BatchLaunch> launch[2][3];
     int mode = PF_BATCH_FUSED;
     hipStream_t cap = nullptr;  // capture stream for the graph modes
     struct Graph {
         const void *in = nullptr;
         void *out = nullptr;
+        int mode = -1;  // the mode the launches were captured in
         hipGraphExec_t exec = nullptr;
     } graph[2];
 };
@@ -1029,13 +1032,13 @@ void batch_free(pf_batch *b) {
 // Enqueue one direction of the batch on stream s in the current mode (graphs aside).
 int batch_issue(pf_batch *b, int dir, const void *in, void *out, hipStream_t s) {
     if (b->mode & PF_BATCH_FUSED) {
-        for (int k = 0; k < 3; ++k) {
-            pf::BatchLaunch L = b->launch[dir][k];
-            L.b.user_in = (const char *)in;
-            L.b.user_out = (char *)out;
-            const hipError_t e = pf::launch_batch(L, s);
-            if (e != hipSuccess) return hip_status(e);
-        }
+        for (int k = 0; k < 3; ++k)
+            for (pf::BatchLaunch L : b->launch[dir][k]) {
+                L.b.user_in = (const char *)in;
+                L.b.user_out = (char *)out;
+                const hipError_t e = pf::launch_batch(L, s);
+                if (e != hipSuccess) return hip_status(e);
+            }
         return PF_OK;
     }
     const bool fwd = dir == 0;
@@ -1055,8 +1058,8 @@ int batch_run(pf_batch *b, int dir, const void *in, void *out, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (!(b->mode & PF_BATCH_GRAPH)) return batch_issue(b, dir, in, out, s);
     pf_batch::Graph &g = b->graph[dir];
-    if (!g.exec || g.in != in || g.out != out) {
-        if (g.exec) {  // buffers changed: capture again once the old graph has finished
+    if (!g.exec || g.in != in || g.out != out || g.mode != b->mode) {
+        if (g.exec) {  // buffers or mode changed: capture again once the old graph has finished
             if (hipStreamSynchronize(s) != hipSuccess) return PF_EHIP;
             (void)hipGraphExecDestroy(g.exec);
             g.exec = nullptr;
@@ -1078,6 +1081,7 @@ int batch_run(pf_batch *b, int dir, const void *in, void *out, void *stream) {
         }
         g.in = in;
         g.out = out;
+        g.mode = b->mode;
     }
     return hip_status(hipGraphLaunch(g.exec, s));
 }
@@ -1135,58 +1139,77 @@ int pf_batch_setup(int count, const int *dims, const pf_layout *l, const pf_tune
         b->plans[i]->ws = (char *)b->ws + woff[i];
         b->plans[i]->own_ws = false;
     }
-    // fused passes: per (direction, pass) a PassArgs table and the block prefix
-    const size_t tab = align256(count * sizeof(PassArgs)), pre = align256((count + 1) * sizeof(long long));
+    // fused passes: per (direction, pass) a PassArgs table and block prefixes.
+    // Transforms are grouped by block size (sorted, largest first), one launch
+    // per group: a transform tuned to narrow tiles keeps its own small blocks
+    // instead of running in the largest block of the batch with most lanes idle.
+    const size_t tab = align256(count * sizeof(PassArgs)), pre = align256((2 * count + 1) * sizeof(long long));
     if (hipMalloc(&b->tables, 6 * (tab + pre)) != hipSuccess) {
         b->tables = nullptr;
         batch_free(b);
         return PF_ENOMEM;
     }
     std::vector<unsigned char> host(6 * (tab + pre), 0);
+    std::vector<int> order(count);
     for (int dir = 0; dir < 2; ++dir)
         for (int k = 0; k < 3; ++k) {
             const size_t at = (size_t)(dir * 3 + k) * (tab + pre);
             PassArgs *A = reinterpret_cast<PassArgs *>(host.data() + at);
             long long *F = reinterpret_cast<long long *>(host.data() + at + tab);
-            pf::BatchLaunch &L = b->launch[dir][k];
-            std::memset(&L, 0, sizeof(L));
+            const PassArgs *Adev = reinterpret_cast<const PassArgs *>((char *)b->tables + at);
+            const long long *Fdev = reinterpret_cast<const long long *>((char *)b->tables + at + tab);
             // user side of this pass: forward X reads / backward X writes the real
             // arrays; forward Z writes / backward Z reads the complex arrays
             const bool xpass = (dir == 0 && k == 0) || (dir == 1 && k == 2);
-            const bool zpass = (dir == 0 && k == 2) || (dir == 1 && k == 0);
-            L.b.in_user = (dir == 0 && k == 0) || (dir == 1 && k == 0);
-            L.b.out_user = (dir == 0 && k == 2) || (dir == 1 && k == 2);
-            long long blocks = 0;
+            const int in_user = k == 0, out_user = k == 2;
             for (int i = 0; i < count; ++i) {
-                const PassDesc &d = b->plans[i]->pass[dir][k];
-                if (i == 0) {
-                    L.kind = d.kind;
-                    L.dir = d.dir;
-                    L.prec = d.prec;
-                } else if (d.kind != L.kind) {
+                order[i] = i;
+                if (b->plans[i]->pass[dir][k].kind != b->plans[0]->pass[dir][k].kind) {
                     batch_free(b);
                     return PF_EUNSUPPORTED;
                 }
-                A[i] = d.a;
-                char *w = (char *)b->plans[i]->ws;
-                const size_t uoff = xpass ? b->roff[i] : b->coff[i];
-                A[i].in = L.b.in_user ? (const void *)uoff : (const void *)w;
-                A[i].out = L.b.out_user ? (void *)uoff : (void *)w;
-                (void)zpass;
-                F[i] = blocks;
-                blocks += d.blocks;
-                L.threads = std::max(L.threads, d.threads);
-                L.lds = std::max(L.lds, d.lds);
             }
-            F[count] = blocks;
-            if (blocks > 0x7fffffffLL) {
-                batch_free(b);
-                return PF_EUNSUPPORTED;
+            std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+                return b->plans[u]->pass[dir][k].threads > b->plans[v]->pass[dir][k].threads;
+            });
+            int f = 0;  // next free prefix slot
+            for (int j = 0; j < count;) {
+                const unsigned thr = b->plans[order[j]]->pass[dir][k].threads;
+                pf::BatchLaunch L;
+                std::memset(&L, 0, sizeof(L));
+                const PassDesc &d0 = b->plans[order[j]]->pass[dir][k];
+                L.kind = d0.kind;
+                L.dir = d0.dir;
+                L.prec = d0.prec;
+                L.threads = thr;
+                L.b.in_user = in_user;
+                L.b.out_user = out_user;
+                L.b.args = Adev + j;
+                L.b.first = Fdev + f;
+                long long blocks = 0;
+                int n = 0;
+                for (; j < count && b->plans[order[j]]->pass[dir][k].threads == thr; ++j, ++n) {
+                    const int i = order[j];
+                    const PassDesc &d = b->plans[i]->pass[dir][k];
+                    A[j] = d.a;
+                    char *w = (char *)b->plans[i]->ws;
+                    const size_t uoff = xpass ? b->roff[i] : b->coff[i];
+                    A[j].in = in_user ? (const void *)uoff : (const void *)w;
+                    A[j].out = out_user ? (void *)uoff : (void *)w;
+                    F[f + n] = blocks;
+                    blocks += d.blocks;
+                    L.lds = std::max(L.lds, d.lds);
+                }
+                F[f + n] = blocks;
+                f += n + 1;
+                if (blocks > 0x7fffffffLL) {
+                    batch_free(b);
+                    return PF_EUNSUPPORTED;
+                }
+                L.blocks = (unsigned)blocks;
+                L.b.count = n;
+                b->launch[dir][k].push_back(L);
             }
-            L.blocks = (unsigned)blocks;
-            L.b.args = reinterpret_cast<const PassArgs *>((char *)b->tables + at);
-            L.b.first = reinterpret_cast<const long long *>((char *)b->tables + at + tab);
-            L.b.count = count;
         }
     if (hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {

@@ -98,6 +98,13 @@ def test_all_modes_agree_bitwise_and_graph_replays():
                 assert junk.isfinite()
                 assert torch.equal(C2, ref_c), (mode, rep)
                 assert torch.equal(R2, ref_r), (mode, rep)
+        # a graph captured in one mode is not replayed in another: fused launches after serial ones
+        b.set_mode(pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH)
+        b.ftran(R, C2)
+        b.set_mode(pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH)
+        b.ftran(R, C2)
+        torch.cuda.synchronize()
+        assert torch.equal(C2, ref_c)
         # new buffers: the graph is captured again
         b.set_mode(pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH)
         R3 = R.clone()
@@ -115,7 +122,15 @@ def test_tuned_plans_match_oracle():
             for _ in dims]
     print(f"case batch dims={dims} tune={tune}", flush=True)
     with pf.Batch(dims, tune=tune) as b:
-        check_batch(b, 1e-6)
+        R, C, Cin, Rout = check_batch(b, 1e-6)
+        # the fused passes split into one launch per block size here; serial
+        # per-transform chains must give the same bits
+        b.set_mode(pf.PF_BATCH_SERIAL)
+        C2, R2 = torch.zeros_like(C), torch.zeros_like(Rout)
+        b.ftran(R, C2)
+        b.btran(Cin, R2)
+        torch.cuda.synchronize()
+        assert torch.equal(C2, C) and torch.equal(R2, Rout)
     with pf.Batch(dims, pf.Layout(precision=pf.PF_F64), tune=tune) as b:
         check_batch(b, 1e-12)
 
