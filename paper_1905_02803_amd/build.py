@@ -29,13 +29,17 @@ def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
     bdir = os.path.join(os.path.dirname(out), "_build")
     os.makedirs(bdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:  # the sources compile concurrently
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmd = [HIPCC] + FLAGS + list(extra) + inc + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     if verbose:

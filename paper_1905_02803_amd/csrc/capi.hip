@@ -213,7 +213,7 @@ int built_options(const pf_layout *l) {
 // 16-column blocks, 16-byte aligned rows), contiguous lines, and unaligned
 // rows (Side::v8).
 void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc,
-                    int tuned_tc = 0, bool p2_ok = true) {
+                    int tuned_tc = 0) {
     if (tuned_tc > 0 && tuned_tc < max_tc) max_tc = tuned_tc;
     d.dir = dir;
     d.prec = p->lay.precision;
@@ -222,7 +222,7 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
     a.fft = fs;
     a.tw = (const char *)p->tw_dev + twoff;
     a.C = p->nxh;
-    if (p2_ok && !p->opt.generic_only && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
+    if (!p->opt.generic_only && pf::p2_supported(fs.n, p->lay.precision) && pf::p2_tc(fs.n) <= max_tc) {
         // compile-time radix plan, persistent blocks (grid set once the tile count is known)
         d.kind = pf::PASS_C2C_P2;
         a.math = pf::p2_has_mfma(fs.n) ? p->lay.math : 0;
@@ -550,9 +550,10 @@ void build_passes(pf_plan *p) {
         const bool empty = p->lay.third == PF_THIRD_EMPTY;
         FftSpec fz = p->fz;
         if (empty) fz.nstages = 0;
-        const bool cheb = p->lay.third == PF_THIRD_CHEB;  // type-I DCT by the even extension (generic kernel)
-        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], !cheb);
+        const bool cheb = p->lay.third == PF_THIRD_CHEB;  // type-I DCT by the even extension
+        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2]);
         if (cheb) z.a.cheb = p->nz;
+        if (cheb && z.kind == pf::PASS_C2C_P2) z.a.math = 4;  // mirrored loads, the first nz points stored
         if (empty && z.kind == pf::PASS_C2C_P2) z.a.math = 3;  // the power-of-two kernel's reorder-only form
         z.a.A = p->ny;
         z.a.CB = (long long)p->nkb * (p->B >> z.a.tc_log2);
@@ -815,7 +816,7 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     int dev = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    for (int n : {ny, nz})
+    for (int n : {ny, p->fz.n})
         if (e == hipSuccess && pf::p2_supported(n, l->precision)) e = pf::p2_prepare(n);
     if (e == hipSuccess && p->fast_x) e = pf::p2x_prepare(nx);
     if (e != hipSuccess) {

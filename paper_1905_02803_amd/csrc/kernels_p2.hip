@@ -408,6 +408,15 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     const int ntiles = (int)(a.A * a.CB);
     const long long in_step = a.in_s.sp * T;
     const long long out_step = a.out_s.sp * T;
+    // MT == 4, the type-I DCT of the a.cheb = N / 2 + 1 points of a side line
+    // (Sec. 3.1) as the N-point DFT of its even extension: point j of the
+    // extension is stored point j or N - j, and only points j < a.cheb are written
+    constexpr bool CH = MT == 4;
+    const int nsrc = CH ? a.cheb : N;
+    // offset of extension point j from the address of point q (q = j mod T)
+    auto ext = [&](int j, int q, long long sp) -> long long {
+        return (long long)((CH && j >= nsrc ? N - j : j) - q) * sp;
+    };
 
     // element (column 2 cp, point q) of tile t on a side, and the valid column count
     const int A = (int)a.A;
@@ -429,11 +438,14 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
         if constexpr (INP == 1) {  // two lines, 8 bytes per lane each
             if (2 * cp_in < ncol) {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) d0[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + m * in_step);
+                for (int m = 0; m < 16; ++m)
+                    d0[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + (CH ? ext(q_in + T * m, q_in, 1) : m * in_step));
             }
             if (2 * cp_in + 1 < ncol) {
 #pragma unroll
-                for (int m = 0; m < 16; ++m) d1[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + a.in_s.sc + m * in_step);
+                for (int m = 0; m < 16; ++m)
+                    d1[m] = gld<streamed<LD_C2C_POINTS>()>(in + b + a.in_s.sc +
+                                                           (CH ? ext(q_in + T * m, q_in, 1) : m * in_step));
             }
         } else if constexpr (INP == 2) {
             // rows not 16-byte aligned: 8-byte column accesses, each instruction
@@ -445,17 +457,24 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
             const int col = 2 * cp_in + (odd ? 1 : 0);
             if (col < ncol) {
                 const long long e = b + (odd ? a.in_s.sc - a.in_s.sp : 0);  // column col, row q & ~1
+                const int q0 = q_in & ~1;
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
-                    d0[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + m * in_step);
-                    d1[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + a.in_s.sp + m * in_step);
+                    if constexpr (CH) {
+                        d0[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + ext(q0 + T * m, q0, a.in_s.sp));
+                        d1[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + ext(q0 + 1 + T * m, q0, a.in_s.sp));
+                    } else {
+                        d0[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + m * in_step);
+                        d1[m] = gld<streamed<LD_C2C_ROWS>()>(in + e + a.in_s.sp + m * in_step);
+                    }
                 }
             }
         } else if (2 * cp_in < ncol) {  // rows: both columns in one 16-byte load
             // a partially valid pair only occurs on a side padded to whole 16-column blocks
 #pragma unroll
             for (int m = 0; m < 16; ++m) {
-                const float4 x = gld<streamed<LD_C2C_ROWS>()>(reinterpret_cast<const float4 *>(in + b + m * in_step));
+                const long long o = CH ? ext(q_in + T * m, q_in, a.in_s.sp) : m * in_step;
+                const float4 x = gld<streamed<LD_C2C_ROWS>()>(reinterpret_cast<const float4 *>(in + b + o));
                 d0[m] = make_float2(x.x, x.y);
                 d1[m] = make_float2(x.z, x.w);
             }
@@ -530,11 +549,14 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
             if constexpr (OUTP == 1) {
                 if (2 * cp_out < ncol) {
 #pragma unroll
-                    for (int m = 0; m < 16; ++m) gst<streamed<ST_C2C_POINTS>()>(out + b + m * out_step, v0[m]);
+                    for (int m = 0; m < 16; ++m)
+                        if (!CH || q_out + T * m < nsrc) gst<streamed<ST_C2C_POINTS>()>(out + b + m * out_step, v0[m]);
                 }
                 if (2 * cp_out + 1 < ncol) {
 #pragma unroll
-                    for (int m = 0; m < 16; ++m) gst<streamed<ST_C2C_POINTS>()>(out + b + a.out_s.sc + m * out_step, v1[m]);
+                    for (int m = 0; m < 16; ++m)
+                        if (!CH || q_out + T * m < nsrc)
+                            gst<streamed<ST_C2C_POINTS>()>(out + b + a.out_s.sc + m * out_step, v1[m]);
                 }
             } else if constexpr (OUTP == 2) {  // rows not 16-byte aligned: as the loads, in reverse
                 const bool odd = q_out & 1;
@@ -542,17 +564,20 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
                 const int col = 2 * cp_out + (odd ? 1 : 0);
                 if (col < ncol) {
                     const long long e = b + (odd ? a.out_s.sc - a.out_s.sp : 0);
+                    const int q0 = q_out & ~1;
 #pragma unroll
                     for (int m = 0; m < 16; ++m) {
-                        gst<streamed<ST_C2C_UROWS>()>(out + e + m * out_step, v0[m]);
-                        gst<streamed<ST_C2C_UROWS>()>(out + e + a.out_s.sp + m * out_step, v1[m]);
+                        if (!CH || q0 + T * m < nsrc) gst<streamed<ST_C2C_UROWS>()>(out + e + m * out_step, v0[m]);
+                        if (!CH || q0 + 1 + T * m < nsrc)
+                            gst<streamed<ST_C2C_UROWS>()>(out + e + a.out_s.sp + m * out_step, v1[m]);
                     }
                 }
             } else if (2 * cp_out < ncol) {
 #pragma unroll
                 for (int m = 0; m < 16; ++m)
-                    gst<streamed<INP == 1 ? ST_C2C_ROWS_INP : ST_C2C_ROWS>()>(reinterpret_cast<float4 *>(out + b + m * out_step),
-                                                                   pack2(v0[m], v1[m]));
+                    if (!CH || q_out + T * m < nsrc)
+                        gst<streamed<INP == 1 ? ST_C2C_ROWS_INP : ST_C2C_ROWS>()>(
+                            reinterpret_cast<float4 *>(out + b + m * out_step), pack2(v0[m], v1[m]));
             }
         }
         __syncthreads();  // the next tile's stage 0 overwrites the LDS tile
@@ -962,28 +987,34 @@ static const void *p2_pick_io(int dir, int inp, int outp) {
 // kernel symbol for (n, dir, inp, outp, math); nullptr if not built.  The
 // matrix-core variants exist for the 16-column tiles with a middle radix-16
 // stage: n = 512 and 1024.
-// mt: 0 plain, 1 / 2 matrix-core middle stage (512 and 1024 only), 3 no transform
+// mt: 0 plain, 1 / 2 matrix-core middle stage (512 and 1024 only), 3 no
+// transform, 4 type-I DCT by the even extension
 static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
     switch (n) {
         case 256:
             return mt == 0 ? p2_pick_io<256, 16, 0>(dir, inp, outp)
-                 : mt == 3 ? p2_pick_io<256, 16, 3>(dir, inp, outp) : nullptr;
+                 : mt == 3 ? p2_pick_io<256, 16, 3>(dir, inp, outp)
+                 : mt == 4 ? p2_pick_io<256, 16, 4>(dir, inp, outp) : nullptr;
         case 512:
             return mt == 0 ? p2_pick_io<512, 16, 0>(dir, inp, outp)
                  : mt == 1 ? p2_pick_io<512, 16, 1>(dir, inp, outp)
                  : mt == 2 ? p2_pick_io<512, 16, 2>(dir, inp, outp)
-                           : p2_pick_io<512, 16, 3>(dir, inp, outp);
+                 : mt == 3 ? p2_pick_io<512, 16, 3>(dir, inp, outp)
+                           : p2_pick_io<512, 16, 4>(dir, inp, outp);
         case 1024:
             return mt == 0 ? p2_pick_io<1024, 16, 0>(dir, inp, outp)
                  : mt == 1 ? p2_pick_io<1024, 16, 1>(dir, inp, outp)
                  : mt == 2 ? p2_pick_io<1024, 16, 2>(dir, inp, outp)
-                           : p2_pick_io<1024, 16, 3>(dir, inp, outp);
+                 : mt == 3 ? p2_pick_io<1024, 16, 3>(dir, inp, outp)
+                           : p2_pick_io<1024, 16, 4>(dir, inp, outp);
         case 2048:
             return mt == 0 ? p2_pick_io<2048, 8, 0>(dir, inp, outp)
-                 : mt == 3 ? p2_pick_io<2048, 8, 3>(dir, inp, outp) : nullptr;
+                 : mt == 3 ? p2_pick_io<2048, 8, 3>(dir, inp, outp)
+                 : mt == 4 ? p2_pick_io<2048, 8, 4>(dir, inp, outp) : nullptr;
         case 4096:
             return mt == 0 ? p2_pick_io<4096, 4, 0>(dir, inp, outp)
-                 : mt == 3 ? p2_pick_io<4096, 4, 3>(dir, inp, outp) : nullptr;
+                 : mt == 3 ? p2_pick_io<4096, 4, 3>(dir, inp, outp)
+                 : mt == 4 ? p2_pick_io<4096, 4, 4>(dir, inp, outp) : nullptr;
         default: return nullptr;
     }
 }
@@ -999,7 +1030,7 @@ bool p2_has_mfma(int n) { return n == 512 || n == 1024; }
 hipError_t p2_prepare(int n) {
     hipError_t e = hipSuccess;
     for (int dir : {-1, 1})
-        for (int io = 0; io < 20; ++io) {
+        for (int io = 0; io < 25; ++io) {
             const int mt = io / 5, k5 = io % 5;  // (inp, outp): (0,0) (0,1) (1,0) (0,2) (2,0)
             const int inp = k5 == 2 ? 1 : k5 == 4 ? 2 : 0, outp = k5 == 1 ? 1 : k5 == 3 ? 2 : 0;
             const void *k = p2_pick(n, dir, inp, outp, mt);

@@ -99,10 +99,11 @@ struct PassArgs {
     Side in_s, out_s;
     int inp, outp;  // power-of-two C2C pass, kind of side: 1 lines, 0 aligned rows, 2 unaligned rows
     int math;       // power-of-two passes: 0 plain, 1 / 2 middle radix-16 stage on MFMA (FP16 / BF16 hi+lo),
-                    // 3 (C2C pass) no transform: the reorder alone
+                    // 3 (C2C pass) no transform: the reorder alone, 4 (C2C pass) type-I DCT by the
+                    // even extension (lines of cheb = fft.n / 2 + 1 points)
     int tile_order; // power-of-two C2C pass: 0 tile t = (t / CB, t % CB), 1 tile t = (t % A, t / A)
     int xcd;        // power-of-two C2C pass: 1 to give each XCD runs of consecutive tiles
-    int cheb;       // generic C2C pass: > 0 = lines of cheb points, transformed as their even
+    int cheb;       // C2C pass: > 0 = lines of cheb points, transformed as their even
                     // extension of length fft.n = 2 (cheb - 1) (type-I DCT); 0 = plain
     // X passes: real lines (y, z) flattened as g = z * ny + y; line g's spectrum
     // is workspace row (z nkb + kb) ypitch + y0 + y of column block kb

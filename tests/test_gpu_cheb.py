@@ -25,7 +25,9 @@ def rel(a, b):
     return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
 
 
-SHAPES = [(17, 16, 16), (9, 7, 15), (33, 20, 24), (257, 8, 12), (65, 30, 1024), (5, 256, 32), (2, 6, 10)]
+# 2 (nz - 1) in {256 .. 4096} runs the power-of-two kernel in FP32 (mirrored loads, masked stores)
+SHAPES = [(17, 16, 16), (9, 7, 15), (33, 20, 24), (257, 8, 12), (65, 30, 1024), (5, 256, 32), (2, 6, 10),
+          (129, 6, 20), (513, 5, 36), (1025, 3, 16), (2049, 2, 6)]
 
 
 @pytest.mark.parametrize("stride1", [1, 0])
