@@ -288,8 +288,12 @@ int pf_get_timing(pf_plan *p, int dir, int pass, double *total_ms, long long *co
  * (1 at z = 0 and nz - 1, 2 inside): the adjoint of the type-I DCT is
  * W C W^-1, and the interior-mode factors of the R2C / C2R adjoints cancel.
  * in, out: real [nz][ny][nx]; spec: complex Z-pencil buffer of the plan
- * (caller-owned scratch, overwritten).  All distinct (PF_EALIAS), 16-byte
- * aligned.  PF_EUNSUPPORTED for other plans.
+ * (caller-owned scratch, contents unspecified on return).  All distinct
+ * (PF_EALIAS), 16-byte aligned.  PF_EUNSUPPORTED for other plans.
+ * FP32 plans whose extension length 2 (nz - 1) is 256 .. 4096 run the z part
+ * (forward DCT, product, backward DCT, and the adjoint's weights, which act
+ * along z only and commute with the X and Y stages) as one pass on the
+ * plan's workspace; the spectrum is then never written to spec.
  */
 int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjoint, void *stream);
 

@@ -68,6 +68,10 @@ struct pf_plan {
     PassDesc pass[2][kPasses];
     const char *pass_names[2][kPasses];
     double pass_bytes[2][kPasses];
+    // Chebyshev third transform with a power-of-two extension (FP32, 1 x 1):
+    // the spectral step's Z passes and product fused into one pass on W
+    bool spec_fused;
+    PassDesc spec;
     bool timing;
     PassTiming tim[2][kPasses];
     std::vector<EventPair> pool;
@@ -591,6 +595,20 @@ void build_passes(pf_plan *p) {
         }
         p->npass[dir] = 3;
         if (p->blocked) add_remaps(p, dir);
+        if (dir == 0 && cheb && z.kind == pf::PASS_C2C_P2 && !p->blocked && !p->share) {
+            // fused spectral step: the forward Z pass's tiles, W on both sides
+            PassDesc f = z;
+            f.a.in_s = f.a.out_s = wsz;
+            f.a.inp = f.a.outp = 0;
+            f.a.tile_order = 0;
+            f.a.xcd = 0;
+            f.lds = pf::p2_lds_bytes(fz.n, 0);
+            const long long tiles = f.a.A * f.a.CB;
+            const long long resident = (long long)p->ncu * pf::p2_spec_blocks_per_cu(fz.n, f.threads, f.lds);
+            f.blocks = (unsigned)(tiles < resident ? tiles : resident);
+            p->spec = f;
+            p->spec_fused = true;
+        }
     }
     if (p->share) build_share_only(p);
 }
@@ -818,6 +836,8 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, dev);
     for (int n : {ny, p->fz.n})
         if (e == hipSuccess && pf::p2_supported(n, l->precision)) e = pf::p2_prepare(n);
+    const bool cheb_p2 = l->third == PF_THIRD_CHEB && !o.generic_only && pf::p2_supported(p->fz.n, l->precision);
+    if (e == hipSuccess && cheb_p2) e = pf::p2_spec_prepare(p->fz.n);
     if (e == hipSuccess && p->fast_x) e = pf::p2x_prepare(nx);
     if (e != hipSuccess) {
         (void)hipFree(p->tw_dev);
@@ -957,6 +977,20 @@ int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjo
     a.nx = p->nx, a.ny = p->ny, a.nz = p->nz, a.nxh = p->nxh, a.stride1 = p->lay.stride1, a.f64 = f64;
     a.conj = adjoint;
     a.scale = 1.0 / ((double)p->nx * p->ny * 2.0 * (p->nz - 1));
+    if (p->spec_fused) {  // X, Y forward; Z, product, Z in one pass on W; Y, X backward
+        int r = check_call(p, in, out);
+        if (!r) r = run_one(p, 0, 0, in, p->ws, s);
+        if (!r) r = run_one(p, 0, 1, p->ws, p->ws, s);
+        if (!r) {
+            pf::PassDesc d = p->spec;
+            d.a.in = p->ws;
+            d.a.out = p->ws;
+            r = hip_status(pf::p2_spec_launch(d, adjoint, p->nx, (float)a.scale, s));
+        }
+        if (!r) r = run_one(p, 1, 1, p->ws, p->ws, s);
+        if (!r) r = run_one(p, 1, 2, p->ws, out, s);
+        return r;
+    }
     const void *src = in;
     if (adjoint) {  // out = in / w(z): the adjoint of the type-I DCT is w C w^-1
         const hipError_t e = pf::launch_zweight(in, out, p->nx, p->ny, p->nz, f64, -1, s);

@@ -584,6 +584,172 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     }
 }
 
+// ---- fused spectral step along z (Chebyshev third transform, Sec. 3.1) -----
+// All stages of one N-point column FFT on a tile whose rows are 16-byte column
+// pairs on both sides (thread point set q + T m, pair cp, in every stage):
+// inputs x[q + T m] in (v0, v1), outputs X[q + T m] in the same registers.
+// Ends after the last stage's LDS reads; the caller synchronises before the
+// LDS tile is written again.
+template <int N, int TC, int DIR>
+__device__ __forceinline__ void p2_rows_fft(cx<float> (&v0)[16], cx<float> (&v1)[16], float4 *buf,
+                                            const cx<float> *twl, int q, int cp) {
+    constexpr int T = N / 16;
+    constexpr int S = p2_stages(N);
+    constexpr int RL = p2_radix(N, S - 1);
+    constexpr int NSL = p2_ns(N, S - 1);
+    Dft<float, 16, DIR>::run(v0);
+    Dft<float, 16, DIR>::run(v1);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q * 16 + r, cp)] = pack2(v0[r], v1[r]);
+    __syncthreads();
+    if constexpr (S == 3) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const float4 x = buf[p2_slot<TC>(q + T * m, cp)];
+            v0[m] = make_float2(x.x, x.y);
+            v1[m] = make_float2(x.z, x.w);
+        }
+        __syncthreads();
+        p2_butterflies2<N, 16, 16, DIR>(v0, v1, q, twl + p2_twoff(N, 1));
+        const int k = q & 15;
+        const int base = (q - k) * 16 + k;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(base + r * 16, cp)] = pack2(v0[r], v1[r]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const float4 x = buf[p2_slot<TC>(q + T * m, cp)];
+        v0[m] = make_float2(x.x, x.y);
+        v1[m] = make_float2(x.z, x.w);
+    }
+    p2_butterflies2<N, RL, NSL, DIR>(v0, v1, q, twl + p2_twoff(N, S - 1));
+}
+
+// The spectral step's z part on the blocked workspace after the forward X and
+// Y stages, in place, one tile (ky line, 16 kx columns) at a time: the type-I
+// DCT of the nz = N / 2 + 1 rows (the N-point DFT of their even extension),
+// the product with m = i mu, mu = -scale kx' / (kx'^2 + ky'^2 + kz'^2)
+// (conj(m) when ADJ), mu = 0 at k = 0, and the inverse DFT of the product --
+// still an even sequence, so its first nz points are the backward type-I DCT.
+// kx' = 2 pi kx / nx, ky' = 2 pi ky / ny (ky signed), kz' = 2 pi kz / N with
+// kz = min(k, N - k).  The adjoint's end-node weights w(z) (1 at z = 0 and
+// nz - 1, 2 inside) act along z only and so commute with the X and Y stages:
+// rows are divided by w(z) on load and multiplied by w(z) on store.  The
+// spectrum never leaves the block.  a.A = ny lines, a.CB column tiles, a.C =
+// nxh valid columns, a.in_s the workspace side, a.cheb = nz; a.out the workspace.
+template <int N, int TC, int ADJ>
+__global__ __launch_bounds__(N / 16 * TC / 2) void k_spec_p2(PassArgs a, int nx, float scale) {
+    constexpr int T = N / 16;
+    constexpr int CP = TC / 2;
+    constexpr int NT = T * CP;
+    float4 *buf = reinterpret_cast<float4 *>(pf_smem);
+    cx<float> *twl = reinterpret_cast<cx<float> *>(buf + N * CP);
+    const int tid = threadIdx.x;
+    const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
+    for (int i = tid; i < N - 1; i += NT) twl[i] = tw[i];
+    cx<float> *__restrict__ ws = reinterpret_cast<cx<float> *>(a.out);
+    const int nz = a.cheb;
+    const int CB = (int)a.CB;
+    const int ny = (int)a.A;
+    const int ntiles = (int)(a.A * a.CB);
+    const Side &sd = a.in_s;
+    // workspace address of (tile t, pair cp, row 0) and the tile's valid column count
+    auto tile_base = [&](int t, int cp, int &ncol) -> long long {
+        const int ta = t / CB, cb = t - ta * CB;
+        ncol = min(TC, a.C - cb * TC);
+        return (long long)ta * sd.sa + (long long)(cb / sd.cpb) * sd.sblk + (long long)(cb % sd.cpb) * TC * sd.sc +
+               (long long)(2 * cp) * sd.sc;
+    };
+    auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
+        const int tv = opaque_tid();
+        const int cp = tv % CP, q = tv / CP;
+        int ncol;
+        const long long b = tile_base(t, cp, ncol);
+        if (2 * cp < ncol) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int j = q + T * m;
+                const int z = j < nz ? j : N - j;  // the even extension
+                const float4 x = gld<streamed<LD_C2C_ROWS>()>(reinterpret_cast<const float4 *>(ws + b + z * sd.sp));
+                d0[m] = make_float2(x.x, x.y);
+                d1[m] = make_float2(x.z, x.w);
+            }
+        }
+    };
+
+    int t = blockIdx.x;
+    cx<float> p0[16], p1[16];
+    if (t < ntiles) load(p0, p1, t);
+    __syncthreads();  // twiddle table in LDS
+    const float two_pi = 6.283185307179586f;
+    const float kyf = two_pi / (float)ny, kxf = two_pi / (float)nx, kzf = two_pi / (float)N;
+    const float sg = ADJ ? -1.f : 1.f;
+    for (; t < ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        const int cp = tv % CP, q = tv / CP;
+        cx<float> v0[16], v1[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            v0[m] = p0[m];
+            v1[m] = p1[m];
+        }
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(p0, p1, tn);
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int j = q + T * m;
+                const int z = j < nz ? j : N - j;
+                const float w = (z == 0 || z == nz - 1) ? 1.f : 0.5f;
+                v0[m] = make_float2(v0[m].x * w, v0[m].y * w);
+                v1[m] = make_float2(v1[m].x * w, v1[m].y * w);
+            }
+        }
+        p2_rows_fft<N, TC, -1>(v0, v1, buf, twl, q, cp);
+        {
+            const int ta = t / CB, cb = t - ta * CB;
+            const int kx0 = cb * TC + 2 * cp;
+            const int kys = 2 * ta <= ny ? ta : ta - ny;
+            const float kyr = kyf * (float)kys;
+            const float kx0r = kxf * (float)kx0, kx1r = kxf * (float)(kx0 + 1);
+            const float r0 = kx0r * kx0r + kyr * kyr, r1 = kx1r * kx1r + kyr * kyr;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int k = q + T * m;
+                const float kzr = kzf * (float)(2 * k <= N ? k : N - k);
+                const float kz2 = kzr * kzr;
+                const float k20 = r0 + kz2, k21 = r1 + kz2;
+                const float mu0 = k20 > 0.f ? sg * (-scale * kx0r / k20) : 0.f;
+                const float mu1 = sg * (-scale * kx1r / k21);  // kx0 + 1 > 0
+                v0[m] = make_float2(-mu0 * v0[m].y, mu0 * v0[m].x);
+                v1[m] = make_float2(-mu1 * v1[m].y, mu1 * v1[m].x);
+            }
+        }
+        __syncthreads();  // the inverse transform rewrites the LDS tile
+        p2_rows_fft<N, TC, 1>(v0, v1, buf, twl, q, cp);
+        {
+            int ncol;
+            const long long b = tile_base(t, cp, ncol);
+            if (2 * cp < ncol) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    const int j = q + T * m;
+                    if (j < nz) {
+                        float4 x = pack2(v0[m], v1[m]);
+                        if constexpr (ADJ) {
+                            const float w = (j == 0 || j == nz - 1) ? 1.f : 2.f;
+                            x = make_float4(x.x * w, x.y * w, x.z * w, x.w * w);
+                        }
+                        gst<streamed<ST_C2C_ROWS>()>(reinterpret_cast<float4 *>(ws + b + j * sd.sp), x);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the next tile's stage 0 overwrites the LDS tile
+    }
+}
+
 // ---- X stage for even power-of-two nx, FP32 --------------------------------
 // A real line x of length nx = 2M is transformed as the complex line
 // z[m] = x[2m] + i x[2m+1] of length M (8-byte loads, half the butterflies),
@@ -1023,6 +1189,50 @@ const void *p2_symbol(const PassDesc &d) {
     if (d.kind == PASS_R2C_P2) return p2x_pick(2 * d.a.fft.n, 1, d.a.math);
     if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0, d.a.math);
     return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);
+}
+
+template <int N, int TC>
+static const void *spec_pick_n(int adj) {
+    return adj ? reinterpret_cast<const void *>(&k_spec_p2<N, TC, 1>)
+               : reinterpret_cast<const void *>(&k_spec_p2<N, TC, 0>);
+}
+
+// fused spectral-step kernel for extension length n; nullptr if not built
+static const void *spec_pick(int n, int adj) {
+    switch (n) {
+        case 256: return spec_pick_n<256, 16>(adj);
+        case 512: return spec_pick_n<512, 16>(adj);
+        case 1024: return spec_pick_n<1024, 16>(adj);
+        case 2048: return spec_pick_n<2048, 8>(adj);
+        case 4096: return spec_pick_n<4096, 4>(adj);
+        default: return nullptr;
+    }
+}
+
+hipError_t p2_spec_prepare(int n) {
+    for (int adj = 0; adj < 2; ++adj) {
+        const void *k = spec_pick(n, adj);
+        if (!k) return hipErrorInvalidValue;
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2_lds_bytes(n, 0));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int p2_spec_blocks_per_cu(int n, unsigned threads, size_t lds) {
+    int nb = 0;
+    const void *k = spec_pick(n, 0);
+    if (!k) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)threads, lds) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t p2_spec_launch(const PassDesc &d, int adj, int nx, float scale, hipStream_t s) {
+    const void *k = spec_pick(d.a.fft.n, adj);
+    if (!k) return hipErrorInvalidDeviceFunction;
+    PassArgs a = d.a;
+    void *args[] = {&a, &nx, &scale};
+    return hipLaunchKernel(k, dim3(d.blocks), dim3(d.threads), args, d.lds, s);
 }
 
 bool p2_has_mfma(int n) { return n == 512 || n == 1024; }

@@ -181,6 +181,12 @@ size_t p2_lds_bytes(int n, int math);
 hipError_t p2_prepare(int n);
 int p2_blocks_per_cu(const PassDesc &d);
 hipError_t p2_launch(const PassDesc &d, hipStream_t s);
+// fused spectral step along z on the workspace (Chebyshev third transform,
+// extension length d.a.fft.n = 256 .. 4096, FP32): forward type-I DCT, product
+// with the multiplier (its conjugate and the end-node weights when adj), inverse
+hipError_t p2_spec_prepare(int n);
+int p2_spec_blocks_per_cu(int n, unsigned threads, size_t lds);
+hipError_t p2_spec_launch(const PassDesc &d, int adj, int nx, float scale, hipStream_t s);
 // Even power-of-two X stage, FP32 (fft.n of the pass is nx / 2).
 bool p2x_supported(int nx, int prec);
 int p2x_threads(int nx);
