@@ -24,21 +24,39 @@
 
 namespace pf {
 
+extern __shared__ __align__(16) unsigned char pf_smem[];
+
+// Twiddle tables are read through a pointer qualified as global memory: the
+// stage functions below are out of line, and an unqualified pointer would
+// turn every access into a flat one (as would a pointer into LDS, which is
+// why the stages take the column as an element offset into pf_smem).
+#define PF_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ cx<T> load_tw(const PF_GLOBAL cx<T> *p) {
+    const PF_GLOBAL T *q = reinterpret_cast<const PF_GLOBAL T *>(p);
+    return cmk<T>(q[0], q[1]);
+}
+
 // ---- one Stockham stage on one LDS column ------------------------------
 // Butterfly j (j < n/R) reads x[j + r n/R], applies W_{Ns R}^{r k} with
 // k = j mod Ns, runs the radix-R DFT and writes (j - k) R + k + r Ns.
 // Every thread of the workgroup must call this (it holds two barriers).
 // Kept out of line: inlining all radices into the runtime stage loop makes
-// the register allocator keep their live ranges together.
+// the register allocator keep their live ranges together.  The column is
+// pf_smem element col_off on (so that its accesses are LDS instructions);
+// j mod Ns is j - floor(j mag / 2^32) Ns with mag = ceil(2^32 / Ns), exact
+// for j, Ns < 2^16.
 template <typename T>
 struct EMax {
     static constexpr int value = sizeof(T) == 4 ? kEMax : kEMax / 2;
 };
 
 template <typename T, int R, int DIR>
-__device__ __attribute__((noinline)) void fft_stage(cx<T> *col, int n, int Ns, const cx<T> *__restrict__ tw, int lane,
-                                          int wpc) {
+__device__ __attribute__((noinline)) void fft_stage(int col_off, int n, int Ns, unsigned mag,
+                                                    const PF_GLOBAL cx<T> *__restrict__ tw, int lane, int wpc) {
     constexpr int BM = (EMax<T>::value + R - 1) / R;
+    cx<T> *col = reinterpret_cast<cx<T> *>(pf_smem) + col_off;
     const int nb = n / R;
     cx<T> v[BM][R];
 #pragma unroll
@@ -54,12 +72,12 @@ __device__ __attribute__((noinline)) void fft_stage(cx<T> *col, int n, int Ns, c
     for (int i = 0; i < BM; ++i) {
         const int j = lane + i * wpc;
         if (j < nb) {
-            const int k = j % Ns;
+            const int k = Ns > 1 ? j - (int)__umulhi((unsigned)j, mag) * Ns : 0;
             if (Ns > 1) {
-                const cx<T> *t = tw + k * (R - 1);
+                const PF_GLOBAL cx<T> *t = tw + k * (R - 1);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    cx<T> w = t[r - 1];
+                    cx<T> w = load_tw<T>(t + r - 1);
                     if (DIR > 0) w.y = -w.y;
                     v[i][r] = cmul(v[i][r], w);
                 }
@@ -73,31 +91,33 @@ __device__ __attribute__((noinline)) void fft_stage(cx<T> *col, int n, int Ns, c
     __syncthreads();
 }
 
-// Whole 1D FFT of length fs.n on one LDS column, in natural order.
+// Whole 1D FFT of length fs.n on the LDS column at pf_smem element col_off,
+// in natural order.
 template <typename T, int DIR>
-__device__ __forceinline__ void fft_lds(cx<T> *col, const FftSpec &fs, const cx<T> *__restrict__ tw, int lane,
-                                        int wpc) {
+__device__ __forceinline__ void fft_lds(int col_off, const FftSpec &fs, const cx<T> *tw_table, int lane, int wpc) {
+    const PF_GLOBAL cx<T> *tw = (const PF_GLOBAL cx<T> *)tw_table;
     int Ns = 1;
     for (int s = 0; s < fs.nstages; ++s) {
         const int R = fs.radix[s];
-        const cx<T> *t = tw + fs.twoff[s];
+        const PF_GLOBAL cx<T> *t = tw + fs.twoff[s];
+        const unsigned mag = Ns > 1 ? 0xFFFFFFFFu / (unsigned)Ns + 1u : 0u;
         switch (R) {
-            case 16: fft_stage<T, 16, DIR>(col, fs.n, Ns, t, lane, wpc); break;
-            case 8: fft_stage<T, 8, DIR>(col, fs.n, Ns, t, lane, wpc); break;
-            case 4: fft_stage<T, 4, DIR>(col, fs.n, Ns, t, lane, wpc); break;
-            case 2: fft_stage<T, 2, DIR>(col, fs.n, Ns, t, lane, wpc); break;
-            case 3: fft_stage<T, 3, DIR>(col, fs.n, Ns, t, lane, wpc); break;
-            case 5: fft_stage<T, 5, DIR>(col, fs.n, Ns, t, lane, wpc); break;
-            default: fft_stage<T, 7, DIR>(col, fs.n, Ns, t, lane, wpc); break;
+            case 16: fft_stage<T, 16, DIR>(col_off, fs.n, Ns, mag, t, lane, wpc); break;
+            case 8: fft_stage<T, 8, DIR>(col_off, fs.n, Ns, mag, t, lane, wpc); break;
+            case 4: fft_stage<T, 4, DIR>(col_off, fs.n, Ns, mag, t, lane, wpc); break;
+            case 2: fft_stage<T, 2, DIR>(col_off, fs.n, Ns, mag, t, lane, wpc); break;
+            case 3: fft_stage<T, 3, DIR>(col_off, fs.n, Ns, mag, t, lane, wpc); break;
+            case 5: fft_stage<T, 5, DIR>(col_off, fs.n, Ns, mag, t, lane, wpc); break;
+            default: fft_stage<T, 7, DIR>(col_off, fs.n, Ns, mag, t, lane, wpc); break;
         }
         Ns *= R;
     }
 }
 
-extern __shared__ __align__(16) unsigned char pf_smem[];
-
-__device__ __forceinline__ long long side_base(const Side &s, long long a, long long cb, int tc) {
-    return a * s.sa + (cb / s.cpb) * s.sblk + (cb % s.cpb) * (long long)tc * s.sc;
+__device__ __forceinline__ long long side_base(const Side &s, int a, int cb, int tc) {
+    const int cpb = (int)s.cpb;
+    const int blk = cb / cpb;
+    return (long long)a * s.sa + (long long)blk * s.sblk + (long long)((cb - blk * cpb) * tc) * s.sc;
 }
 
 // ---- C2C along a strided axis, TC columns per workgroup -------------------
@@ -112,12 +132,14 @@ __device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp
     const int nthr = blockDim.x;
     const int TC = 1 << a.tc_log2;
     const int wpc = 1 << a.wpc_log2;
-    const long long ta = tile / a.CB;
-    const long long cb = tile - ta * a.CB;
+    // tile counts stay below 2^31 (checked at plan time): 32-bit index arithmetic
+    const int CB = (int)a.CB;
+    const int ta = (int)tile / CB;
+    const int cb = (int)tile - ta * CB;
     const long long ib = side_base(a.in_s, ta, cb, TC);
     const long long ob = side_base(a.out_s, ta, cb, TC);
-    const long long left = (long long)a.C - cb * TC;
-    const int ncol = left < TC ? (int)left : TC;
+    const int left = a.C - cb * TC;
+    const int ncol = left < TC ? left : TC;
     const int n = a.fft.n;
     const int pitch = a.pitch;
     const cx<T> *__restrict__ in = reinterpret_cast<const cx<T> *>(inp);
@@ -127,33 +149,41 @@ __device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp
     // type-I DCT (a.cheb > 0): point p of the even extension is source point p or n - p
     const int cheb = a.cheb;
     auto src = [cheb, n](int p) { return cheb > 0 && p >= cheb ? n - p : p; };
-    if (a.in_s.sc == 1) {  // rows of the tile are contiguous: column fastest
-        const int c = tid & (TC - 1);
-        if (c < ncol)
-            for (int p = tid >> a.tc_log2; p < n; p += rows_per)
-                lds[c * pitch + pidx(p)] = in[ib + c + (long long)src(p) * a.in_s.sp];
-    } else {  // columns are contiguous lines: point fastest
-        const int c = tid >> a.wpc_log2;
-        if (c < ncol)
-            for (int p = tid & (wpc - 1); p < n; p += wpc)
-                lds[c * pitch + pidx(p)] = in[ib + (long long)c * a.in_s.sc + (long long)src(p) * a.in_s.sp];
+    // per thread: column c, points p0, p0 + dp, ...; element (c, p) at base + p sp
+    const bool in_rows = a.in_s.sc == 1;  // rows of the tile contiguous: column fastest
+    {
+        const int c = in_rows ? (tid & (TC - 1)) : (tid >> a.wpc_log2);
+        const int p0 = in_rows ? (tid >> a.tc_log2) : (tid & (wpc - 1));
+        const int dp = in_rows ? rows_per : wpc;
+        const long long sp = a.in_s.sp;
+        const cx<T> *base = in + ib + (long long)c * a.in_s.sc;
+        cx<T> *dst = lds + c * pitch;
+        if (c < ncol) {
+            if (cheb > 0) {
+                for (int p = p0; p < n; p += dp) dst[pidx(p)] = base[(long long)src(p) * sp];
+            } else {
+                const cx<T> *q = base + (long long)p0 * sp;
+                const long long step = (long long)dp * sp;
+                for (int p = p0; p < n; p += dp, q += step) dst[pidx(p)] = *q;
+            }
+        }
     }
     __syncthreads();
     const int col = tid >> a.wpc_log2;
     const bool act = col < TC;
-    fft_lds<T, DIR>(lds + (act ? col : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+    fft_lds<T, DIR>((act ? col : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
                     act ? (tid & (wpc - 1)) : n, wpc);
     const int nout = cheb > 0 ? cheb : n;  // the DCT keeps outputs 0 .. cheb - 1
-    if (a.out_s.sc == 1) {
-        const int c = tid & (TC - 1);
+    {
+        const bool out_rows = a.out_s.sc == 1;
+        const int c = out_rows ? (tid & (TC - 1)) : (tid >> a.wpc_log2);
+        const int p0 = out_rows ? (tid >> a.tc_log2) : (tid & (wpc - 1));
+        const int dp = out_rows ? rows_per : wpc;
+        const long long step = (long long)dp * a.out_s.sp;
+        cx<T> *q = out + ob + (long long)c * a.out_s.sc + (long long)p0 * a.out_s.sp;
+        const cx<T> *srcl = lds + c * pitch;
         if (c < ncol)
-            for (int p = tid >> a.tc_log2; p < nout; p += rows_per)
-                out[ob + c + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
-    } else {
-        const int c = tid >> a.wpc_log2;
-        if (c < ncol)
-            for (int p = tid & (wpc - 1); p < nout; p += wpc)
-                out[ob + (long long)c * a.out_s.sc + (long long)p * a.out_s.sp] = lds[c * pitch + pidx(p)];
+            for (int p = p0; p < nout; p += dp, q += step) *q = srcl[pidx(p)];
     }
 }
 
@@ -202,7 +232,7 @@ __device__ __forceinline__ void r2c_x_body(const PassArgs &a, const void *inp, v
         }
     }
     __syncthreads();
-    fft_lds<T, -1>(lds + (act ? c : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+    fft_lds<T, -1>((act ? c : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
                    act ? (tid & (wpc - 1)) : n, wpc);
     const int B = 1 << a.b_log2;
     const int total = a.nkb * TC * B;
@@ -267,7 +297,7 @@ __device__ __forceinline__ void c2r_x_body(const PassArgs &a, const void *inp, v
     __syncthreads();
     const int c = tid >> a.wpc_log2;
     const bool act = c < TC;
-    fft_lds<T, 1>(lds + (act ? c : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
+    fft_lds<T, 1>((act ? c : 0) * pitch, a.fft, reinterpret_cast<const cx<T> *>(a.tw),
                   act ? (tid & (wpc - 1)) : n, wpc);
     if (act) {
         const long long ga = g0 + 2 * c, gb = ga + 1;
