@@ -51,6 +51,12 @@ template <typename T>
 struct EMax {
     static constexpr int value = sizeof(T) == 4 ? kEMax : kEMax / 2;
 };
+// global accesses a thread keeps in flight when it moves a tile between HBM
+// and LDS (FP64: fewer, so that the staging registers do not spill)
+template <typename T>
+struct Stage {
+    static constexpr int value = sizeof(T) == 4 ? 16 : 4;
+};
 
 template <typename T, int R, int DIR>
 __device__ __attribute__((noinline)) void fft_stage(int col_off, int n, int Ns, unsigned mag,
@@ -159,12 +165,22 @@ __device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp
         const cx<T> *base = in + ib + (long long)c * a.in_s.sc;
         cx<T> *dst = lds + c * pitch;
         if (c < ncol) {
-            if (cheb > 0) {
-                for (int p = p0; p < n; p += dp) dst[pidx(p)] = base[(long long)src(p) * sp];
-            } else {
-                const cx<T> *q = base + (long long)p0 * sp;
-                const long long step = (long long)dp * sp;
-                for (int p = p0; p < n; p += dp, q += step) dst[pidx(p)] = *q;
+            // EM loads in flight before the first wait, then the LDS writes
+            constexpr int EM = Stage<T>::value;
+            const long long step = (long long)dp * sp;
+            for (int p1 = p0; p1 < n; p1 += EM * dp) {
+                cx<T> r[EM];
+                const cx<T> *q = base + (long long)p1 * sp;
+#pragma unroll
+                for (int i = 0; i < EM; ++i) {
+                    const int p = p1 + i * dp;
+                    if (p < n) r[i] = cheb > 0 ? base[(long long)src(p) * sp] : q[i * step];
+                }
+#pragma unroll
+                for (int i = 0; i < EM; ++i) {
+                    const int p = p1 + i * dp;
+                    if (p < n) dst[pidx(p)] = r[i];
+                }
             }
         }
     }
@@ -182,13 +198,27 @@ __device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp
         const long long step = (long long)dp * a.out_s.sp;
         cx<T> *q = out + ob + (long long)c * a.out_s.sc + (long long)p0 * a.out_s.sp;
         const cx<T> *srcl = lds + c * pitch;
-        if (c < ncol)
-            for (int p = p0; p < nout; p += dp, q += step) *q = srcl[pidx(p)];
+        if (c < ncol) {
+            constexpr int EM = Stage<T>::value;
+            for (int p1 = p0; p1 < nout; p1 += EM * dp, q += EM * step) {
+                cx<T> r[EM];
+#pragma unroll
+                for (int i = 0; i < EM; ++i) {
+                    const int p = p1 + i * dp;
+                    if (p < nout) r[i] = srcl[pidx(p)];
+                }
+#pragma unroll
+                for (int i = 0; i < EM; ++i) {
+                    const int p = p1 + i * dp;
+                    if (p < nout) q[i * step] = r[i];
+                }
+            }
+        }
     }
 }
 
 template <typename T, int DIR>
-__global__ __launch_bounds__(1024) void k_c2c_tile(PassArgs a) {
+__global__ __launch_bounds__(kGenericThreads) void k_c2c_tile(PassArgs a) {
     c2c_tile_body<T, DIR>(a, a.in, a.out, blockIdx.x);
 }
 
@@ -225,10 +255,23 @@ __device__ __forceinline__ void r2c_x_body(const PassArgs &a, const void *inp, v
         const bool va = ga < a.lines, vb = gb < a.lines;
         const T *pa = in + ga * a.ld_real;
         const T *pb = in + gb * a.ld_real;
-        for (int p = tid & (wpc - 1); p < n; p += wpc) {
-            const T xa = va ? pa[p] : T(0);
-            const T xb = vb ? pb[p] : T(0);
-            lds[c * pitch + pidx(p)] = cmk<T>(xa, xb);
+        // EM loads per line in flight before the first wait
+        constexpr int EM = Stage<T>::value;
+        for (int p1 = tid & (wpc - 1); p1 < n; p1 += EM * wpc) {
+            T ra[EM], rb[EM];
+#pragma unroll
+            for (int i = 0; i < EM; ++i) {
+                const int p = p1 + i * wpc;
+                if (p < n) {
+                    ra[i] = va ? pa[p] : T(0);
+                    rb[i] = vb ? pb[p] : T(0);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < EM; ++i) {
+                const int p = p1 + i * wpc;
+                if (p < n) lds[c * pitch + pidx(p)] = cmk<T>(ra[i], rb[i]);
+            }
         }
     }
     __syncthreads();
@@ -238,23 +281,43 @@ __device__ __forceinline__ void r2c_x_body(const PassArgs &a, const void *inp, v
     const int total = a.nkb * TC * B;
     const long long kbstride = (long long)a.ypitch << a.b_log2;
     const T h = T(0.5);
-    for (int f = tid; f < total; f += nthr) {
-        const int kk = f & (B - 1);
-        const int cc = (f >> a.b_log2) & (TC - 1);
-        const int kb = f >> (a.b_log2 + a.tc_log2);
-        const int k = kb * B + kk;
-        const long long ga = g0 + 2 * cc;
-        if (k >= a.nxh || ga >= a.lines) continue;
-        const cx<T> *col = lds + cc * pitch;
-        const cx<T> z = col[pidx(k)];
-        const cx<T> w = col[pidx(k == 0 ? 0 : n - k)];
-        out[rowoff[2 * cc] + kb * kbstride + kk] = cmk<T>((z.x + w.x) * h, (z.y - w.y) * h);
-        if (ga + 1 < a.lines) out[rowoff[2 * cc + 1] + kb * kbstride + kk] = cmk<T>((z.y + w.y) * h, (w.x - z.x) * h);
+    // modes f = (kb, cc, kk) of the tile, EH per thread at a time: LDS reads
+    // first, then the split and the stores
+    constexpr int EH = Stage<T>::value / 2;
+    for (int f1 = tid; f1 < total; f1 += EH * nthr) {
+        cx<T> zr[EH], wr[EH];
+#pragma unroll
+        for (int i = 0; i < EH; ++i) {
+            const int f = f1 + i * nthr;
+            const int kk = f & (B - 1);
+            const int cc = (f >> a.b_log2) & (TC - 1);
+            const int k = (f >> (a.b_log2 + a.tc_log2)) * B + kk;
+            if (f < total && k < a.nxh) {
+                const cx<T> *col = lds + cc * pitch;
+                zr[i] = col[pidx(k)];
+                wr[i] = col[pidx(k == 0 ? 0 : n - k)];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < EH; ++i) {
+            const int f = f1 + i * nthr;
+            const int kk = f & (B - 1);
+            const int cc = (f >> a.b_log2) & (TC - 1);
+            const int kb = f >> (a.b_log2 + a.tc_log2);
+            const int k = kb * B + kk;
+            const long long ga = g0 + 2 * cc;
+            if (f < total && k < a.nxh && ga < a.lines) {
+                const cx<T> z = zr[i], w = wr[i];
+                out[rowoff[2 * cc] + kb * kbstride + kk] = cmk<T>((z.x + w.x) * h, (z.y - w.y) * h);
+                if (ga + 1 < a.lines)
+                    out[rowoff[2 * cc + 1] + kb * kbstride + kk] = cmk<T>((z.y + w.y) * h, (w.x - z.x) * h);
+            }
+        }
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_r2c_x(PassArgs a) {
+__global__ __launch_bounds__(kGenericThreads) void k_r2c_x(PassArgs a) {
     r2c_x_body<T>(a, a.in, a.out, blockIdx.x);
 }
 
@@ -277,21 +340,41 @@ __device__ __forceinline__ void c2r_x_body(const PassArgs &a, const void *inp, v
     const int B = 1 << a.b_log2;
     const int total = a.nkb * TC * B;
     const long long kbstride = (long long)a.ypitch << a.b_log2;
-    for (int f = tid; f < total; f += nthr) {
-        const int kk = f & (B - 1);
-        const int cc = (f >> a.b_log2) & (TC - 1);
-        const int kb = f >> (a.b_log2 + a.tc_log2);
-        const int k = kb * B + kk;
-        const long long ga = g0 + 2 * cc;
-        if (k >= a.nxh || ga >= a.lines) continue;
-        const cx<T> xa = in[rowoff[2 * cc] + kb * kbstride + kk];
-        const cx<T> xb = (ga + 1 < a.lines) ? in[rowoff[2 * cc + 1] + kb * kbstride + kk] : cmk<T>(T(0), T(0));
-        cx<T> *col = lds + cc * pitch;
-        if (k == 0 || 2 * k == n) {
-            col[pidx(k)] = cmk<T>(xa.x, xb.x);
-        } else {
-            col[pidx(k)] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
-            col[pidx(n - k)] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+    // modes f = (kb, cc, kk) of the tile, EH per thread at a time: all loads
+    // in flight before the first wait, then the LDS writes
+    constexpr int EH = Stage<T>::value / 2;
+    for (int f1 = tid; f1 < total; f1 += EH * nthr) {
+        cx<T> ra[EH], rb[EH];
+#pragma unroll
+        for (int i = 0; i < EH; ++i) {
+            const int f = f1 + i * nthr;
+            const int kk = f & (B - 1);
+            const int cc = (f >> a.b_log2) & (TC - 1);
+            const int kb = f >> (a.b_log2 + a.tc_log2);
+            const int k = kb * B + kk;
+            const long long ga = g0 + 2 * cc;
+            if (f < total && k < a.nxh && ga < a.lines) {
+                ra[i] = in[rowoff[2 * cc] + kb * kbstride + kk];
+                rb[i] = (ga + 1 < a.lines) ? in[rowoff[2 * cc + 1] + kb * kbstride + kk] : cmk<T>(T(0), T(0));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < EH; ++i) {
+            const int f = f1 + i * nthr;
+            const int kk = f & (B - 1);
+            const int cc = (f >> a.b_log2) & (TC - 1);
+            const int k = (f >> (a.b_log2 + a.tc_log2)) * B + kk;
+            const long long ga = g0 + 2 * cc;
+            if (f < total && k < a.nxh && ga < a.lines) {
+                const cx<T> xa = ra[i], xb = rb[i];
+                cx<T> *col = lds + cc * pitch;
+                if (k == 0 || 2 * k == n) {
+                    col[pidx(k)] = cmk<T>(xa.x, xb.x);
+                } else {
+                    col[pidx(k)] = cmk<T>(xa.x - xb.y, xa.y + xb.x);
+                    col[pidx(n - k)] = cmk<T>(xa.x + xb.y, xb.x - xa.y);
+                }
+            }
         }
     }
     __syncthreads();
@@ -305,16 +388,28 @@ __device__ __forceinline__ void c2r_x_body(const PassArgs &a, const void *inp, v
         T *pa = out + ga * a.ld_real;
         T *pb = out + gb * a.ld_real;
         const cx<T> *col = lds + c * pitch;
-        for (int p = tid & (wpc - 1); p < n; p += wpc) {
-            const cx<T> z = col[pidx(p)];
-            if (va) pa[p] = z.x;
-            if (vb) pb[p] = z.y;
+        constexpr int EM = Stage<T>::value;
+        for (int p1 = tid & (wpc - 1); p1 < n; p1 += EM * wpc) {
+            cx<T> r[EM];
+#pragma unroll
+            for (int i = 0; i < EM; ++i) {
+                const int p = p1 + i * wpc;
+                if (p < n) r[i] = col[pidx(p)];
+            }
+#pragma unroll
+            for (int i = 0; i < EM; ++i) {
+                const int p = p1 + i * wpc;
+                if (p < n) {
+                    if (va) pa[p] = r[i].x;
+                    if (vb) pb[p] = r[i].y;
+                }
+            }
         }
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_c2r_x(PassArgs a) {
+__global__ __launch_bounds__(kGenericThreads) void k_c2r_x(PassArgs a) {
     c2r_x_body<T>(a, a.in, a.out, blockIdx.x);
 }
 
@@ -341,7 +436,7 @@ __device__ __forceinline__ void *batch_out(const BatchArgs &b, const PassArgs &a
 }
 
 template <typename T, int DIR>
-__global__ __launch_bounds__(1024) void k_c2c_tile_b(BatchArgs b) {
+__global__ __launch_bounds__(kGenericThreads) void k_c2c_tile_b(BatchArgs b) {
     const long long blk = blockIdx.x;
     const int i = batch_find(b, blk);
     const PassArgs &a = b.args[i];
@@ -349,7 +444,7 @@ __global__ __launch_bounds__(1024) void k_c2c_tile_b(BatchArgs b) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_r2c_x_b(BatchArgs b) {
+__global__ __launch_bounds__(kGenericThreads) void k_r2c_x_b(BatchArgs b) {
     const long long blk = blockIdx.x;
     const int i = batch_find(b, blk);
     const PassArgs &a = b.args[i];
@@ -357,7 +452,7 @@ __global__ __launch_bounds__(1024) void k_r2c_x_b(BatchArgs b) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_c2r_x_b(BatchArgs b) {
+__global__ __launch_bounds__(kGenericThreads) void k_c2r_x_b(BatchArgs b) {
     const long long blk = blockIdx.x;
     const int i = batch_find(b, blk);
     const PassArgs &a = b.args[i];
@@ -366,6 +461,7 @@ __global__ __launch_bounds__(1024) void k_c2r_x_b(BatchArgs b) {
 
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t s) {
     if (L.blocks == 0) return hipSuccess;
+    if (L.threads == 0 || L.threads > (unsigned)kGenericThreads) return hipErrorInvalidConfiguration;
     const dim3 g(L.blocks), bl(L.threads);
     const bool f64 = L.prec != 0;
     switch (L.kind) {
@@ -659,6 +755,8 @@ hipError_t prepare_kernels(size_t max_lds) {
 hipError_t launch_pass(const PassDesc &d, hipStream_t s) {
     const dim3 g(d.blocks), b(d.threads);
     const bool f64 = d.prec != 0;
+    const bool generic = d.kind == PASS_C2C || d.kind == PASS_R2C_X || d.kind == PASS_C2R_X;
+    if (generic && (d.threads == 0 || d.threads > (unsigned)kGenericThreads)) return hipErrorInvalidConfiguration;
     switch (d.kind) {
         case PASS_C2C:
             if (f64) {

@@ -11,6 +11,9 @@ namespace pf {
 constexpr int kMaxStages = 16;  // radix stages of one 1D length
 constexpr int kEMax = 16;       // complex elements per thread per stage (F32; F64 uses half)
 constexpr int kMaxLds = 128 * 1024;  // dynamic LDS any kernel may request
+// threads per block of the generic kernels: the tile chooser keeps TC x wpc
+// <= 512, and n <= 8192 (FP32) / 4096 (FP64) keeps wpc <= 512 at TC = 1
+constexpr int kGenericThreads = 512;
 
 // Mixed-radix plan of one 1D length n = radix[0] * radix[1] * ...
 // Stage s has Ns = radix[0] * ... * radix[s-1] and reads its twiddles
