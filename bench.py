@@ -41,6 +41,9 @@ def parse():
                     help="summarise two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, WRITE_SIZE) "
                          "into profiles/ and exit")
     ap.add_argument("--pmc-commands", nargs=2, default=None, help="the two commands that produced the CSVs")
+    ap.add_argument("--kt-summary", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
+                    help="write the per-kernel summaries under profiles/ from a rocprofv3 kernel trace of this "
+                         "benchmark (COMMAND: the rocprofv3 command that produced it), then exit")
     return ap.parse_args()
 
 
@@ -74,6 +77,78 @@ def traffic_from_profile(pass_name: str, n: int):
         return None
     p = rec.get("passes", {}).get(pass_name)
     return None if p is None else p["hbm_bytes"]
+
+
+def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> None:
+    """Per-kernel statistics from a rocprofv3 kernel trace of this benchmark, one file per workload.
+
+    Dispatches are split where each section of the run starts: the 1024^3 plans
+    (plain, matrix-core variants, layout variants) up to the first generic-kernel
+    launch, which opens the batched section; the spectral step from its first
+    X launch (k_r2c_p2<256, ...>); the share-only leg from its first fill.
+    """
+    import csv
+
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    names = [r["Kernel_Name"] for r in rows]
+
+    def first(pred, start=0):
+        return next((i for i in range(start, len(rows)) if pred(names[i])), len(rows))
+
+    generic = ("k_c2c_tile", "k_r2c_x", "k_c2r_x")
+    b0 = first(lambda k: any(g in k for g in generic))
+    s0 = first(lambda k: "k_r2c_p2<256" in k, b0)
+    h0 = first(lambda k: "k_fill" in k, s0)
+
+    def table(rs):
+        d = {}
+        for r in rs:
+            d.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+        tot = sum(sum(v) for v in d.values()) or 1.0
+        out = [f"{'kernel':60s} {'calls':>7s} {'avg ms':>9s} {'min ms':>9s} {'max ms':>9s} {'% time':>7s}"]
+        for k, v in sorted(d.items(), key=lambda kv: -sum(kv[1])):
+            n = k if len(k) <= 60 else k[:57] + "..."
+            out.append(f"{n:60s} {len(v):7d} {statistics.mean(v):9.3f} {min(v):9.3f} {max(v):9.3f} "
+                       f"{100 * sum(v) / tot:7.2f}")
+        return out
+
+    pairs = steps + warmup
+    head = [f"command: {command}", "durations from the kernel trace (End - Start per dispatch), MI355X", ""]
+    files = {
+        "kernels_fft_1024cubed.txt": [
+            "rocprofv3 kernel-trace statistics, 1024^3 FP32 R2C+C2R, STRIDE1, out-of-place", *head,
+            f"full-grid plans: plain FP32 kernels <.., 0>: {pairs} pairs = {warmup} warm-up + {steps} timed; "
+            "matrix-core variants",
+            f"<.., 1> = FP16x2 and <.., 2> = BF16x2: {pairs} pairs each plus one forward for the error check; "
+            "the copy probe;",
+            f"the layout variants (Z-pencil without STRIDE1, in place, empty third transform: {pairs} pairs each, "
+            "their plain",
+            "kernels <.., 0> add to the counts above); torch kernels of the error checks and input copies",
+            *table(rows[:b0]), "",
+            "share-only leg: rank (0, 3) of a 1 x 8 grid, X-pencil [128][1024][1024] -> Z-pencil [513][128][1024],",
+            f"{pairs} pairs (the same transform kernels on the rank's share, plus fills and block copies)",
+            *table(rows[h0:])],
+        "kernels_batch64_mixed.txt": [
+            "rocprofv3 kernel-trace statistics, 64 batched FP32 R2C+C2R transforms "
+            "(synth.batch_sizes(4, 64), 7-smooth sizes in [48, 320]^3)", *head,
+            f"modes serial, serial + hipGraph, fused, fused + hipGraph, with default and tuned plans: "
+            f"{pairs} pairs each; k_*_b are the fused launches",
+            "(one per pass and block size), k_c2c_tile / k_r2c_x / k_c2r_x the serial ones (one per transform "
+            "and pass)", *table(rows[b0:s0])],
+        "kernels_cheb_spectral_512x512x257.txt": [
+            "rocprofv3 kernel-trace statistics, Chebyshev spectral step on 512 x 512 x 257 FP32 "
+            "(type-I DCT along z)", *head,
+            f"L u, L^T g and autograd forward + backward ({pairs} each), then {pairs} forward + backward "
+            "transform pairs",
+            "k_spec_p2<512, 16, ADJ>: the fused z pass (DCT, product, inverse DCT); k_c2c_p2<512, .., 4>: the "
+            "DCT Z passes", *table(rows[s0:h0])],
+    }
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    for name, lines in files.items():
+        with open(os.path.join(ROOT, "profiles", name), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print(f"wrote profiles/{name} ({len(lines)} lines)")
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
@@ -408,6 +483,9 @@ def share_only_timing(pf, nx, ny, nz, args, dev, stream, m2=8, r2=3):
 
 def main():
     args = parse()
+    if args.kt_summary:
+        summarize_trace(args.kt_summary[0], args.kt_summary[1], args.steps, args.warmup)
+        return
     if args.pmc_summary:
         summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.n, args.pmc_commands)
         return

@@ -223,13 +223,13 @@ __global__ __launch_bounds__(kGenericThreads) void k_c2c_tile(PassArgs a) {
 }
 
 // Row offsets in the blocked workspace of the 2 TC real lines of an X tile:
-// line g = z ny + y starts at (z nkb ny + y) B.
+// line g = z ny + y starts at row z zrows + y0 + y (column block 0).
 __device__ __forceinline__ void x_row_offsets(const PassArgs &a, long long g0, int nl, long long *rowoff) {
     for (int l = threadIdx.x; l < nl; l += blockDim.x) {
         const long long g = g0 + l;
         const long long z = g / a.ny;
         const long long y = g - z * a.ny;
-        rowoff[l] = ((z * a.nkb) * a.ypitch + a.y0 + y) << a.b_log2;
+        rowoff[l] = (z * a.zrows + a.y0 + y) << a.b_log2;
     }
 }
 
@@ -279,7 +279,7 @@ __device__ __forceinline__ void r2c_x_body(const PassArgs &a, const void *inp, v
                    act ? (tid & (wpc - 1)) : n, wpc);
     const int B = 1 << a.b_log2;
     const int total = a.nkb * TC * B;
-    const long long kbstride = (long long)a.ypitch << a.b_log2;
+    const long long kbstride = a.kbrows << a.b_log2;
     const T h = T(0.5);
     // modes f = (kb, cc, kk) of the tile, EH per thread at a time: LDS reads
     // first, then the split and the stores
@@ -339,7 +339,7 @@ __device__ __forceinline__ void c2r_x_body(const PassArgs &a, const void *inp, v
     __syncthreads();
     const int B = 1 << a.b_log2;
     const int total = a.nkb * TC * B;
-    const long long kbstride = (long long)a.ypitch << a.b_log2;
+    const long long kbstride = a.kbrows << a.b_log2;
     // modes f = (kb, cc, kk) of the tile, EH per thread at a time: all loads
     // in flight before the first wait, then the LDS writes
     constexpr int EH = Stage<T>::value / 2;
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs f) {
             r /= ny;
             const int kb = f.kb0[b] + (int)(r % nk);
             const int z = f.z0[b] + (int)(r / nk);
-            const long long row = ((long long)z * f.nkb + kb) * f.ny + f.y0[b] + y;
+            const long long row = (long long)z * f.zrows + (long long)kb * f.kbrows + f.y0[b] + y;
             const int kx0 = kb * f.B + c * epc;  // first mode of the chunk
             const long long at = row * CH + c;
             if (kx0 + epc <= f.keep0 || kx0 >= f.keep1) {

@@ -760,16 +760,16 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_spec_p2(PassArgs a, int nx,
 // W_nx^-k, after replacing X[0] and X[M] by their real parts (the staged
 // complex-to-real transform), and an unnormalised inverse DFT_M returns
 // x[2m] + i x[2m+1].  A tile is 16 consecutive lines (8 line pairs); the
-// spectra go to / come from the blocked workspace [z][kb][y][16].  Twiddles:
+// spectra go to / come from the blocked workspace (rows of 16 modes).  Twiddles:
 // a.tw holds the M-point stage table (M - 1 entries) and at offset M the
 // split table W_nx^k, k = 0 .. M.
 
 // Row offsets in the workspace of the 16 lines of tile t (line g = z ny + y
-// starts at (z nkb ny + y) 16).
+// starts at row z zrows + y0 + y, column block 0).
 __device__ __forceinline__ long long x_rowoff(const PassArgs &a, int g) {
     const int z = g / a.ny;
     const int y = g - z * a.ny;
-    return (((long long)z * a.nkb) * a.ypitch + a.y0 + y) << 4;
+    return ((long long)z * a.zrows + a.y0 + y) << 4;
 }
 
 template <int M, int MT>
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
     cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
     const int lines = (int)a.lines;
     const int ntiles = (lines + 15) / 16;
-    const long long kbstride = (long long)a.ypitch << 4;
+    const long long kbstride = a.kbrows << 4;
 
     auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
         const int tv = opaque_tid();
@@ -950,24 +950,23 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     // pair pr; it holds X[k] and X[M-k] of both lines (for k = 0 the partner is
     // X[M], the first slot of the last column block), and threads 0..15 hold
     // X[M/2] of line tid.  A wave reads whole 128-byte rows of the workspace.
-    // Addresses: one 64-bit tile base (uniform) plus 32-bit offsets (16 lines
-    // span at most 16 z planes of the workspace).
+    // Addresses: one 64-bit tile base (uniform) plus offsets from it.
     auto load = [&](float4(&xk)[NIT], float4(&xm)[NIT], float2 &xh, int t) {
         const int g0 = 16 * t;
         const int z0 = g0 / a.ny;
         const int y0 = g0 - z0 * a.ny;
-        const cx<float> *tb = in + ((((long long)z0 * a.nkb) * a.ypitch + a.y0 + y0) << 4);
-        const int zplane = a.nkb * a.ypitch * 16;  // elements per z plane of the workspace
-        const int kbs = a.ypitch * 16;
+        const cx<float> *tb = in + (((long long)z0 * a.zrows + a.y0 + y0) << 4);
+        const long long zplane = a.zrows * 16;  // elements between z planes of the workspace
+        const long long kbs = a.kbrows * 16;    // elements between column blocks
         // line l of the tile (g = g0 + l, any number of z planes when ny < 16)
         // starts at row offset rowrel(l) from the tile base (z0, y0)
         auto rowrel = [&](int l) {
             const int g = g0 + l;
             const int z = g / a.ny;
             const int y = g - z * a.ny;
-            return (z - z0) * zplane + (y - y0) * 16;
+            return (long long)(z - z0) * zplane + (y - y0) * 16;
         };
-        auto col = [&](int k) { return (k >> 4) * kbs + (k & 15); };
+        auto col = [&](int k) { return (long long)(k >> 4) * kbs + (k & 15); };
         // lines past the end load the last line instead; their results are never stored
         const int lmax = lines - 1 - g0;
         const int pr = (tid >> 4) & 7;  // the same line pair for every item (NT is a multiple of 128)

@@ -71,7 +71,8 @@ struct RemapArgs {
 // alone.  `words`: 4-byte words per element (2 for FP32 complex, 4 for FP64).
 struct FillArgs {
     void *w;
-    int words, B, ny, nkb;
+    int words, B, ny;
+    long long zrows, kbrows;  // workspace rows between z planes / column blocks
     int keep0, keep1;
     int nbox;
     int z0[4], z1[4], kb0[4], kb1[4], y0[4], y1[4];
@@ -109,11 +110,12 @@ struct PassArgs {
     int cheb;       // C2C pass: > 0 = lines of cheb points, transformed as their even
                     // extension of length fft.n = 2 (cheb - 1) (type-I DCT); 0 = plain
     // X passes: real lines (y, z) flattened as g = z * ny + y; line g's spectrum
-    // is workspace row (z nkb + kb) ypitch + y0 + y of column block kb
+    // is workspace row z zrows + kb kbrows + y0 + y of column block kb
     long long lines;
     long long ld_real;  // elements between consecutive real lines
     int ny, nkb, b_log2, nxh;
-    int ypitch, y0;
+    int y0;
+    long long zrows, kbrows;
 };
 
 struct PassDesc {
