@@ -335,14 +335,19 @@ def batch_timing(pf, args, dev, stream, count=64, seed=4, check=True):
     flops = sum(5.0 * N * math.log2(N) for N in Ns)
     nbytes = sum(2 * (N * 4 + (nx // 2 + 1) * ny * nz * 8) + 8 * (nx // 2 + 1) * ny * nz * 8
                  for N, (nx, ny, nz) in zip(Ns, dims))  # both directions: X, Y, Z passes
-    tuned = autotune.tune_for(dims)
+    serial_modes = (("serial", pf.PF_BATCH_SERIAL), ("serial_graph", pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH))
+    fused_modes = (("fused", pf.PF_BATCH_FUSED), ("fused_graph", pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH))
+    # the cached plans of each mode: radix orders and tiles (serial), radix orders alone (fused)
+    runs = (("default", None, serial_modes + fused_modes),
+            ("tuned", autotune.tune_for(dims, mode="serial"), serial_modes),
+            ("tuned", autotune.tune_for(dims, mode="fused"), fused_modes))
     out = {"count": count, "sizes": f"synth.batch_sizes({seed}, {count}): 7-smooth, each dimension in [48, 320]",
            "points": sum(Ns), "gflop_per_pair": flops / 1e9, "alg_bytes_per_pair": nbytes, "modes": {}}
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
-    for tname, tune in (("default", None), ("tuned", tuned)):
+    for tname, tune, modes in runs:
         if tname == "tuned" and tune is None:
-            out["modes"]["tuned"] = "no cached plans for these sizes"
+            out["modes"]["tuned_" + modes[0][0]] = "no cached plans for these sizes"
             continue
         b = pf.Batch(dims, tune=tune)
         R = b.empty(0).zero_()
@@ -351,8 +356,7 @@ def batch_timing(pf, args, dev, stream, count=64, seed=4, check=True):
         for i in range(count):
             v = b.view(R, 0, i)
             v.copy_(torch.rand(v.shape, generator=g, device=dev) * 2 - 1)
-        for mname, mode in (("serial", pf.PF_BATCH_SERIAL), ("serial_graph", pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH),
-                            ("fused", pf.PF_BATCH_FUSED), ("fused_graph", pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH)):
+        for mname, mode in modes:
             b.set_mode(mode)
             for _ in range(args.warmup):
                 b.ftran(R, C)

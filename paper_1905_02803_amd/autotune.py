@@ -4,10 +4,18 @@ tile width per axis (pf_tune), chosen by timing on the device.
 For each transform of the batch, the three axes are tuned one after the
 other (x, then y, then z), each by timing a one-transform batch
 (forward + backward) for every candidate of that axis with the other axes at
-their best so far.  Candidates: radix orders 0..3 (16-first, 8-first,
-4-first, odd-first) times tile widths {default, 1, 2, 4, 8, 16, 32} line
-pairs for x and {default, 1, 2, 4, 8} columns for y and z.  The result is
-cached as JSON keyed by the device name and "nx,ny,nz".
+their best so far.  Two searches per transform:
+
+* radix orders 0..3 (16-first, 8-first, 4-first, odd-first) with the default
+  tiles -- the plans of the fused mode, whose launches group transforms by
+  block size: a tile width of its own would put a transform in a group of
+  smaller blocks and split the launch, which one-transform timings cannot
+  see;
+* from there, radix orders times tile widths {default, 1, 2, 4, 8, 16, 32}
+  line pairs for x and {default, 1, 2, 4, 8} columns for y and z -- the
+  plans of the serial mode.
+
+The result is cached as JSON keyed by "nx,ny,nz".
 
 Usage (on a GPU):  python -m paper_1905_02803_amd.autotune --count 64 --seed 4 --out FILE
 """
@@ -37,15 +45,19 @@ def load(path: str = DEFAULT_CACHE) -> dict:
         return json.load(f)
 
 
-def tune_for(dims, path: str = DEFAULT_CACHE):
-    """pf_tune entries for dims from the cache, or None if any transform is missing."""
+def tune_for(dims, path: str = DEFAULT_CACHE, mode: str = "serial"):
+    """pf_tune entries for dims from the cache (mode "serial": radix orders and
+    tiles; "fused": radix orders, default tiles), or None if any transform is missing."""
     cache = load(path).get("entries", {})
     out = []
     for d in dims:
         e = cache.get(key(d))
-        if e is None:
+        if e is None or (mode == "fused" and "fused_radix_order" not in e):
             return None
-        out.append((tuple(e["radix_order"]), tuple(e["tile"])))
+        if mode == "fused":
+            out.append((tuple(e["fused_radix_order"]), (0, 0, 0)))
+        else:
+            out.append((tuple(e["radix_order"]), tuple(e["tile"])))
     return out
 
 
@@ -80,18 +92,27 @@ def tune_batch(dims, reps: int = 7, warm: int = 2, log=print) -> dict:
         best = [[0, 0, 0], [0, 0, 0]]  # radix orders, tiles
         base = _time_one(pf, torch, d, (tuple(best[0]), tuple(best[1])), reps, warm)
         cur = base
-        for axis in range(3):
-            for order in ORDERS:
-                for tile in TILES[axis]:
-                    cand = [list(best[0]), list(best[1])]
-                    cand[0][axis], cand[1][axis] = order, tile
-                    if cand == best:
-                        continue
-                    t = _time_one(pf, torch, d, (tuple(cand[0]), tuple(cand[1])), reps, warm)
-                    if t < cur:
-                        cur, best = t, cand
-        entries[k] = {"radix_order": best[0], "tile": best[1], "ms_default": base, "ms_tuned": cur}
-        log(f"[{n + 1}/{len(dims)}] {k}: default {base:.4f} ms -> {cur:.4f} ms with {best}", flush=True)
+
+        def search(tiles):
+            nonlocal cur, best
+            for axis in range(3):
+                for order in ORDERS:
+                    for tile in tiles[axis]:
+                        cand = [list(best[0]), list(best[1])]
+                        cand[0][axis], cand[1][axis] = order, tile
+                        if cand == best:
+                            continue
+                        t = _time_one(pf, torch, d, (tuple(cand[0]), tuple(cand[1])), reps, warm)
+                        if t < cur:
+                            cur, best = t, cand
+
+        search({0: (0,), 1: (0,), 2: (0,)})  # radix orders only
+        orders, ms_orders = list(best[0]), cur
+        search(TILES)
+        entries[k] = {"radix_order": best[0], "tile": best[1], "fused_radix_order": orders,
+                      "ms_default": base, "ms_orders": ms_orders, "ms_tuned": cur}
+        log(f"[{n + 1}/{len(dims)}] {k}: default {base:.4f} ms -> orders {orders} {ms_orders:.4f} ms -> "
+            f"{cur:.4f} ms with {best}", flush=True)
     return entries
 
 
