@@ -77,17 +77,18 @@ def test_spectral_step_matches_oracle(shape, stride1):
 
 
 FUSED = [(129, 6, 20), (257, 8, 12), (513, 5, 36), (1025, 3, 16), (2049, 2, 6)]
+UNFUSED = [(17, 16, 16), (33, 24, 20), (65, 10, 12)]  # other extension lengths: Z, product, Z as three passes
 
 
-@pytest.mark.parametrize("shape", FUSED, ids=lambda v: "x".join(map(str, v)))
-def test_fused_spectral_step_fp32(shape):
-    """FP32 with 2 (nz - 1) = 256 .. 4096: the z part (DCT, product, inverse DCT and
-    the adjoint's weights) runs as one pass on the workspace.  Checked against the
-    oracle's composition with the multiplier and the weights applied in numpy, and
-    by the dot-product identity; the spectrum never reaches the Z-pencil, so both
-    user layouts give the same bits."""
+@pytest.mark.parametrize("shape", FUSED + UNFUSED, ids=lambda v: "x".join(map(str, v)))
+def test_spectral_step_fp32(shape):
+    """FP32 step and adjoint against the oracle's composition with the multiplier
+    and the weights applied in numpy, and by the dot-product identity.  With
+    2 (nz - 1) = 256 .. 4096 the z part (DCT, product, inverse DCT and the
+    adjoint's weights) runs as one pass on the workspace; the spectrum never
+    reaches the Z-pencil, so both user layouts give the same bits."""
     nz, ny, nx = shape
-    print(f"case fused spectral step shape={shape}", flush=True)
+    print(f"case FP32 spectral step shape={shape}", flush=True)
     u = synth.uniform(71, shape).astype(np.float32)
     g = synth.uniform(72, shape).astype(np.float32)
     outs = []
@@ -95,17 +96,20 @@ def test_fused_spectral_step_fp32(shape):
         with pf.Plan(nx, ny, nz, pf.Layout(stride1=stride1, third=pf.PF_THIRD_CHEB)) as plan:
             ud, gd = torch.from_numpy(u).cuda(), torch.from_numpy(g).cuda()
             outs.append((pf.spectral_step(plan, ud), pf.spectral_step(plan, gd, adjoint=True)))
-    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
-    Lu, Ltg = outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy()
+    if shape in FUSED:
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
     M = multiplier(nx, ny, nz)
-    assert rel(Lu, oracle.c2r3d_cheb(oracle.r2c3d_cheb(u) * M, nx)) < 1e-6
     w = np.full(nz, 2.0)
     w[0] = w[-1] = 1.0
     w = w[:, None, None]
-    assert rel(Ltg, w * oracle.c2r3d_cheb(oracle.r2c3d_cheb(g / w) * np.conj(M), nx)) < 1e-6
-    a = float(np.sum(Lu.astype(np.float64) * g))
-    b = float(np.sum(u.astype(np.float64) * Ltg))
-    assert abs(a - b) <= 1e-5 * float(np.linalg.norm(Lu) * np.linalg.norm(g))
+    ref = oracle.c2r3d_cheb(oracle.r2c3d_cheb(u) * M, nx)
+    ref_t = w * oracle.c2r3d_cheb(oracle.r2c3d_cheb(g / w) * np.conj(M), nx)
+    for Lu, Ltg in ((o[0].cpu().numpy(), o[1].cpu().numpy()) for o in outs):
+        assert rel(Lu, ref) < 1e-6
+        assert rel(Ltg, ref_t) < 1e-6
+        a = float(np.sum(Lu.astype(np.float64) * g))
+        b = float(np.sum(u.astype(np.float64) * Ltg))
+        assert abs(a - b) <= 1e-5 * float(np.linalg.norm(Lu) * np.linalg.norm(g))
 
 
 def test_adjoint_dot_product_and_explicit_transpose():
