@@ -719,9 +719,11 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_spec_p2(PassArgs a, int nx,
                 const int k = q + T * m;
                 const float kzr = kzf * (float)(2 * k <= N ? k : N - k);
                 const float kz2 = kzr * kzr;
+                // 1 / |k|^2 by the hardware reciprocal (1 ulp): the step's FP32
+                // error budget is set by the transforms, not by this product
                 const float k20 = r0 + kz2, k21 = r1 + kz2;
-                const float mu0 = k20 > 0.f ? sg * (-scale * kx0r / k20) : 0.f;
-                const float mu1 = sg * (-scale * kx1r / k21);  // kx0 + 1 > 0
+                const float mu0 = k20 > 0.f ? sg * (-scale * kx0r) * __builtin_amdgcn_rcpf(k20) : 0.f;
+                const float mu1 = sg * (-scale * kx1r) * __builtin_amdgcn_rcpf(k21);  // kx0 + 1 > 0
                 v0[m] = make_float2(-mu0 * v0[m].y, mu0 * v0[m].x);
                 v1[m] = make_float2(-mu1 * v1[m].y, mu1 * v1[m].x);
             }
