@@ -302,10 +302,12 @@ int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjo
 /*
  * Many independent 3D transforms of different sizes run together (the same
  * method per transform, Sec. 2; the paper's "any grid dimensions", Sec. 3.1).
- * Each transform uses the generic kernels (runtime mixed-radix plans); a
- * fused pass is ONE kernel launch over the tiles of every transform's pass
- * (a device table maps each workgroup to its transform), so a direction is
- * three launches whatever the count.
+ * Each transform uses the generic kernels (runtime mixed-radix plans).  A
+ * fused pass is one kernel launch per distinct block size among the
+ * transforms' passes, over the tiles of every transform of that size (a
+ * device table maps each workgroup to its transform), so a direction takes
+ * at most three launches per block size whatever the count (block sizes are
+ * powers of two up to 512).
  *
  * pf_tune: per axis (x, y, z) a radix order (0: radix 16 first, then 8, 4, 2,
  * 3, 5, 7; 1: 8, 4, 2, 3, 5, 7; 2: 4, 2, 3, 5, 7; 3: 3, 5, 7 first, then 16,
@@ -321,7 +323,7 @@ typedef struct pf_tune {
 typedef struct pf_batch pf_batch;
 
 #define PF_BATCH_SERIAL 0  /* transform after transform, three launches each   */
-#define PF_BATCH_FUSED 1   /* one launch per pass over all transforms (default) */
+#define PF_BATCH_FUSED 1   /* per pass, one launch per block size over all transforms (default) */
 #define PF_BATCH_GRAPH 2   /* flag: replay the direction from a captured hipGraph */
 
 /*
