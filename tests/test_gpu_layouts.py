@@ -87,3 +87,42 @@ def test_useeven_changes_no_result(grid):
             torch.cuda.synchronize()
             outs.append((U.clone(), r.clone()))
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("nz", [17, 257])  # extension 32 (mixed-radix kernel) and 512 (power-of-two kernel)
+def test_cheb_third_transform_on_processor_grid_and_share(nz):
+    """The Chebyshev third transform (type-I DCT along z) on the m1 x m2 blocks
+    (bitwise slices of the 1 x 1 result) and on one share-only rank (the
+    masked oracle composition, restricted to the rank's Z-pencil block)."""
+    ny, nx = 20, 32
+    print(f"case cheb grid/share nz={nz}", flush=True)
+    u = synth.uniform(78, (nz, ny, nx)).astype(np.float32)
+    base = dict(third=pf.PF_THIRD_CHEB)
+    with pf.Plan(nx, ny, nz, pf.Layout(**base)) as full:
+        ref = full.ftran(torch.from_numpy(u).cuda()).cpu().numpy()  # [kx][ky][kz]
+    assert rel(ref, oracle.to_stride1(oracle.r2c3d_cheb(u))) < 1e-6
+    # m1 x m2 blocks: the concatenated Z-pencil blocks are the 1 x 1 result, bitwise
+    from tests.test_gpu_grid import blocks, unblocks
+
+    nxh = nx // 2 + 1
+    lay = pf.Layout(m1=2, m2=3, **base)
+    with pf.Plan(nx, ny, nz, lay) as grid:
+        ub = torch.from_numpy(blocks(u.transpose(2, 1, 0), nx, ny, nz, lay, pf.PF_PENCIL_X)).cuda()
+        out = torch.empty(nxh * ny * nz, dtype=torch.complex64, device="cuda")
+        pf.pf_ftran_r2c(grid.handle, ub.data_ptr(), out.data_ptr(), 0)
+        torch.cuda.synchronize()
+    assert np.array_equal(unblocks(out.cpu().numpy(), (nxh, ny, nz), nx, ny, nz, lay, pf.PF_PENCIL_Z), ref)
+    # share-only rank (1, 2) of the same grid
+    lay = pf.Layout(m1=2, m2=3, share_only=1, r1=1, r2=2, **base)
+    stx, szx, _ = pf.pf_query_dims(nx, ny, nz, lay, pf.PF_PENCIL_X, 1, 2)
+    stz, szz, _ = pf.pf_query_dims(nx, ny, nz, lay, pf.PF_PENCIL_Z, 1, 2)
+    xz, xy = slice(stx[2], stx[2] + szx[2]), slice(stx[1], stx[1] + szx[1])
+    zkx, zky = slice(stz[0], stz[0] + szz[0]), slice(stz[1], stz[1] + szz[1])
+    um = np.zeros_like(u)
+    um[xz, xy, :] = u[xz, xy, :]
+    with pf.Plan(nx, ny, nz, lay) as share:
+        got = share.ftran(torch.from_numpy(np.ascontiguousarray(u[xz, xy, :])).cuda()).cpu().numpy()
+    want = oracle.to_stride1(oracle.r2c3d_cheb(um))
+    # normalised by the whole masked transform (FP32 rounding scale), as for the other share tests
+    err = np.linalg.norm((got - want[zkx, zky, :]).ravel()) / np.linalg.norm(want.ravel())
+    assert err < 1e-6
