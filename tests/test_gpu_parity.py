@@ -104,6 +104,27 @@ def test_forward_and_backward_match_oracle(shape, prec, stride1):
         assert rel(back.cpu().numpy() / (nx * ny * nz), u) < TOL[prec]
 
 
+# the longest lines each precision accepts on every axis (FP32 8192, FP64 4096), and
+# 4096 / 8192 where the power-of-two kernels stop (X above 2048, Y and Z above 4096)
+MAX_CASES = [((2, 3, 8192), pf.PF_F32), ((3, 8192, 2), pf.PF_F32), ((8192, 2, 3), pf.PF_F32),
+             ((2, 3, 4096), pf.PF_F32), ((3, 4096, 2), pf.PF_F32),
+             ((2, 3, 4096), pf.PF_F64), ((3, 4096, 2), pf.PF_F64), ((4096, 2, 3), pf.PF_F64)]
+
+
+@pytest.mark.parametrize("stride1", [1, 0])
+@pytest.mark.parametrize("shape,prec", MAX_CASES, ids=lambda v: ids(v) if isinstance(v, tuple) else str(v))
+def test_maximum_lengths_match_oracle(shape, prec, stride1):
+    nz, ny, nx = shape
+    print(f"case max shape={shape} prec={prec} stride1={stride1}", flush=True)
+    u = synth.uniform(200 + nx + ny, shape).astype(np_real(prec))
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=prec, stride1=stride1)) as plan:
+        got = plan.ftran(torch.from_numpy(u).cuda()).cpu().numpy()
+        assert rel(got, to_layout(oracle.r2c3d(u), stride1)) < TOL[prec]
+        V = synth.complex_half(201 + nx, (nz, ny, nx // 2 + 1)).astype(np_cplx(prec))
+        back = plan.btran(torch.from_numpy(to_layout(V, stride1)).cuda()).cpu().numpy()
+        assert rel(back, oracle.c2r3d(V, nx)) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [pf.PF_F32, pf.PF_F64])
 @pytest.mark.parametrize("shape", [(24, 20, 36), (9, 7, 15), (6, 10, 480), (3, 1024, 2), (16, 512, 36), (1024, 6, 40),
                                    (5, 7, 512), (40, 24, 1024)], ids=ids)
