@@ -147,3 +147,51 @@ def test_batch_argument_errors():
         with pytest.raises(pf.PfError) as e:
             b.set_mode(9)
         assert e.value.code == pf.PF_EINVAL
+
+
+@pytest.mark.timeout(600)
+def test_full_batch_workload():
+    """The benchmark's batch (synth.batch_sizes(4, 64): 64 transforms, 285.8 M points)
+    in the configurations it times: fused and graph-replayed with the tuned fused
+    plans, and the serial chains with the tuned serial plans.  Every transform
+    round-trips to N u; fused and serial results agree to rounding (their tuned
+    radix orders differ); the two smallest transforms and the largest match the
+    FP64 oracle in full."""
+    from paper_1905_02803_amd import autotune
+
+    dims = synth.batch_sizes(4, 64)
+    print(f"case full batch: {len(dims)} transforms", flush=True)
+    outs = {}
+    for mode, tune in ((pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH, autotune.tune_for(dims, mode="fused")),
+                       (pf.PF_BATCH_SERIAL, autotune.tune_for(dims, mode="serial"))):
+        with pf.Batch(dims, mode=mode, tune=tune) as b:
+            R = b.empty(0).zero_()
+            C = b.empty(1).zero_()
+            R2 = b.empty(0).zero_()
+            g = torch.Generator(device="cuda")
+            g.manual_seed(4)
+            for i in range(len(dims)):
+                v = b.view(R, 0, i)
+                v.copy_(torch.rand(v.shape, generator=g, device="cuda") * 2 - 1)
+            for _ in range(2):  # the second call replays the captured graph
+                b.ftran(R, C)
+            b.btran(C, R2)
+            torch.cuda.synchronize()
+            for i, (nx, ny, nz) in enumerate(dims):
+                u, back = b.view(R, 0, i), b.view(R2, 0, i)
+                err = float((back / (nx * ny * nz) - u).norm() / u.norm())
+                assert err < 1e-6, (i, dims[i], err)
+            outs[mode] = (R.clone(), C.clone())
+            if mode & pf.PF_BATCH_FUSED:
+                order = sorted(range(len(dims)), key=lambda j: dims[j][0] * dims[j][1] * dims[j][2])
+                for i in order[:2] + order[-1:]:
+                    u = b.view(R, 0, i).cpu().numpy()
+                    ref = oracle.to_stride1(oracle.r2c3d(u))
+                    assert rel(b.view(C, 1, i).cpu().numpy(), ref) < 1e-6, (i, dims[i])
+    (Rf, Cf), (Rs, Cs) = outs[pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH], outs[pf.PF_BATCH_SERIAL]
+    assert torch.equal(Rf, Rs)
+    # tuned radix orders differ between the two plan sets, so compare per transform to rounding
+    with pf.Batch(dims) as b:
+        for i in range(len(dims)):
+            cf, cs = b.view(Cf, 1, i), b.view(Cs, 1, i)
+            assert float((cf - cs).norm() / cs.norm()) < 1e-6, (i, dims[i])

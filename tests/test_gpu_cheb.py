@@ -149,7 +149,8 @@ def test_gradcheck_16x16x17():
 
 @pytest.mark.timeout(600)
 def test_512x512x257_config_matches_oracle():
-    """The benchmark's own Chebyshev grid (FP32, GRF-like data): forward transform and the step."""
+    """The benchmark's own Chebyshev grid (FP32): forward transform, the step against the
+    oracle, and the adjoint by the dot-product identity and as autograd's gradient."""
     nz, ny, nx = 257, 512, 512
     print("case 512x512x257 FP32", flush=True)
     u = synth.uniform(90, (nz, ny, nx)).astype(np.float32)
@@ -161,3 +162,15 @@ def test_512x512x257_config_matches_oracle():
     assert rel(got, oracle.to_stride1(U)) < 1e-6
     ref = oracle.c2r3d_cheb(U * multiplier(nx, ny, nz), nx)
     assert rel(step, ref) < 1e-6
+    # the adjoint at full size: <L u, g> = <u, L^T g>, and autograd's gradient is L^T of its seed
+    g = synth.uniform(91, (nz, ny, nx)).astype(np.float32)
+    with pf.Plan(nx, ny, nz, pf.Layout(third=pf.PF_THIRD_CHEB)) as plan:
+        gd = torch.from_numpy(g).cuda()
+        ltg = pf.spectral_step(plan, gd, adjoint=True)
+        ud = torch.from_numpy(u).cuda().requires_grad_(True)
+        (pf.spectral_step_autograd(ud, plan) * gd).sum().backward()
+        assert torch.equal(ud.grad, ltg)
+        ltg = ltg.cpu().numpy()
+    a = float(np.sum(step.astype(np.float64) * g))
+    b = float(np.sum(u.astype(np.float64) * ltg))
+    assert abs(a - b) <= 1e-5 * float(np.linalg.norm(step) * np.linalg.norm(g))
