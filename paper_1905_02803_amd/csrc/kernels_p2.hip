@@ -876,40 +876,40 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
         __syncthreads();
 
         // split and store: chunk = (column block kb, line pair pr, mode pair kp)
-        for (int f = tv; f < NKB * 64; f += NT) {
+        // over the first M modes; the chunks of k = 0 also store mode M (alone
+        // in the last column block, and computed from Z[0] as mode 0 is)
+        auto split = [&](int k, int pr, float2 &xa, float2 &xb) {
+            const int kz = k < M ? k : k - M;       // Z is M-periodic
+            const int km = k == 0 ? 0 : M - k;      // (M - k) mod M for k <= M
+            const float4 zk = buf[p2_slot<TC>(kz < M ? kz : 0, pr)];
+            const float4 zm = buf[p2_slot<TC>(km < M ? km : 0, pr)];
+            const cx<float> w = spl[k <= M ? k : M];
+            // line a: (zk.x, zk.y), (zm.x, zm.y); line b: .z, .w
+            const float2 Ea = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            const float2 Oa = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+            const float2 Eb = make_float2(0.5f * (zk.z + zm.z), 0.5f * (zk.w - zm.w));
+            const float2 Ob = make_float2(0.5f * (zk.w + zm.w), 0.5f * (zm.z - zk.z));
+            xa = cadd(Ea, cmul(w, Oa));
+            xb = cadd(Eb, cmul(w, Ob));
+        };
+        for (int f = tv; f < (NKB - 1) * 64; f += NT) {
             const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
             const int ga = 16 * t + 2 * pr;
             const int k0 = kb * 16 + 2 * kp;
-            if (ga >= lines || k0 > M) continue;
+            if (ga >= lines) continue;
             float2 xa[2], xb[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int k = k0 + e;
-                const int kz = k < M ? k : k - M;       // Z is M-periodic
-                const int km = k == 0 ? 0 : M - k;      // (M - k) mod M for k <= M
-                const float4 zk = buf[p2_slot<TC>(kz < M ? kz : 0, pr)];
-                const float4 zm = buf[p2_slot<TC>(km < M ? km : 0, pr)];
-                const cx<float> w = spl[k <= M ? k : M];
-                // line a: (zk.x, zk.y), (zm.x, zm.y); line b: .z, .w
-                const float2 Ea = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-                const float2 Oa = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
-                const float2 Eb = make_float2(0.5f * (zk.z + zm.z), 0.5f * (zk.w - zm.w));
-                const float2 Ob = make_float2(0.5f * (zk.w + zm.w), 0.5f * (zm.z - zk.z));
-                xa[e] = cadd(Ea, cmul(w, Oa));
-                xb[e] = cadd(Eb, cmul(w, Ob));
-            }
+            for (int e = 0; e < 2; ++e) split(k0 + e, pr, xa[e], xb[e]);
             const long long col = (long long)kb * kbstride + 2 * kp;
-            cx<float> *oa = out + rowoff[2 * pr] + col;
-            if (k0 + 1 <= M)
-                gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(oa), pack2(xa[0], xa[1]));
-            else
-                gst<streamed<ST_R2C>()>(oa, xa[0]);
-            if (ga + 1 < lines) {
-                cx<float> *ob = out + rowoff[2 * pr + 1] + col;
-                if (k0 + 1 <= M)
-                    gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(ob), pack2(xb[0], xb[1]));
-                else
-                    gst<streamed<ST_R2C>()>(ob, xb[0]);
+            gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(out + rowoff[2 * pr] + col), pack2(xa[0], xa[1]));
+            if (ga + 1 < lines)
+                gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(out + rowoff[2 * pr + 1] + col), pack2(xb[0], xb[1]));
+            if (k0 == 0) {
+                float2 na, nb;
+                split(M, pr, na, nb);
+                const long long cm = (long long)(NKB - 1) * kbstride;
+                gst<streamed<ST_R2C>()>(out + rowoff[2 * pr] + cm, na);
+                if (ga + 1 < lines) gst<streamed<ST_R2C>()>(out + rowoff[2 * pr + 1] + cm, nb);
             }
         }
         __syncthreads();  // LDS tile and row offsets are reused by the next tile
