@@ -166,15 +166,17 @@ void block_split(int n, int M, int r, int *start, int *size) {
     *start = r * q + (r < rem ? r : rem);
 }
 
-// Threads per column (power of two, >= n / kEMax) and columns per tile.
-void choose_tile(int n, int csize, int max_tc, int *tc_log2, int *wpc_log2, int *pitch, size_t *lds) {
+// Threads per column (power of two, >= n / kEMax) and columns per tile, while
+// the tile fits max_threads threads and the LDS budget.
+void choose_tile(int n, int csize, int max_tc, int *tc_log2, int *wpc_log2, int *pitch, size_t *lds,
+                 int max_threads = 512) {
     const int emax = csize == 16 ? pf::kEMax / 2 : pf::kEMax;  // elements per thread (F64 halves it)
     int wpc = 1;
     while (wpc * emax < n) wpc <<= 1;
     if (wpc > 1024) wpc = 1024;
     const int p = pf::pidx(n - 1) + 1;
     int tc = 1;
-    while (tc * 2 <= max_tc && tc * 2 * wpc <= 512 && (size_t)(tc * 2) * p * csize <= kLdsBudget) tc <<= 1;
+    while (tc * 2 <= max_tc && tc * 2 * wpc <= max_threads && (size_t)(tc * 2) * p * csize <= kLdsBudget) tc <<= 1;
     *tc_log2 = ilog2(tc);
     *wpc_log2 = ilog2(wpc);
     *pitch = p;
@@ -515,7 +517,9 @@ void build_passes(pf_plan *p) {
         x.a.fft = p->fx;
         x.a.tw = (const char *)p->tw_dev + p->tw_off[0];
         const int xmax = p->opt.tile[0] > 0 && p->opt.tile[0] < 64 ? p->opt.tile[0] : 64;
-        choose_tile(p->nx, p->csize, xmax, &x.a.tc_log2, &x.a.wpc_log2, &x.a.pitch, &x.lds);
+        // X tiles of at most 256 threads: more, smaller blocks per CU measured
+        // 3-9% faster on the generic X passes (the Y / Z passes keep 512)
+        choose_tile(p->nx, p->csize, xmax, &x.a.tc_log2, &x.a.wpc_log2, &x.a.pitch, &x.lds, 256);
         x.threads = 1u << (x.a.tc_log2 + x.a.wpc_log2);
         x.a.lines = (long long)p->ny * p->nz;
         x.a.ld_real = p->nx;
