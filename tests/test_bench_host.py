@@ -1,0 +1,94 @@
+"""Host logic of the benchmark's profile pipeline (CPU only), on synthetic
+rocprofv3 CSV files: the kernel-trace summary splits the run into its
+workloads, and the counter summary scales FETCH_SIZE / WRITE_SIZE by the copy
+probe and assigns the transform's dispatches to passes in launch order."""
+import csv
+import json
+import os
+
+import pytest
+
+import bench
+
+KERNELS = ["void pf::k_r2c_p2<512, 0>(pf::PassArgs)",
+           "void pf::k_c2c_p2<1024, 16, -1, 0, 0, 0>(pf::PassArgs)",
+           "void pf::k_c2c_p2<1024, 16, -1, 0, 1, 0>(pf::PassArgs)",
+           "void pf::k_c2c_p2<1024, 16, 1, 1, 0, 0>(pf::PassArgs)",
+           "void pf::k_c2c_p2<1024, 16, 1, 0, 0, 0>(pf::PassArgs)",
+           "void pf::k_c2r_p2<512, 0>(pf::PassArgs)"]
+
+
+@pytest.fixture
+def tmp_root(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernels_digest", lambda: "digest")
+    return tmp_path
+
+
+def write_trace(path, names_ms):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        t = 1000
+        for i, (name, ms) in enumerate(names_ms):
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Start_Timestamp": t,
+                        "End_Timestamp": t + int(ms * 1e6)})
+            t += int(ms * 1e6) + 10
+
+
+def test_trace_summary_splits_the_workloads(tmp_root):
+    trace = tmp_root / "kt.csv"
+    names = [(KERNELS[0], 2.0), (KERNELS[0], 1.0), (KERNELS[1], 1.5),
+             ("void pf::k_c2c_tile<float, -1>(pf::PassArgs)", 0.02),       # the batch begins
+             ("void pf::k_c2c_tile_b<float, -1>(pf::BatchArgs)", 0.3),
+             ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 0.11),             # the spectral step begins
+             ("void pf::k_spec_p2<512, 16, 0>(pf::PassArgs, int, float)", 0.23),
+             ("pf::k_fill(pf::FillArgs)", 0.09),                            # the share-only leg begins
+             (KERNELS[0], 0.28)]
+    write_trace(trace, names)
+    bench.summarize_trace(str(trace), "CMD", steps=10, warmup=2)
+    prof = tmp_root / "profiles"
+    main = (prof / "kernels_fft_1024cubed.txt").read_text()
+    batch = (prof / "kernels_batch64_mixed.txt").read_text()
+    spec = (prof / "kernels_cheb_spectral_512x512x257.txt").read_text()
+    assert "command: CMD" in main and "command: CMD" in batch and "command: CMD" in spec
+    # the 1024^3 table: two launches of the X kernel averaging 1.5 ms, then the share leg
+    head, share = main.split("share-only leg")
+    row = next(line for line in head.splitlines() if line.startswith(KERNELS[0]))
+    assert row.split()[-5:-3] == ["2", "1.500"]
+    assert "k_fill" in share and "k_fill" not in head and "k_c2c_tile" not in main
+    assert "k_c2c_tile_b" in batch and "k_spec_p2" not in batch and "k_r2c_p2<512" not in batch
+    assert "k_spec_p2" in spec and "k_fill" not in spec
+
+
+def write_counters(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, (name, kib) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": kib})
+
+
+def test_counter_summary_scales_by_the_copy_probe_and_assigns_passes(tmp_root):
+    n = 16
+    copy_kib = bench.COPY_BYTES(n) / 1024.0
+    # FETCH reads half of the copy's bytes (scale 2), WRITE all of them (scale 1)
+    for counter, copy_val, path in (("FETCH_SIZE", copy_kib / 2, "fetch.csv"), ("WRITE_SIZE", copy_kib, "write.csv")):
+        rows = []
+        for rep in range(2):  # two forward + backward pairs: pass i reads i + 1 KiB
+            rows += [(k, float(i + 1)) for i, k in enumerate(KERNELS)]
+        rows += [("void pf::k_c2c_p2<1024, 16, -1, 0, 1, 1>(pf::PassArgs)", 99.0)]  # a later variant: not counted
+        rows += [("pf::k_copy(HIP_vector_type<float, 4u> const*, HIP_vector_type<float, 4u>*, unsigned long)",
+                  copy_val)]
+        write_counters(tmp_root / path, counter, rows)
+    bench.summarize_pmc(str(tmp_root / "fetch.csv"), str(tmp_root / "write.csv"), n, ["A", "B"])
+    rec = json.loads((tmp_root / "profiles" / f"traffic_fft_{n}cubed.json").read_text())
+    assert rec["kernels_sha256"] == "digest"
+    assert rec["FETCH_SIZE"]["scale"] == pytest.approx(2.0) and rec["WRITE_SIZE"]["scale"] == pytest.approx(1.0)
+    for i, name in enumerate(bench.PASS_ORDER):
+        e = rec["passes"][name]
+        assert e["kernel"] == KERNELS[i] and e["dispatches"] == 2
+        assert e["fetch_bytes"] == pytest.approx(2 * 1024 * (i + 1))
+        assert e["write_bytes"] == pytest.approx(1024 * (i + 1))
+        assert e["hbm_bytes"] == pytest.approx(3 * 1024 * (i + 1))
+    assert os.path.exists(tmp_root / "profiles" / f"traffic_fft_{n}cubed.txt")
