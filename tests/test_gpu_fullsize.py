@@ -9,6 +9,8 @@
 * 512^3 and 480 x 360 x 250 FP32 random fields: the same checks.
 * 32^3 FP64, uniform[-1, 1] from seed 1: forward, backward and round trip at
   1e-12.
+* 2048^3 FP32 (eight times the benchmark's grid): round trip and Parseval,
+  which hold at any size, reduced on the device.
 The oracle runs in FP64 on the host (OpenMP); FP32 inputs are promoted exactly.
 """
 import numpy as np
@@ -113,3 +115,34 @@ def test_32_cubed_f64_matches_oracle():
         vd = plan.btran(torch.from_numpy(oracle.to_stride1(V)).cuda())
         torch.cuda.synchronize()
         assert rel(vd.cpu().numpy(), oracle.c2r3d(V, 32)) < 1e-12
+
+
+@pytest.mark.timeout(600)
+def test_2048_cubed_round_trip_and_parseval():
+    """A grid eight times the benchmark's (2048^3 FP32, 34 GB per array; the
+    power-of-two kernels with 8-column Y / Z tiles and the 1024-point X
+    kernel): properties that hold at any size, reduced on the device in FP64
+    chunks -- the round trip returns N u, and Parseval holds with the
+    half-spectrum weights (1 for kx = 0 and nx/2, 2 otherwise)."""
+    n = 2048
+    print("case 2048^3 round trip and Parseval", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    u = torch.empty((n, n, n), device="cuda", dtype=torch.float32).uniform_(-1.0, 1.0, generator=g)
+    with pf.Plan(n, n, n) as plan:
+        U = plan.ftran(u)                     # STRIDE1 [kx][ky][kz]
+        back = plan.btran(U)
+        torch.cuda.synchronize()
+        su = sd = se = 0.0
+        for z in range(0, n, 64):
+            uc = u[z:z + 64].double()
+            su += float((uc * uc).sum())
+            d = back[z:z + 64].double() / float(n) ** 3 - uc
+            sd += float((d * d).sum())
+        w = torch.full((n // 2 + 1,), 2.0, dtype=torch.float64, device="cuda")
+        w[0] = w[-1] = 1.0
+        for kx in range(0, n // 2 + 1, 64):
+            Uc = U[kx:kx + 64]
+            se += float((Uc.real.double() ** 2 + Uc.imag.double() ** 2).sum(dim=(1, 2)).mul(w[kx:kx + 64]).sum())
+    assert (sd / su) ** 0.5 < 1e-6
+    assert abs(se / float(n) ** 3 - su) <= 1e-6 * su
