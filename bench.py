@@ -85,7 +85,8 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
     Dispatches are split where each section of the run starts: the 1024^3 plans
     (plain, matrix-core variants, layout variants) up to the first generic-kernel
     launch, which opens the batched section; the spectral step from its first
-    X launch (k_r2c_p2<256, ...>); the share-only leg from its first fill.
+    X launch (k_r2c_p2<256, ...>); the share-only leg from its first fill; the
+    other grids (512^3, then 480 x 360 x 250) from the next k_r2c_p2<256, ...>.
     """
     import csv
 
@@ -100,6 +101,7 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
     b0 = first(lambda k: any(g in k for g in generic))
     s0 = first(lambda k: "k_r2c_p2<256" in k, b0)
     h0 = first(lambda k: "k_fill" in k, s0)
+    o0 = first(lambda k: "k_r2c_p2<256" in k, h0)
 
     def table(rs):
         d = {}
@@ -128,7 +130,11 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
             *table(rows[:b0]), "",
             "share-only leg: rank (0, 3) of a 1 x 8 grid, X-pencil [128][1024][1024] -> Z-pencil [513][128][1024],",
             f"{pairs} pairs (the same transform kernels on the rank's share, plus fills and block copies)",
-            *table(rows[h0:])],
+            *table(rows[h0:o0])],
+        "kernels_fft_512cubed_480x360x250.txt": [
+            "rocprofv3 kernel-trace statistics, FP32 R2C+C2R at 512^3 (power-of-two kernels) and "
+            "480 x 360 x 250 (mixed-radix kernels), STRIDE1, out-of-place", *head,
+            f"{pairs} pairs each", *table(rows[o0:])],
         "kernels_batch64_mixed.txt": [
             "rocprofv3 kernel-trace statistics, 64 batched FP32 R2C+C2R transforms "
             "(synth.batch_sizes(4, 64), 7-smooth sizes in [48, 320]^3)", *head,
@@ -270,6 +276,42 @@ def cpu_baseline(n: int, u=None, forward_outputs=None):
         "kind": "oracle",
         "sample": f"one R2C+C2R pair at {n}^3 (FP64, OpenMP over lines), {dt:.2f} s wall",
     }, errs
+
+
+def other_grid_timings(pf, args, dev, stream):
+    """The other FP32 grids of the plain path (STRIDE1, out-of-place, uniform[-1, 1] data): 512^3, all on
+    the power-of-two kernels, and the uneven 480 x 360 x 250, all on the mixed-radix ones: ms per pair,
+    GFLOP/s and algorithmic HBM GB/s."""
+    import torch
+
+    out = {}
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    for nx, ny, nz in ((512, 512, 512), (480, 360, 250)):
+        plan = pf.Plan(nx, ny, nz, pf.Layout())
+        u = torch.empty((nz, ny, nx), device=dev, dtype=torch.float32).uniform_(-1.0, 1.0, generator=g)
+        U = plan.empty_complex(dev)
+        r = plan.empty_real(dev)
+        for _ in range(args.warmup):
+            plan.ftran(u, U)
+            plan.btran(U, r)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.ftran(u, U)
+            plan.btran(U, r)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        N = float(nx) * ny * nz
+        nbytes = sum(plan.pass_bytes(d, i) for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD)
+                     for i in range(plan.num_passes(d)))
+        out[f"{nx}x{ny}x{nz}"] = {"ms_per_pair": ms, "gflops": 5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9,
+                                  "alg_GBps": nbytes / (ms * 1e-3) / 1e9}
+        plan.destroy()
+    return out
 
 
 def layout_timings(pf, nx, ny, nz, args, dev, stream, u):
@@ -596,6 +638,7 @@ def main():
     batched = batch_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
     spectral = spectral_timing(pf, args, dev, stream)
     share = share_only_timing(pf, nx, ny, nz, args, dev, stream)
+    other_grids = other_grid_timings(pf, args, dev, stream)  # last: the trace summary splits on its first launch
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
     gflops = flops / (ms * 1e-3) / 1e9
@@ -644,6 +687,7 @@ def main():
         "passes": passes,
         "share_only": share,
         "layouts": layouts,
+        "other_grids": other_grids,
         "batched": batched,
         "spectral_step": spectral,
         "cpu_baseline": cpu,

@@ -44,7 +44,9 @@ def test_trace_summary_splits_the_workloads(tmp_root):
              ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 0.11),             # the spectral step begins
              ("void pf::k_spec_p2<512, 16, 0>(pf::PassArgs, int, float)", 0.23),
              ("pf::k_fill(pf::FillArgs)", 0.09),                            # the share-only leg begins
-             (KERNELS[0], 0.28)]
+             (KERNELS[0], 0.28),
+             ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 0.4),              # the other grids begin
+             ("void pf::k_r2c_x<float>(pf::PassArgs)", 0.1)]
     write_trace(trace, names)
     bench.summarize_trace(str(trace), "CMD", steps=10, warmup=2)
     prof = tmp_root / "profiles"
@@ -59,6 +61,9 @@ def test_trace_summary_splits_the_workloads(tmp_root):
     assert "k_fill" in share and "k_fill" not in head and "k_c2c_tile" not in main
     assert "k_c2c_tile_b" in batch and "k_spec_p2" not in batch and "k_r2c_p2<512" not in batch
     assert "k_spec_p2" in spec and "k_fill" not in spec
+    other = (prof / "kernels_fft_512cubed_480x360x250.txt").read_text()
+    assert "k_r2c_p2<256" in other and "k_r2c_x<float>" in other and "k_fill" not in other
+    assert "k_r2c_x<float>" not in share
 
 
 def write_counters(path, counter, rows):
