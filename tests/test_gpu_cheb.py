@@ -112,6 +112,28 @@ def test_spectral_step_fp32(shape):
         assert abs(a - b) <= 1e-5 * float(np.linalg.norm(Lu) * np.linalg.norm(g))
 
 
+@pytest.mark.parametrize("prec", [pf.PF_F64, pf.PF_F32])
+@pytest.mark.parametrize("shape,k0,q0", [((17, 8, 16), 3, 5), ((17, 8, 16), 1, 0), ((129, 6, 20), 4, 37)],
+                         ids=["17x8x16-k3-q5", "17x8x16-k1-q0", "129x6x20-k4-q37"])
+def test_spectral_step_closed_form(shape, k0, q0, prec):
+    """An analytic pin of the step, independent of the oracle: a cosine in x times
+    a Gauss-Lobatto cosine in z is one mode of the transform (the latter is an
+    eigenvector of the type-I DCT), so L u = i kx' (-1/|k'|^2) u in that mode,
+    i.e. L u = kx' / (kx'^2 + kz'^2) sin(2 pi k0 x / nx) cos(pi q0 z / (nz - 1))
+    with kx' = 2 pi k0 / nx, kz' = pi q0 / (nz - 1), uniform in y."""
+    nz, ny, nx = shape
+    x = np.arange(nx)[None, None, :]
+    z = np.arange(nz)[:, None, None]
+    u = np.cos(2 * np.pi * k0 * x / nx) * np.cos(np.pi * q0 * z / (nz - 1)) * np.ones((1, ny, 1))
+    kx, kz = 2 * np.pi * k0 / nx, np.pi * q0 / (nz - 1)
+    want = kx / (kx * kx + kz * kz) * np.sin(2 * np.pi * k0 * x / nx) * np.cos(np.pi * q0 * z / (nz - 1)) \
+        * np.ones((1, ny, 1))
+    rdt = np.float64 if prec == pf.PF_F64 else np.float32
+    with pf.Plan(nx, ny, nz, pf.Layout(precision=prec, third=pf.PF_THIRD_CHEB)) as plan:
+        got = pf.spectral_step(plan, torch.from_numpy(u.astype(rdt)).cuda()).cpu().numpy()
+    assert rel(got, want) < (1e-12 if prec == pf.PF_F64 else 1e-6)
+
+
 def test_adjoint_dot_product_and_explicit_transpose():
     nz, ny, nx = 9, 8, 10
     with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F64, third=pf.PF_THIRD_CHEB)) as plan:

@@ -349,3 +349,26 @@ def test_stages_compose_to_the_whole_transform(shape):
     U = synth.complex_half(26, (nz, ny, nx // 2 + 1))
     B = oracle.stage_c2c(oracle.stage_c2c(U, nx, "z", +1), nx, "y", +1)
     assert rel(oracle.stage_x_c2r(B, nx), brute_c2r(U, nx)) < 1e-13
+
+
+def test_cheb_composition_with_the_spectral_multiplier_has_the_closed_form():
+    """The reference the spectral-step tests build from the oracle (Chebyshev
+    forward, the multiplier m = i kx' (-1/|k'|^2) / (nx ny 2 (nz - 1)), Chebyshev
+    backward) reproduces the analytic result on a single mode:
+    cos(2 pi k0 x / nx) cos(pi q0 z / (nz - 1)) maps to
+    kx' / (kx'^2 + kz'^2) sin(2 pi k0 x / nx) cos(pi q0 z / (nz - 1))."""
+    for (nz, ny, nx), k0, q0 in (((17, 8, 16), 3, 5), ((9, 6, 10), 2, 0), ((12, 4, 15), 7, 11)):
+        kxs = 2 * np.pi * np.arange(nx // 2 + 1) / nx
+        kys = 2 * np.pi * np.fft.fftfreq(ny, 1.0 / ny) / ny
+        kzs = np.pi * np.arange(nz) / (nz - 1)
+        k2 = kxs[None, None, :] ** 2 + kys[None, :, None] ** 2 + kzs[:, None, None] ** 2
+        with np.errstate(divide="ignore", invalid="ignore"):
+            m = 1j * np.where(k2 > 0, -kxs[None, None, :] / k2, 0.0) / (nx * ny * 2.0 * (nz - 1))
+        x = np.arange(nx)[None, None, :]
+        z = np.arange(nz)[:, None, None]
+        u = np.cos(2 * np.pi * k0 * x / nx) * np.cos(np.pi * q0 * z / (nz - 1)) * np.ones((1, ny, 1))
+        kx, kz = 2 * np.pi * k0 / nx, np.pi * q0 / (nz - 1)
+        want = kx / (kx * kx + kz * kz) * np.sin(2 * np.pi * k0 * x / nx) * np.cos(np.pi * q0 * z / (nz - 1)) \
+            * np.ones((1, ny, 1))
+        got = oracle.c2r3d_cheb(oracle.r2c3d_cheb(u) * m, nx)
+        assert rel(got, want) < 1e-13, ((nz, ny, nx), k0, q0)
