@@ -11,6 +11,8 @@
   1e-12.
 * 2048^3 FP32 (eight times the benchmark's grid): round trip and Parseval,
   which hold at any size, reduced on the device.
+* 1024^3 plane wave: every output of the forward transform and of the C2R of
+  a single mode against the closed form.
 The oracle runs in FP64 on the host (OpenMP); FP32 inputs are promoted exactly.
 """
 import numpy as np
@@ -146,3 +148,38 @@ def test_2048_cubed_round_trip_and_parseval():
             se += float((Uc.real.double() ** 2 + Uc.imag.double() ** 2).sum(dim=(1, 2)).mul(w[kx:kx + 64]).sum())
     assert (sd / su) ** 0.5 < 1e-6
     assert abs(se / float(n) ** 3 - su) <= 1e-6 * su
+
+
+@pytest.mark.timeout(600)
+def test_1024_cubed_single_mode_every_output():
+    """Every output at the benchmark's size against a closed form: the plane wave
+    cos(2 pi (3x + 5y + 7z) / 1024) has the single half-spectrum entry N/2 at
+    (kx, ky, kz) = (3, 5, 7) and zeros elsewhere, and the C2R of that single
+    entry is N times the wave.  Reduced on the device in FP64 chunks."""
+    n = 1024
+    N = float(n) ** 3
+    print("case 1024^3 single mode", flush=True)
+    u = torch.empty((n, n, n), device="cuda", dtype=torch.float32)
+    x = torch.arange(n, device="cuda", dtype=torch.float64)
+    for z in range(0, n, 64):
+        zz = torch.arange(z, z + 64, device="cuda", dtype=torch.float64)[:, None, None]
+        u[z:z + 64] = torch.cos(2 * np.pi * (3 * x[None, None, :] + 5 * x[None, :, None] + 7 * zz) / n).float()
+    with pf.Plan(n, n, n) as plan:
+        U = plan.ftran(u)                              # STRIDE1 [kx][ky][kz]
+        torch.cuda.synchronize()
+        peak = complex(U[3, 5, 7].item())
+        U[3, 5, 7] = 0
+        rest = sum(float(U[k:k + 64].abs().double().pow(2).sum()) for k in range(0, n // 2 + 1, 64)) ** 0.5
+        assert abs(peak - N / 2) <= 1e-6 * N / 2
+        assert rest <= 1e-6 * N / 2
+        U.zero_()
+        U[3, 5, 7] = N / 2
+        back = plan.btran(U)
+        torch.cuda.synchronize()
+        num = den = 0.0
+        for z in range(0, n, 64):
+            b = back[z:z + 64].double()
+            ref = N * u[z:z + 64].double()
+            num += float((b - ref).pow(2).sum())
+            den += float(ref.pow(2).sum())
+        assert (num / den) ** 0.5 < 1e-6
