@@ -107,7 +107,8 @@ extern "C" {
  * flag is accepted and changes no result and no layout.  third =
  * PF_THIRD_EMPTY skips the transform along Z (Sec. 3.1): the forward output
  * is the Z-pencil of the X-then-Y transformed data, z untransformed, and the
- * backward transform starts from such an array.  third = PF_THIRD_CHEB
+ * backward transform starts from such an array; nz may then have any prime
+ * factors (nothing is transformed along z).  third = PF_THIRD_CHEB
  * replaces the Z FFT by the type-I DCT Y[k] = x[0] + (-1)^k x[nz-1] + 2
  * sum_{j=1}^{nz-2} x[j] cos(pi j k / (nz - 1)) in both directions (it is its
  * own inverse up to 2 (nz - 1), so the round trip returns nx ny 2 (nz - 1) u);

@@ -197,9 +197,12 @@ int check_impl(int nx, int ny, int nz, const pf_layout *l) {
     // Eq. 2 read as: every rank's block of every pencil is non-empty.
     if (l->m1 > nxh || l->m1 > ny || l->m2 > ny || l->m2 > nz) return PF_EINVAL;
     FftSpec f;
-    // under the Chebyshev third transform the z length transformed is 2 (nz - 1), checked below
+    // under the Chebyshev third transform the z length transformed is 2 (nz - 1), checked below;
+    // the empty third transform transforms nothing along z, so nz need not factor
     const bool cheb = l->third == PF_THIRD_CHEB;
-    if (!factor_length(nx, &f) || !factor_length(ny, &f) || (!cheb && !factor_length(nz, &f))) return PF_EUNSUPPORTED;
+    const bool empty = l->third == PF_THIRD_EMPTY;
+    if (!factor_length(nx, &f) || !factor_length(ny, &f) || (!cheb && !empty && !factor_length(nz, &f)))
+        return PF_EUNSUPPORTED;
     const int maxn = l->precision == PF_F64 ? 4096 : 8192;
     if (nx > maxn || ny > maxn || nz > maxn) return PF_EUNSUPPORTED;
     if (cheb) {  // the DCT runs as a length 2 (nz - 1) transform
@@ -795,7 +798,14 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     p->kbrows = (long long)ny;
     factor_length(nx, &p->fx, o.radix_order[0]);
     factor_length(ny, &p->fy, o.radix_order[1]);
-    factor_length(l->third == PF_THIRD_CHEB ? 2 * (nz - 1) : nz, &p->fz, o.radix_order[2]);
+    if (!factor_length(l->third == PF_THIRD_CHEB ? 2 * (nz - 1) : nz, &p->fz, o.radix_order[2])) {
+        // only the empty third transform gets here (check_impl): an nz that does not
+        // factor needs no z plan -- zero stages, no twiddles.  Such lengths are never
+        // powers of two, so the pass is the generic kernel, which reads no twiddles
+        // at zero stages (the power-of-two reorder form copies a full table).
+        std::memset(&p->fz, 0, sizeof(p->fz));
+        p->fz.n = nz;
+    }
 
     // twiddle tables, one allocation, each table 256-byte aligned
     std::vector<unsigned char> host;

@@ -194,3 +194,14 @@ def test_cheb_third_transform_lengths():
     assert pf.pf_check(16, 16, 17) == pf.PF_EUNSUPPORTED
     assert pf.pf_check(16, 16, 1, cheb) == pf.PF_EINVAL
     assert pf.pf_check(16, 16, 12, cheb) == pf.PF_EUNSUPPORTED  # 2 * 11
+
+
+def test_empty_third_transform_takes_any_nz():
+    """With the empty third transform nothing is transformed along z, so nz may
+    have any prime factors (x and y still need 7-smooth lengths)."""
+    empty = pf.Layout(third=pf.PF_THIRD_EMPTY)
+    for nz in (17, 33, 1021):
+        assert pf.pf_check(16, 16, nz, empty) == pf.PF_OK
+        assert pf.pf_check(16, 16, nz) == pf.PF_EUNSUPPORTED
+    assert pf.pf_check(16, 22, 17, empty) == pf.PF_EUNSUPPORTED  # y = 2 * 11
+    assert pf.pf_check(16, 16, 8193, empty) == pf.PF_EUNSUPPORTED  # longer than a generic tile line

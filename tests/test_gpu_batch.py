@@ -195,3 +195,33 @@ def test_full_batch_workload():
         for i in range(len(dims)):
             cf, cs = b.view(Cf, 1, i), b.view(Cs, 1, i)
             assert float((cf - cs).norm() / cs.norm()) < 1e-6, (i, dims[i])
+
+
+@pytest.mark.parametrize("third", [pf.PF_THIRD_EMPTY, pf.PF_THIRD_CHEB], ids=["empty", "cheb"])
+def test_batch_with_other_third_transforms(third):
+    """The batch takes the layout's third transform too: every transform matches
+    the oracle's composition (X and Y stages, then nothing or the type-I DCT
+    along z), forward and backward, fused and serial bitwise equal."""
+    dims = [(36, 20, 17), (48, 30, 9), (40, 16, 33)]  # nz - 1 = 16, 8, 32 for the DCT
+    print(f"case batch third={third}", flush=True)
+    fwd = oracle.r2c3d_third_empty if third == pf.PF_THIRD_EMPTY else oracle.r2c3d_cheb
+    bwd = oracle.c2r3d_third_empty if third == pf.PF_THIRD_EMPTY else oracle.c2r3d_cheb
+    outs = []
+    for mode in (pf.PF_BATCH_FUSED, pf.PF_BATCH_SERIAL):
+        with pf.Batch(dims, pf.Layout(third=third), mode=mode) as b:
+            R = b.empty(0).zero_()
+            C = b.empty(1).zero_()
+            fill(b, R, 0, 60, np.float32)
+            b.ftran(R, C)
+            Cin = b.empty(1).zero_()
+            fill(b, Cin, 1, 70, np.complex64)
+            Rout = b.empty(0).zero_()
+            b.btran(Cin, Rout)
+            torch.cuda.synchronize()
+            for i, (nx, ny, nz) in enumerate(dims):
+                u = b.view(R, 0, i).cpu().numpy()
+                assert rel(b.view(C, 1, i).cpu().numpy(), oracle.to_stride1(fwd(u))) < 1e-6, (i, dims[i])
+                V = oracle.from_stride1(b.view(Cin, 1, i).cpu().numpy())
+                assert rel(b.view(Rout, 0, i).cpu().numpy(), bwd(V, nx)) < 1e-6, (i, dims[i])
+            outs.append((C.clone(), Rout.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])

@@ -26,7 +26,8 @@ def rel(a, b):
 
 
 SHAPES = [(12, 10, 16), (9, 7, 15), (16, 32, 1024), (32, 64, 512), (5, 256, 48),
-          (256, 12, 36), (1024, 6, 40), (2048, 3, 10)]  # the last three: power-of-two Z, reorder-only kernel
+          (256, 12, 36), (1024, 6, 40), (2048, 3, 10),  # these three: power-of-two Z, reorder-only kernel
+          (17, 10, 16), (1021, 3, 8)]                   # nz with prime factors above 7: nothing to factor
 
 
 @pytest.mark.parametrize("stride1", [1, 0])
