@@ -61,3 +61,19 @@ def test_mfma_option_requires_f32():
     with pytest.raises(pf.PfError) as e:
         pf.Plan(32, 32, 32, pf.Layout(math=pf.PF_MFMA_FP16X2, precision=pf.PF_F64))
     assert e.value.code == pf.PF_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("math", [pf.PF_MFMA_FP16X2, pf.PF_MFMA_BF16X2])
+def test_mfma_with_chebyshev_third_transform(math):
+    """Matrix-core X and Y stages (nx = 1024, ny = 512) with the type-I DCT along
+    z (plain arithmetic, extension 512 on the power-of-two kernel): forward and
+    backward against the oracle's composition at the variant's bound."""
+    nz, ny, nx = 257, 512, 1024
+    print(f"case mfma + cheb math={math}", flush=True)
+    u = synth.uniform(33, (nz, ny, nx)).astype(np.float32)
+    with pf.Plan(nx, ny, nz, pf.Layout(math=math, third=pf.PF_THIRD_CHEB)) as plan:
+        got = plan.ftran(torch.from_numpy(u).cuda()).cpu().numpy()
+        assert rel(got, oracle.to_stride1(oracle.r2c3d_cheb(u))) < BOUND[math]
+        V = synth.complex_half(34, (nz, ny, nx // 2 + 1)).astype(np.complex64)
+        back = plan.btran(torch.from_numpy(oracle.to_stride1(V)).cuda()).cpu().numpy()
+        assert rel(back, oracle.c2r3d_cheb(V, nx)) < BOUND[math]
