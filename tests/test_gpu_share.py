@@ -129,3 +129,22 @@ def test_share_only_at_512_cubed_on_1x8():
     err = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(full.ravel()))
     print(f"block error / whole-transform norm {err:.3e}, block-relative {rel(got, ref):.3e}", flush=True)
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("math,bound", [(pf.PF_MFMA_FP16X2, 1e-6), (pf.PF_MFMA_BF16X2, 1e-5)])
+def test_share_only_with_matrix_core_stages(math, bound):
+    """A share whose X (nx = 1024) and Y (ny = 512) stages run on the matrix
+    cores: the forward result against the masked oracle at the variant's bound,
+    normalised by the whole masked transform (as for the FP32 shares)."""
+    nz, ny, nx = 16, 512, 1024
+    lay = pf.Layout(m1=2, m2=4, share_only=1, r1=1, r2=3, math=math)
+    print(f"case share mfma math={math}", flush=True)
+    xz, xy, zkx, zky = ranges(nx, ny, nz, lay)
+    u = synth.uniform(901, (nz, ny, nx)).astype(np.float32)
+    um = np.zeros_like(u)
+    um[xz, xy, :] = u[xz, xy, :]
+    with pf.Plan(nx, ny, nz, lay) as plan:
+        got = plan.ftran(torch.from_numpy(np.ascontiguousarray(u[xz, xy, :])).cuda()).cpu().numpy()
+    want = oracle.r2c3d(um)
+    err = np.linalg.norm((got - z_block(want, zkx, zky, 1)).ravel()) / np.linalg.norm(want.ravel())
+    assert err < bound
