@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--kt-summary", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
                     help="write the per-kernel summaries under profiles/ from a rocprofv3 kernel trace of this "
                          "benchmark (COMMAND: the rocprofv3 command that produced it), then exit")
+    ap.add_argument("--sq-summary", nargs=2, metavar=("COUNTER_CSV", "COMMAND"),
+                    help="write profiles/counters_sq_fft.txt from a rocprofv3 --pmc run of this benchmark with "
+                         "the SQ instruction counters (COMMAND: the rocprofv3 command that produced it), then exit")
     return ap.parse_args()
 
 
@@ -79,6 +82,22 @@ def traffic_from_profile(pass_name: str, n: int):
     return None if p is None else p["hbm_bytes"]
 
 
+def section_starts(names):
+    """Dispatch indices where the benchmark's sections start, from the kernel names in launch order:
+    the batch (first generic-kernel launch), the spectral step (its first k_r2c_p2<256, ...>), the
+    share-only leg (its first fill) and the other grids (the next k_r2c_p2<256, ...>)."""
+
+    def first(pred, start=0):
+        return next((i for i in range(start, len(names)) if pred(names[i])), len(names))
+
+    generic = ("k_c2c_tile", "k_r2c_x", "k_c2r_x")
+    b0 = first(lambda k: any(g in k for g in generic))
+    s0 = first(lambda k: "k_r2c_p2<256" in k, b0)
+    h0 = first(lambda k: "k_fill" in k, s0)
+    o0 = first(lambda k: "k_r2c_p2<256" in k, h0)
+    return b0, s0, h0, o0
+
+
 def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> None:
     """Per-kernel statistics from a rocprofv3 kernel trace of this benchmark, one file per workload.
 
@@ -92,16 +111,7 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
 
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-    names = [r["Kernel_Name"] for r in rows]
-
-    def first(pred, start=0):
-        return next((i for i in range(start, len(rows)) if pred(names[i])), len(rows))
-
-    generic = ("k_c2c_tile", "k_r2c_x", "k_c2r_x")
-    b0 = first(lambda k: any(g in k for g in generic))
-    s0 = first(lambda k: "k_r2c_p2<256" in k, b0)
-    h0 = first(lambda k: "k_fill" in k, s0)
-    o0 = first(lambda k: "k_r2c_p2<256" in k, h0)
+    b0, s0, h0, o0 = section_starts([r["Kernel_Name"] for r in rows])
 
     def table(rs):
         d = {}
@@ -155,6 +165,89 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
         with open(os.path.join(ROOT, "profiles", name), "w") as f:
             f.write("\n".join(lines) + "\n")
         print(f"wrote profiles/{name} ({len(lines)} lines)")
+
+
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_LDS",
+               "SQ_INSTS_SALU", "SQ_BUSY_CYCLES", "SQ_ACTIVE_INST_VALU")
+# MI355X: 256 CUs of 4 SIMDs; without packed FP32 a wave64 VALU instruction holds its SIMD 4 cycles
+VALU_SIMDS, VALU_CYCLES_PER_INST, CLOCK_GHZ = 1024, 4, 2.4
+
+
+def summarize_sq(counter_csv: str, command: str) -> None:
+    """Per-kernel instruction counts from a rocprofv3 --pmc run of this benchmark with SQ_COUNTERS.
+
+    Writes profiles/counters_sq_fft.txt: for each section of the run (split as
+    in the kernel-trace summary) and each of the library's kernels, the
+    per-dispatch averages of the counters, and where the grid is fixed by the
+    section, VALU lane slots per complex mode of the pass (SQ_INSTS_VALU x 64 /
+    M, inactive lanes included) and the time the VALU instructions alone hold
+    the SIMDs (SQ_INSTS_VALU x 4 cycles / 1024 SIMDs at 2.4 GHz) next to the
+    dispatch's duration.  A kernel whose VALU time is near its duration is
+    bound by VALU issue, one far below it by memory.
+    """
+    import csv
+
+    disp = {}
+    for r in csv.DictReader(open(counter_csv)):
+        d = disp.setdefault(int(r["Dispatch_Id"]), {
+            "name": r["Kernel_Name"], "ms": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6,
+            "scratch": r.get("Scratch_Size", ""), "c": {}})
+        d["c"][r["Counter_Name"]] = float(r["Counter_Value"])
+    ds = [disp[k] for k in sorted(disp)]
+    b0, s0, h0, o0 = section_starts([d["name"] for d in ds])
+
+    def modes(nx, ny, nz):
+        return (nx // 2 + 1) * ny * nz
+
+    m1024, m512 = modes(1024, 1024, 1024), modes(512, 512, 512)
+    sections = [
+        ("1024^3 FP32 plans (plain, matrix-core and layout variants; M = 513 x 1024 x 1024 complex modes)",
+         ds[:b0], lambda k: m1024),
+        ("64 batched transforms, 7-smooth sizes in [48, 320]^3 (serial and fused launches; sizes vary per "
+         "dispatch)", ds[b0:s0], lambda k: None),
+        ("Chebyshev spectral step on 512 x 512 x 257 (M = 257 x 512 x 257)", ds[s0:h0],
+         lambda k: modes(512, 512, 257)),
+        ("other grids: 512^3 on the power-of-two kernels (M = 257 x 512 x 512), 480 x 360 x 250 on the "
+         "mixed-radix kernels <float> (M = 241 x 360 x 250)", ds[o0:],
+         lambda k: modes(480, 360, 250) if "<float" in k else m512),
+    ]
+    lines = ["rocprofv3 SQ instruction counters per dispatch, FP32 R2C+C2R workloads of the benchmark, MI355X",
+             f"command: {command}",
+             "counters: " + " ".join(SQ_COUNTERS),
+             "avg ms: dispatch duration under counter collection (kernels serialised); waves: SQ_WAVES;",
+             "valu/wave, vmem/wave (reads + writes), lds/wave: instructions per wave; lanes/elem: SQ_INSTS_VALU x 64 "
+             "per complex mode;",
+             f"valu ms: SQ_INSTS_VALU x {VALU_CYCLES_PER_INST} cycles / {VALU_SIMDS} SIMDs at {CLOCK_GHZ} GHz; "
+             "valu/dur: valu ms over avg ms; scratch: bytes per lane", ""]
+    hdr = (f"{'kernel':60s} {'calls':>5s} {'avg ms':>7s} {'waves':>9s} {'valu/wave':>9s} {'vmem/wave':>9s} "
+           f"{'lds/wave':>8s} {'lanes/elem':>10s} {'valu ms':>8s} {'valu/dur':>8s} {'scratch':>7s}")
+    for title, rs, elems in sections:
+        by = {}
+        for d in rs:
+            if "pf::k_" in d["name"] and "k_copy" not in d["name"]:
+                by.setdefault(d["name"], []).append(d)
+        if not by:
+            continue
+        lines += [title, hdr]
+        for k, v in sorted(by.items(), key=lambda kv: -sum(d["ms"] for d in kv[1])):
+            def avg(c):
+                return statistics.mean(d["c"].get(c, 0.0) for d in v)
+            waves = avg("SQ_WAVES") or 1.0
+            valu = avg("SQ_INSTS_VALU")
+            ms = statistics.mean(d["ms"] for d in v)
+            valu_ms = valu * VALU_CYCLES_PER_INST / (VALU_SIMDS * CLOCK_GHZ * 1e6)
+            m = elems(k)
+            per = f"{valu * 64 / m:10.1f}" if m else f"{'-':>10s}"
+            name = k if len(k) <= 60 else k[:57] + "..."
+            lines.append(f"{name:60s} {len(v):5d} {ms:7.3f} {waves:9.0f} {valu / waves:9.1f} "
+                         f"{(avg('SQ_INSTS_VMEM_RD') + avg('SQ_INSTS_VMEM_WR')) / waves:9.1f} "
+                         f"{avg('SQ_INSTS_LDS') / waves:8.1f} {per} {valu_ms:8.3f} "
+                         f"{(valu_ms / ms if ms > 0 else 0.0):8.2f} {v[0]['scratch']:>7s}")
+        lines.append("")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "counters_sq_fft.txt"), "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
@@ -534,6 +627,9 @@ def main():
         return
     if args.pmc_summary:
         summarize_pmc(args.pmc_summary[0], args.pmc_summary[1], args.n, args.pmc_commands)
+        return
+    if args.sq_summary:
+        summarize_sq(args.sq_summary[0], args.sq_summary[1])
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "

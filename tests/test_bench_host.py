@@ -97,3 +97,42 @@ def test_counter_summary_scales_by_the_copy_probe_and_assigns_passes(tmp_root):
         assert e["write_bytes"] == pytest.approx(1024 * (i + 1))
         assert e["hbm_bytes"] == pytest.approx(3 * 1024 * (i + 1))
     assert os.path.exists(tmp_root / "profiles" / f"traffic_fft_{n}cubed.txt")
+
+
+def test_sq_summary_normalises_by_each_sections_grid(tmp_root):
+    """VALU lane slots per complex mode use the grid of the dispatch's section: 1024^3 for the
+    leading plans, 480 x 360 x 250 for the mixed-radix kernels of the other grids."""
+    m1024 = 513 * 1024 * 1024
+    m480 = 241 * 360 * 250
+    plan = [("void pf::k_c2c_p2<1024, 16, 1, 1, 0, 0>(pf::PassArgs)", m1024 * 40 / 64),
+            ("void pf::k_c2c_tile_b<float, 1>(pf::BatchArgs)", 1e6),              # the batch begins
+            ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 1e6),                     # the spectral step
+            ("pf::k_fill(pf::FillArgs)", 1e6),                                    # the share-only leg
+            ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 1e6),                     # the other grids
+            ("void pf::k_c2c_tile<float, -1>(pf::PassArgs)", m480 * 150 / 64)]
+    path = tmp_root / "sq.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp",
+                               "End_Timestamp", "VGPR_Count", "Scratch_Size"])
+        w.writeheader()
+        for i, (name, valu) in enumerate(plan):
+            for c in bench.SQ_COUNTERS:
+                v = valu if c == "SQ_INSTS_VALU" else 1000.0
+                w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Name": c, "Counter_Value": v,
+                            "Start_Timestamp": 0, "End_Timestamp": 1000000, "VGPR_Count": 128,
+                            "Scratch_Size": 0})
+    bench.summarize_sq(str(path), "CMD")
+    text = (tmp_root / "profiles" / "counters_sq_fft.txt").read_text()
+    assert "command: CMD" in text
+
+    def row(prefix, after):
+        part = text.split(after, 1)[1]
+        return next(line for line in part.splitlines() if line.startswith(prefix)).split()
+
+    r = row("void pf::k_c2c_p2<1024", "1024^3")
+    assert float(r[-4]) == pytest.approx(40.0, abs=0.05)
+    r = row("void pf::k_c2c_tile<float, -1>", "other grids")
+    assert float(r[-4]) == pytest.approx(150.0, abs=0.05)
+    assert "k_fill" not in text  # the share-only leg is not summarised
+    # the batch has no fixed grid: no per-element figure
+    assert row("void pf::k_c2c_tile_b", "batched")[-4] == "-"
