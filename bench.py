@@ -286,10 +286,13 @@ def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
         for i, r in enumerate(ours):
             name = PASS_ORDER[i % len(PASS_ORDER)]
             per.setdefault(name, {"kernel": r["Kernel_Name"], "vals": []})["vals"].append(
-                float(r["Counter_Value"]) * 1024.0 * (factor or 1.0))
+                float(r["Counter_Value"]) * 1024.0)
         for name, d in per.items():
             e = out["passes"].setdefault(name, {"kernel": d["kernel"]})
-            e["fetch_bytes" if counter == "FETCH_SIZE" else "write_bytes"] = statistics.mean(d["vals"])
+            key = "fetch" if counter == "FETCH_SIZE" else "write"
+            raw = statistics.mean(d["vals"])
+            e[key + "_raw_bytes"] = raw  # the counter as read, KiB x 1024
+            e[key + "_bytes"] = raw * (factor or 1.0)  # scaled by the copy probe's factor
             e["dispatches"] = len(d["vals"])
     for e in out["passes"].values():
         e["hbm_bytes"] = e.get("fetch_bytes", 0.0) + e.get("write_bytes", 0.0)
@@ -300,11 +303,14 @@ def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
              f"commands: {commands}",
              f"copy probe: {COPY_BYTES(n)} B read and written per dispatch; "
              f"scale FETCH {out['FETCH_SIZE']['scale']}, WRITE {out['WRITE_SIZE']['scale']}",
-             f"{'pass':<12} {'fetch GB':>9} {'write GB':>9} {'total GB':>9}  kernel"]
+             "the scales are measured on the copy probe alone (16-byte loads and stores of whole lines); the",
+             "raw counter values are listed beside the scaled ones",
+             f"{'pass':<12} {'fetch raw':>9} {'write raw':>9} {'fetch GB':>9} {'write GB':>9} {'total GB':>9}  kernel"]
     for name in PASS_ORDER:
         e = out["passes"].get(name)
         if e:
-            lines.append(f"{name:<12} {e.get('fetch_bytes', 0) / 1e9:9.3f} {e.get('write_bytes', 0) / 1e9:9.3f} "
+            lines.append(f"{name:<12} {e.get('fetch_raw_bytes', 0) / 1e9:9.3f} {e.get('write_raw_bytes', 0) / 1e9:9.3f} "
+                         f"{e.get('fetch_bytes', 0) / 1e9:9.3f} {e.get('write_bytes', 0) / 1e9:9.3f} "
                          f"{e['hbm_bytes'] / 1e9:9.3f}  {e['kernel']}")
     with open(traffic_path(n).replace(".json", ".txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -368,7 +374,39 @@ def cpu_baseline(n: int, u=None, forward_outputs=None):
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": f"one R2C+C2R pair at {n}^3 (FP64, OpenMP over lines), {dt:.2f} s wall",
+        "nproc": os.cpu_count(),
+        "cpus_allowed": len(os.sched_getaffinity(0)),
+        "one_core": cpu_baseline_one_core(min(n, 384)),
     }, errs
+
+
+ONE_CORE_SCRIPT = """
+import json, math, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle, synth
+n = int(sys.argv[2])
+u = synth.grf(2, (n, n, n))
+t0 = time.perf_counter()
+U = oracle.r2c3d(u)
+oracle.c2r3d(U, n)
+dt = time.perf_counter() - t0
+N = float(n) ** 3
+print(json.dumps({"value": 5.0 * N * math.log2(N) / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(),
+                  "kind": "oracle", "sample": f"one R2C+C2R pair at {n}^3 (FP64), {dt:.2f} s wall"}))
+"""
+
+
+def cpu_baseline_one_core(n: int):
+    """The same oracle on one host thread (OMP_NUM_THREADS=1, a child process that touches no GPU), on one
+    pair of an n^3 GRF (n = 384: about 10 s)."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", ONE_CORE_SCRIPT, ROOT, str(n)], env=env, capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def other_grid_timings(pf, args, dev, stream):

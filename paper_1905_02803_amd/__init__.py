@@ -311,12 +311,38 @@ class Plan:
         pf_btran_c2r(self.handle, U.data_ptr(), out.data_ptr(), _stream_handle(stream))
         return out
 
+    @property
+    def inplace_bytes(self) -> int:
+        """Bytes an in-place buffer must hold: max(real, complex) of the plan's arrays."""
+        rs = 8 if self.layout.precision == PF_F64 else 4
+        nreal = nc = 1
+        for v in self.real_shape:
+            nreal *= v
+        for v in self.complex_shape:
+            nc *= v
+        return max(nreal * rs, nc * 2 * rs)
+
+    @staticmethod
+    def _check_buffer(t, nbytes, what):
+        """A contiguous CUDA tensor, 16-byte aligned, whose storage holds nbytes from its data pointer."""
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{what} must be a contiguous CUDA tensor, got {tuple(t.shape)} on {t.device}")
+        if t.data_ptr() % 16:
+            raise ValueError(f"{what} must be 16-byte aligned")
+        st = t.untyped_storage()
+        have = st.data_ptr() + st.nbytes() - t.data_ptr()
+        if have < nbytes:
+            raise ValueError(f"{what} holds {have} bytes from its data pointer, the plan needs {nbytes}")
+
     def ftran_inplace(self, buf, stream=None):
         """In-place forward on a buffer tensor holding max(real, complex) bytes."""
+        self._check_buffer(buf, self.inplace_bytes, "in-place buffer")
         pf_ftran_r2c(self.handle, buf.data_ptr(), buf.data_ptr(), _stream_handle(stream))
         return buf
 
     def btran_inplace(self, buf, stream=None):
+        """In-place backward on a buffer tensor holding max(real, complex) bytes."""
+        self._check_buffer(buf, self.inplace_bytes, "in-place buffer")
         pf_btran_c2r(self.handle, buf.data_ptr(), buf.data_ptr(), _stream_handle(stream))
         return buf
 

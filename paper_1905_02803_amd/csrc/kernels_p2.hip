@@ -192,7 +192,10 @@ __device__ __forceinline__ float4 pack2(float2 a, float2 b) { return make_float4
 // and returns C[4(l/16) .. +4)[l%16]: lane (b, g) brings points 4g .. 4g+3 of
 // butterfly b and receives outputs 4g .. 4g+3 of it.  Both operands are split
 // into a high and a low half-precision part; hi*hi + hi*lo + lo*hi is
-// accumulated in FP32 (the lo*lo term is below FP32 rounding).  FP16 inputs
+// accumulated in FP32.  With FP16's 11-bit significands the dropped lo*lo term
+// and the residual of the two-term split are about 2^-22 of the product, below
+// FP32 rounding; with BF16's 8 bits both are about 2^-16, which sets the BF16
+// form's error floor (about 5e-6 relative L2 over a 3D transform).  FP16 inputs
 // are first scaled by a power of two per butterfly (largest component in
 // [1, 2)); BF16 keeps FP32's exponent range and needs no scale.
 typedef _Float16 mf_h8 __attribute__((ext_vector_type(8)));

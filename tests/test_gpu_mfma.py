@@ -31,14 +31,20 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+@pytest.mark.parametrize("stride1", [1, 0])
 @pytest.mark.parametrize("math", [pf.PF_MFMA_FP16X2, pf.PF_MFMA_BF16X2])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[::-1])))
-def test_mfma_variant_matches_oracle(shape, math):
+def test_mfma_variant_matches_oracle(shape, math, stride1):
+    """Forward, backward and round trip at the variant's bound, for both Z-pencil
+    layouts: stride1 = 0 runs the Z passes on the unaligned [nz][ny][nxh] rows
+    (column-at-a-time accesses traded between lanes) around the matrix-core stages."""
     nz, ny, nx = shape
-    print(f"case shape={shape} math={math}", flush=True)
+    print(f"case shape={shape} math={math} stride1={stride1}", flush=True)
     u = synth.grf(31, shape) if nx * ny * nz > 1 << 16 else synth.uniform(31, shape).astype(np.float32)
     ud = torch.from_numpy(u).cuda()
-    with pf.Plan(nx, ny, nz, pf.Layout(math=math)) as pm, pf.Plan(nx, ny, nz) as pp:
+    to_layout = oracle.to_stride1 if stride1 else (lambda a: a)
+    with pf.Plan(nx, ny, nz, pf.Layout(math=math, stride1=stride1)) as pm, \
+            pf.Plan(nx, ny, nz, pf.Layout(stride1=stride1)) as pp:
         Um = pm.ftran(ud).clone()
         Um2 = pm.ftran(ud).clone()
         Up = pp.ftran(ud)
@@ -46,11 +52,11 @@ def test_mfma_variant_matches_oracle(shape, math):
         torch.cuda.synchronize()
         assert torch.equal(Um, Um2)
         assert not torch.equal(Um, Up)  # the matrix-core stage really ran
-        ref = oracle.to_stride1(oracle.r2c3d(u))
+        ref = to_layout(oracle.r2c3d(u))
         ef = rel(Um.cpu().numpy(), ref)
         rt = rel(bm.cpu().numpy() / u.size, u)
         V = synth.complex_half(32, (nz, ny, nx // 2 + 1)).astype(np.complex64)
-        vb = pm.btran(torch.from_numpy(oracle.to_stride1(V)).cuda())
+        vb = pm.btran(torch.from_numpy(np.ascontiguousarray(to_layout(V))).cuda())
         torch.cuda.synchronize()
         eb = rel(vb.cpu().numpy(), oracle.c2r3d(V, nx))
         print(f"forward {ef:.3e} backward {eb:.3e} round trip {rt:.3e}", flush=True)

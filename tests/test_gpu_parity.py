@@ -209,6 +209,30 @@ def test_inplace_matches_out_of_place(shape, prec):
         assert torch.equal(buf[: u.size].reshape(u.shape), back_ref)
 
 
+def test_inplace_buffer_is_checked_before_the_call():
+    """The binding's in-place calls refuse a buffer that is too small, not
+    16-byte aligned, not contiguous or not on the device, before anything runs."""
+    nz, ny, nx = 6, 10, 16
+    with pf.Plan(nx, ny, nz, pf.Layout(inplace=1)) as p_in:
+        need = p_in.inplace_bytes
+        assert need == max(nx * ny * nz * 4, (nx // 2 + 1) * ny * nz * 8)
+        ok = torch.zeros(need // 4, dtype=torch.float32, device="cuda")
+        p_in.ftran_inplace(ok)
+        p_in.btran_inplace(ok)
+        torch.cuda.synchronize()
+        for bad in (torch.zeros(need // 4 - 4, dtype=torch.float32, device="cuda"),  # 16 bytes short
+                    ok.view(torch.uint8)[4:],                                         # misaligned
+                    torch.zeros(2 * need // 4, dtype=torch.float32, device="cuda")[::2],  # strided
+                    torch.zeros(need // 4, dtype=torch.float32)):                     # host memory
+            with pytest.raises(ValueError):
+                p_in.ftran_inplace(bad)
+            with pytest.raises(ValueError):
+                p_in.btran_inplace(bad)
+        # a view that starts inside a large enough storage but leaves too little after it
+        with pytest.raises(ValueError):
+            p_in.ftran_inplace(ok[4:])
+
+
 def test_call_errors_are_reported():
     with pf.Plan(16, 8, 4) as plan:
         u = plan.empty_real()

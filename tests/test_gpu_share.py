@@ -14,6 +14,7 @@ equal the ordinary plan bit for bit.
 import numpy as np
 import pytest
 
+import errbounds
 import oracle
 import synth
 
@@ -36,6 +37,21 @@ def ranges(nx, ny, nz, lay):
     zkx = slice(stz[0], stz[0] + szz[0])
     zky = slice(stz[1], stz[1] + szz[1])
     return xz, xy, zkx, zky
+
+
+def check_block(got, ref, whole, tol):
+    """A rank's block against the masked oracle: the error over the norm of the
+    whole masked transform (the scale of the rounding error, by Parseval) within
+    tol, and the block's own relative error within the white-floor bound
+    (errbounds.py): tol sqrt(n_block / n_whole) ||whole|| / ||block||."""
+    got, ref, whole = np.asarray(got), np.asarray(ref), np.asarray(whole)
+    e = float(np.linalg.norm((got - ref).ravel()))
+    nw, nb = float(np.linalg.norm(whole.ravel())), float(np.linalg.norm(ref.ravel()))
+    assert e / nw < tol, (e / nw, tol)
+    if nb > 0:
+        bound = errbounds.white_floor_bound(tol, ref.size, whole.size, nw, nb)
+        assert e / nb <= bound, (e / nb, bound)
+    return e / nw, (e / nb if nb > 0 else 0.0)
 
 
 def z_block(U, zkx, zky, stride1):
@@ -78,14 +94,18 @@ def test_share_only_matches_masked_oracle(shape, grid, rank, prec, stride1):
         assert plan.real_shape == u[xz, xy, :].shape
         got = plan.ftran(torch.from_numpy(np.ascontiguousarray(u[xz, xy, :])).cuda())
         torch.cuda.synchronize()
-        ref = z_block(oracle.r2c3d(um), zkx, zky, stride1)
+        whole = oracle.r2c3d(um)
+        ref = z_block(whole, zkx, zky, stride1)
         assert got.shape == ref.shape
         assert rel(got.cpu().numpy(), ref) < tol
+        check_block(got.cpu().numpy(), ref, whole, tol)
         vin = torch.from_numpy(z_block(V, zkx, zky, stride1)).cuda()
         back = plan.btran(vin)
         torch.cuda.synchronize()
-        refb = oracle.c2r3d(Vm, nx)[xz, xy, :]
+        wholeb = oracle.c2r3d(Vm, nx)
+        refb = wholeb[xz, xy, :]
         assert rel(back.cpu().numpy(), refb) < tol
+        check_block(back.cpu().numpy(), refb, wholeb, tol)
         # a second call reuses the workspace: the zero fills must not depend on the first
         got2 = plan.ftran(torch.from_numpy(np.ascontiguousarray(u[xz, xy, :])).cuda())
         torch.cuda.synchronize()
@@ -126,9 +146,10 @@ def test_share_only_at_512_cubed_on_1x8():
     um[xz, xy, :] = u[xz, xy, :]
     full = oracle.r2c3d(um)
     ref = z_block(full, zkx, zky, 1)
-    err = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(full.ravel()))
-    print(f"block error / whole-transform norm {err:.3e}, block-relative {rel(got, ref):.3e}", flush=True)
-    assert err < 1e-6
+    err, err_block = check_block(got, ref, full, 1e-6)
+    print(f"block error / whole-transform norm {err:.3e}, block-relative {err_block:.3e} (white-floor bound "
+          f"{errbounds.white_floor_bound(1e-6, ref.size, full.size, np.linalg.norm(full), np.linalg.norm(ref)):.3e})",
+          flush=True)
 
 
 @pytest.mark.parametrize("math,bound", [(pf.PF_MFMA_FP16X2, 1e-6), (pf.PF_MFMA_BF16X2, 1e-5)])
@@ -146,5 +167,4 @@ def test_share_only_with_matrix_core_stages(math, bound):
     with pf.Plan(nx, ny, nz, lay) as plan:
         got = plan.ftran(torch.from_numpy(np.ascontiguousarray(u[xz, xy, :])).cuda()).cpu().numpy()
     want = oracle.r2c3d(um)
-    err = np.linalg.norm((got - z_block(want, zkx, zky, 1)).ravel()) / np.linalg.norm(want.ravel())
-    assert err < bound
+    check_block(got, z_block(want, zkx, zky, 1), want, bound)
