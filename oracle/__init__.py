@@ -49,11 +49,25 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+def build_sanitized(path: str) -> str:
+    """Compile oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer into `path` (a test build:
+    load it with the sanitizer runtime preloaded, through ORACLE_LIB)."""
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", path,
+           _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return path
+
+
 def _load():
     global _lib
     if _lib is None:
-        build()
-        _lib = bind(ctypes.CDLL(_LIB_PATH))
+        alt = os.environ.get("ORACLE_LIB")  # another build of oracle.c (the sanitizer test's)
+        if alt:
+            _lib = bind(ctypes.CDLL(alt))
+        else:
+            build()
+            _lib = bind(ctypes.CDLL(_LIB_PATH))
     return _lib
 
 
