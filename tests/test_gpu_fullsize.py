@@ -19,7 +19,7 @@ The oracle runs in FP64 on the host (OpenMP); FP32 inputs are promoted exactly.
 import numpy as np
 import pytest
 
-import errbounds
+from tests import errbounds
 import oracle
 import synth
 

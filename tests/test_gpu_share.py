@@ -14,7 +14,7 @@ equal the ordinary plan bit for bit.
 import numpy as np
 import pytest
 
-import errbounds
+from tests import errbounds
 import oracle
 import synth
 
