@@ -4,7 +4,7 @@
   out-of-place: the forward output against the oracle's whole transform, the
   backward of an arbitrary half spectrum against the oracle's staged C2R, the
   round trip (Sec. 4.1) and Parseval; the forward error of every |k| shell
-  against the white-floor bound (errbounds.py).
+  against the staged rounding bound (errbounds.py).
   Also the two matrix-core precision variants at their stated bounds
   (FP16 x 2: 1e-6, BF16 x 2: 1e-5).
 * 512^3 and 480 x 360 x 250 FP32 random fields: the same checks.
@@ -70,8 +70,9 @@ def check_grid(shape, seed, tol, maths=()):
         err = rel(got, ref)
         print(f"forward rel L2 {err:.3e}, round trip {rt:.3e}", flush=True)
         assert err < tol
-        # per |k| shell: the power-law field's energy falls off with |k| while the
-        # rounding error stays white, so each shell is held to the white-floor bound
+        # per |k| shell: the power-law field's energy falls off with |k|, so the
+        # whole-result norm hides the weak shells; each shell is held to the
+        # staged rounding bound of errbounds.py
         for lo, hi, m, e, bound in errbounds.check_shells(got, ref, nx, ny, nz, tol):
             print(f"  shell [{lo:g}, {hi:g}): {m} modes, rel L2 {e:.3e} (bound {bound:.3e})", flush=True)
         del got

@@ -39,19 +39,25 @@ def ranges(nx, ny, nz, lay):
     return xz, xy, zkx, zky
 
 
-def check_block(got, ref, whole, tol):
+def check_block(got, ref, whole, tol, floor_block=None):
     """A rank's block against the masked oracle: the error over the norm of the
     whole masked transform (the scale of the rounding error, by Parseval) within
-    tol, and the block's own relative error within the white-floor bound
-    (errbounds.py): tol sqrt(n_block / n_whole) ||whole|| / ||block||."""
+    tol, and the block's own error within the staged rounding bound of
+    errbounds.py, tol / 2 sqrt(sum of M over the block), when floor_block (M of
+    the whole result cut to the block, in the block's layout) is given."""
     got, ref, whole = np.asarray(got), np.asarray(ref), np.asarray(whole)
     e = float(np.linalg.norm((got - ref).ravel()))
     nw, nb = float(np.linalg.norm(whole.ravel())), float(np.linalg.norm(ref.ravel()))
     assert e / nw < tol, (e / nw, tol)
-    if nb > 0:
-        bound = errbounds.white_floor_bound(tol, ref.size, whole.size, nw, nb)
-        assert e / nb <= bound, (e / nb, bound)
+    if floor_block is not None:
+        errbounds.check_subset(e * e, float(np.sum(floor_block)), tol)
     return e / nw, (e / nb if nb > 0 else 0.0)
+
+
+# passes of the forward transform along x, y, z: axes 2, 1, 0 of a [kz][ky][kx]
+# result; of the backward transform along z, y, x: axes 0, 1, 2 of [z][y][x]
+FWD_AXES = (2, 1, 0)
+BWD_AXES = (0, 1, 2)
 
 
 def z_block(U, zkx, zky, stride1):
@@ -98,14 +104,15 @@ def test_share_only_matches_masked_oracle(shape, grid, rank, prec, stride1):
         ref = z_block(whole, zkx, zky, stride1)
         assert got.shape == ref.shape
         assert rel(got.cpu().numpy(), ref) < tol
-        check_block(got.cpu().numpy(), ref, whole, tol)
+        check_block(got.cpu().numpy(), ref, whole, tol,
+                    z_block(errbounds.staged_floor(whole, FWD_AXES), zkx, zky, stride1))
         vin = torch.from_numpy(z_block(V, zkx, zky, stride1)).cuda()
         back = plan.btran(vin)
         torch.cuda.synchronize()
         wholeb = oracle.c2r3d(Vm, nx)
         refb = wholeb[xz, xy, :]
         assert rel(back.cpu().numpy(), refb) < tol
-        check_block(back.cpu().numpy(), refb, wholeb, tol)
+        check_block(back.cpu().numpy(), refb, wholeb, tol, errbounds.staged_floor(wholeb, BWD_AXES)[xz, xy, :])
         # a second call reuses the workspace: the zero fills must not depend on the first
         got2 = plan.ftran(torch.from_numpy(np.ascontiguousarray(u[xz, xy, :])).cuda())
         torch.cuda.synchronize()
@@ -146,10 +153,10 @@ def test_share_only_at_512_cubed_on_1x8():
     um[xz, xy, :] = u[xz, xy, :]
     full = oracle.r2c3d(um)
     ref = z_block(full, zkx, zky, 1)
-    err, err_block = check_block(got, ref, full, 1e-6)
-    print(f"block error / whole-transform norm {err:.3e}, block-relative {err_block:.3e} (white-floor bound "
-          f"{errbounds.white_floor_bound(1e-6, ref.size, full.size, np.linalg.norm(full), np.linalg.norm(ref)):.3e})",
-          flush=True)
+    floor = z_block(errbounds.staged_floor(full, FWD_AXES), zkx, zky, 1)
+    err, err_block = check_block(got, ref, full, 1e-6, floor)
+    print(f"block error / whole-transform norm {err:.3e}, block-relative {err_block:.3e} (staged bound "
+          f"{0.5e-6 * np.sqrt(floor.sum()) / np.linalg.norm(ref):.3e})", flush=True)
 
 
 @pytest.mark.parametrize("math,bound", [(pf.PF_MFMA_FP16X2, 1e-6), (pf.PF_MFMA_BF16X2, 1e-5)])
@@ -167,4 +174,5 @@ def test_share_only_with_matrix_core_stages(math, bound):
     with pf.Plan(nx, ny, nz, lay) as plan:
         got = plan.ftran(torch.from_numpy(np.ascontiguousarray(u[xz, xy, :])).cuda()).cpu().numpy()
     want = oracle.r2c3d(um)
-    check_block(got, z_block(want, zkx, zky, 1), want, bound)
+    check_block(got, z_block(want, zkx, zky, 1), want, bound,
+                z_block(errbounds.staged_floor(want, FWD_AXES), zkx, zky, 1))
