@@ -202,6 +202,29 @@ int pf_ftran_r2c(pf_plan *p, const void *in, void *out, void *stream);
  */
 int pf_btran_c2r(pf_plan *p, const void *in, void *out, void *stream);
 
+/*
+ * For callers that cannot allocate device memory at call time: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * forward (dir = PF_DIR_FORWARD, as pf_ftran_r2c) or backward (PF_DIR_BACKWARD,
+ * as pf_btran_c2r) transform with the same arguments, layouts and results, but
+ * with a static device array of the library (PF_NOALLOC_MAX_BYTES bytes per
+ * device, held from the first plan made on a device until the process ends) as
+ * the workspace instead of the plan's.  The call allocates nothing: no device
+ * memory, no events (per-pass timing is not recorded for it), no library
+ * buffers; it only enqueues the transform's kernels on `stream`.
+ *
+ * Limits and errors: PF_EWORKSPACE if the plan's workspace
+ * (pf_workspace_bytes) exceeds PF_NOALLOC_MAX_BYTES (FP32 1 x 1 plans up to
+ * e.g. 480 x 360 x 250 or 256^3 fit); PF_EUNSUPPORTED for share-only plans;
+ * otherwise as pf_ftran_r2c / pf_btran_c2r.  Every call on one device shares
+ * that device's array, so calls that overlap in time on one device (two
+ * streams, two threads) race and give undefined results; the caller
+ * serialises them.  The array keeps the last call's contents; no transform
+ * depends on its initial contents.
+ */
+#define PF_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+int pf_exec_noalloc(pf_plan *p, int dir, const void *in, void *out, void *stream);
+
 /* Free the plan's device tables and owned workspace.  NULL is accepted. */
 int pf_destroy(pf_plan *p);
 

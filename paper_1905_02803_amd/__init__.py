@@ -42,7 +42,7 @@ EXPORTED = (
     "pf_set_workspace", "pf_ftran_r2c", "pf_btran_c2r", "pf_destroy", "pf_strerror", "pf_num_passes",
     "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
     "pf_batch_setup", "pf_batch_offset", "pf_batch_bytes", "pf_batch_set_mode", "pf_batch_ftran_r2c",
-    "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step",
+    "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step", "pf_exec_noalloc",
 )
 
 
@@ -104,6 +104,7 @@ def lib():
             "pf_set_workspace": (i, [vp, vp, sz]),
             "pf_ftran_r2c": (i, [vp, vp, vp, vp]),
             "pf_btran_c2r": (i, [vp, vp, vp, vp]),
+            "pf_exec_noalloc": (i, [vp, i, vp, vp, vp]),
             "pf_destroy": (i, [vp]),
             "pf_strerror": (ctypes.c_char_p, [i]),
             "pf_num_passes": (i, [vp, i]),
@@ -178,6 +179,14 @@ def pf_ftran_r2c(h, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
 
 def pf_btran_c2r(h, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
     _raise(lib().pf_btran_c2r(h, in_ptr, out_ptr, stream), "pf_btran_c2r")
+
+
+PF_NOALLOC_MAX_BYTES = 256 << 20
+
+
+def pf_exec_noalloc(h, direction: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    """Transform with the library's static device scratch as the workspace (no allocation)."""
+    _raise(lib().pf_exec_noalloc(h, direction, in_ptr, out_ptr, stream), "pf_exec_noalloc")
 
 
 def pf_run_pass(h, direction: int, pass_index: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:

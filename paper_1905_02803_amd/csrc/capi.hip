@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -641,8 +642,9 @@ void release_timing(pf_plan *p) {
         }
 }
 
-// Set the buffers of pass i of direction dir and enqueue it.
-int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s) {
+// Set the buffers of pass i of direction dir and enqueue it.  untimed: record
+// no events even with timing on (the no-allocation entry point creates none).
+int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s, bool untimed = false) {
     PassDesc d = p->pass[dir][i];
     d.a.in = in;
     d.a.out = out;
@@ -653,7 +655,7 @@ int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s
     d.b.dst = out;
     EventPair ev{nullptr, nullptr};
     bool timed = false;
-    if (p->timing) {
+    if (p->timing && !untimed) {
         ev = take_events(p);
         timed = ev.start && ev.stop && hipEventRecord(ev.start, s) == hipSuccess;
     }
@@ -661,60 +663,95 @@ int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s
     // a pass whose events could not be recorded is left out of the timing
     if (timed && hipEventRecord(ev.stop, s) == hipSuccess)
         p->tim[dir][i].used.push_back(ev);
-    else if (p->timing)
+    else if (p->timing && !untimed)
         p->pool.push_back(ev);
     return hip_status(e);
 }
 
 bool aligned16(const void *ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 
-int check_call(const pf_plan *p, const void *in, const void *out) {
+int check_args(const pf_plan *p, const void *in, const void *out) {
     if (!p || !in || !out) return PF_EINVAL;
     if (!aligned16(in) || !aligned16(out)) return PF_EALIGN;
     if (p->lay.inplace && in != out) return PF_EALIAS;
     if (!p->lay.inplace && in == out) return PF_EALIAS;
+    return PF_OK;
+}
+
+int check_call(const pf_plan *p, const void *in, const void *out) {
+    const int rc = check_args(p, in, out);
+    if (rc) return rc;
     if (!p->ws) return PF_EWORKSPACE;
     return PF_OK;
 }
 
-int run_chain(pf_plan *p, int dir, const void *in, void *out, void *stream) {
-    const int rc = check_call(p, in, out);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
+// The pass chain of one direction with workspace ws (the plan's, or the
+// no-allocation entry point's static scratch; untimed for the latter).
+int run_chain_ws(pf_plan *p, int dir, const void *in, void *out, void *ws, hipStream_t s, bool untimed) {
     if (p->share) {
-        char *w = (char *)p->ws, *g = (char *)p->ws + p->w_bytes;
+        char *w = (char *)ws, *g = (char *)ws + p->w_bytes;
         int r;
         if (dir == 0) {
-            r = run_one(p, 0, 0, nullptr, w, s);
-            if (!r) r = run_one(p, 0, 1, in, w + p->so_x, s);
-            if (!r) r = run_one(p, 0, 2, w + p->so_y, w + p->so_y, s);
-            if (!r) r = run_one(p, 0, 3, w + p->so_zw, g + p->so_zg, s);
-            if (!r) r = run_one(p, 0, 4, g, out, s);
+            r = run_one(p, 0, 0, nullptr, w, s, untimed);
+            if (!r) r = run_one(p, 0, 1, in, w + p->so_x, s, untimed);
+            if (!r) r = run_one(p, 0, 2, w + p->so_y, w + p->so_y, s, untimed);
+            if (!r) r = run_one(p, 0, 3, w + p->so_zw, g + p->so_zg, s, untimed);
+            if (!r) r = run_one(p, 0, 4, g, out, s, untimed);
         } else {
-            r = run_one(p, 1, 0, nullptr, w, s);
-            if (!r) r = run_one(p, 1, 1, in, g, s);
-            if (!r) r = run_one(p, 1, 2, g + p->so_zg, w + p->so_zw, s);
-            if (!r) r = run_one(p, 1, 3, w + p->so_y, w + p->so_y, s);
-            if (!r) r = run_one(p, 1, 4, nullptr, w, s);
-            if (!r) r = run_one(p, 1, 5, w + p->so_x, out, s);
+            r = run_one(p, 1, 0, nullptr, w, s, untimed);
+            if (!r) r = run_one(p, 1, 1, in, g, s, untimed);
+            if (!r) r = run_one(p, 1, 2, g + p->so_zg, w + p->so_zw, s, untimed);
+            if (!r) r = run_one(p, 1, 3, w + p->so_y, w + p->so_y, s, untimed);
+            if (!r) r = run_one(p, 1, 4, nullptr, w, s, untimed);
+            if (!r) r = run_one(p, 1, 5, w + p->so_x, out, s, untimed);
         }
         return r;
     }
     if (!p->blocked) {
         // pass 0: user -> workspace; pass 1: workspace in place; pass 2: workspace -> user
-        int r = run_one(p, dir, 0, in, p->ws, s);
-        if (!r) r = run_one(p, dir, 1, p->ws, p->ws, s);
-        if (!r) r = run_one(p, dir, 2, p->ws, out, s);
+        int r = run_one(p, dir, 0, in, ws, s, untimed);
+        if (!r) r = run_one(p, dir, 1, ws, ws, s, untimed);
+        if (!r) r = run_one(p, dir, 2, ws, out, s, untimed);
         return r;
     }
     // pack: user blocks -> global array G; then G -> W, W in place, W -> G; unpack: G -> user blocks
-    void *g = (char *)p->ws + p->w_bytes;
-    int r = run_one(p, dir, 0, in, g, s);
-    if (!r) r = run_one(p, dir, 1, g, p->ws, s);
-    if (!r) r = run_one(p, dir, 2, p->ws, p->ws, s);
-    if (!r) r = run_one(p, dir, 3, p->ws, g, s);
-    if (!r) r = run_one(p, dir, 4, g, out, s);
+    void *g = (char *)ws + p->w_bytes;
+    int r = run_one(p, dir, 0, in, g, s, untimed);
+    if (!r) r = run_one(p, dir, 1, g, ws, s, untimed);
+    if (!r) r = run_one(p, dir, 2, ws, ws, s, untimed);
+    if (!r) r = run_one(p, dir, 3, ws, g, s, untimed);
+    if (!r) r = run_one(p, dir, 4, g, out, s, untimed);
     return r;
+}
+
+int run_chain(pf_plan *p, int dir, const void *in, void *out, void *stream) {
+    const int rc = check_call(p, in, out);
+    if (rc) return rc;
+    return run_chain_ws(p, dir, in, out, p->ws, (hipStream_t)stream, false);
+}
+
+// ---- static scratch for the no-allocation entry point ----------------------
+// One array per device, allocated with the library's code object and held
+// until the process ends.  Host code never uses its name as an address: the
+// device address comes from hipGetSymbolAddress, once per device (at plan
+// creation, or at the entry point's first call on a device).
+constexpr size_t kScratchBytes = PF_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices];  // device address of `scratch` per device, nullptr until looked up
+
+// Device address of the current device's scratch array (nullptr on failure).
+void *scratch_address() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        scratch_ptr[dev] = ptr;
+    }
+    return scratch_ptr[dev];
 }
 
 }  // namespace
@@ -864,6 +901,14 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
         delete p;
         return hip_status(e);
     }
+    // the no-allocation entry point's scratch on this device: looked up here so
+    // that its first call does not have to
+    if (e == hipSuccess && !scratch_address()) e = hipErrorInvalidSymbol;
+    if (e != hipSuccess) {
+        (void)hipFree(p->tw_dev);
+        delete p;
+        return hip_status(e);
+    }
     p->share = l->share_only != 0;
     p->blocked = !p->share && l->m1 * l->m2 > 1;
     p->w_bytes = ((size_t)p->nz * p->nkb * p->ny * p->B * p->csize + 255) & ~(size_t)255;
@@ -927,6 +972,17 @@ int pf_set_workspace(pf_plan *p, void *ws, size_t bytes) {
 int pf_ftran_r2c(pf_plan *p, const void *in, void *out, void *stream) { return run_chain(p, 0, in, out, stream); }
 
 int pf_btran_c2r(pf_plan *p, const void *in, void *out, void *stream) { return run_chain(p, 1, in, out, stream); }
+
+int pf_exec_noalloc(pf_plan *p, int dir, const void *in, void *out, void *stream) {
+    if (dir != PF_DIR_FORWARD && dir != PF_DIR_BACKWARD) return PF_EINVAL;
+    const int rc = check_args(p, in, out);
+    if (rc) return rc;
+    if (p->share) return PF_EUNSUPPORTED;
+    if (p->ws_bytes > kScratchBytes) return PF_EWORKSPACE;
+    void *ws = scratch_address();
+    if (!ws) return PF_EHIP;
+    return run_chain_ws(p, dir, in, out, ws, (hipStream_t)stream, true);
+}
 
 int pf_destroy(pf_plan *p) {
     if (!p) return PF_OK;
