@@ -67,13 +67,19 @@ extern "C" {
 
 /*
  * math: PF_PLAIN computes every butterfly on the vector ALUs in the plan
- * precision.  The MFMA options (F32 plans only) run the middle radix-16 stage
- * of the power-of-two passes (lengths 512 and 1024 for Y and Z, nx 1024 and
- * 2048 for X) as 16 x 16 complex DFT-matrix products on the matrix cores, with
- * both operands split into high and low half-precision parts (three products,
- * FP32 accumulation); FP16 inputs are scaled by a power of two per butterfly.
- * Other passes run as PF_PLAIN.  The result differs from PF_PLAIN by rounding
- * only (relative L2 against the FP64 oracle is reported by the tests).
+ * precision.  The MFMA options (F32 plans only) run both radix-16 stages of
+ * the power-of-two passes (lengths 512 and 1024 for Y and Z, nx 1024 and 2048
+ * for X, i.e. 16 x 16 x R with R = 2 or 4) as 16 x 16 complex DFT-matrix
+ * products on the matrix cores, with both operands split into high and low
+ * half-precision parts (three products, FP32 accumulation); FP16 inputs are
+ * scaled by a power of two per butterfly; twiddles and the last radix-R stage
+ * stay FP32 on the vector ALUs.  The first stage reads its operands straight
+ * from the loaded registers (where the input side is 16-byte aligned rows or
+ * lines; a Z pass reading unaligned [nz][ny][nxh] rows keeps it on the
+ * vector ALUs).  Other passes run as PF_PLAIN.  The result differs from
+ * PF_PLAIN by rounding only: FP16 x 2 is FP32-class, BF16 x 2 has an error
+ * floor of about 2^-16 per product (relative L2 against the FP64 oracle is
+ * reported by the tests).
  */
 #define PF_PLAIN 0
 #define PF_MFMA_FP16X2 1

@@ -360,6 +360,71 @@ __device__ __forceinline__ void p2_stage1_mfma(float4 *buf, const cx<float> *tws
     __syncthreads();
 }
 
+// Stage 0 (radix 16, no twiddles) of an N-point column FFT on the matrix
+// cores, fed from registers.  Each wave runs 8 groups of 16 butterflies; in
+// group i, lane (b, g) holds points q + (N/16)(4g + s), s < 4, of butterfly
+// (column, q) in x[4 i + s] -- for a side whose columns are contiguous (LINES =
+// false) the group's butterflies are the 16 columns at q = 8w + i, for a side
+// whose points are contiguous (LINES = true) they are 16 consecutive q of one
+// column (group j = 8w + i: column j / (N/256), q = 16 (j mod N/256) + b), so
+// that either way 16 lanes read one 128-byte run.  The outputs r = 4g + s land
+// on points 16 q + r of the LDS tile.
+template <int N, bool LINES>
+__device__ __forceinline__ void p2_mfma_group(int w, int i, int b, int &col, int &q) {
+    if constexpr (LINES) {
+        const int j = 8 * w + i;
+        col = j / (N / 256);
+        q = 16 * (j % (N / 256)) + b;
+    } else {
+        col = b;
+        q = 8 * w + i;
+    }
+}
+
+template <int N, int TC, int DIR, int MT, bool LINES>
+__device__ __forceinline__ void p2_stage0_mfma(cx<float> (&x)[32], float4 *buf,
+                                               const typename MfmaSplit<MT>::vec *atab, int tid) {
+    static_assert(TC == 16, "the matrix-core stage takes 16 columns");
+    const int lane = tid & 63, w = tid >> 6;
+    const int b = lane & 15, g = lane >> 4;
+    MfmaDft16<DIR, MT> dft;
+    dft.load(atab, lane);
+    float2 *lds2 = reinterpret_cast<float2 *>(buf);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        cx<float> y[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) y[s] = x[4 * i + s];
+        dft.run(y);
+        int col, q;
+        p2_mfma_group<N, LINES>(w, i, b, col, q);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) lds2[2 * p2_slot<TC>(16 * q + 4 * g + s, col >> 1) + (col & 1)] = y[s];
+    }
+}
+
+// Stage 0 on the matrix cores with its inputs in the LDS tile (the backward X
+// stage, whose inputs come from the inverse split): every group's inputs are
+// read before any output is written (outputs of butterfly q cover all rows
+// 16 q .. 16 q + 15, so rows of different waves' butterflies interleave).
+template <int N, int TC, int DIR, int MT>
+__device__ __forceinline__ void p2_stage0_mfma_lds(float4 *buf, const typename MfmaSplit<MT>::vec *atab, int tid) {
+    constexpr int T = N / 16;
+    const int lane = tid & 63, w = tid >> 6;
+    const int b = lane & 15, g = lane >> 4;
+    const float2 *lds2 = reinterpret_cast<const float2 *>(buf);
+    cx<float> x[32];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int q = 8 * w + i;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) x[4 * i + s] = lds2[2 * p2_slot<TC>(q + T * (4 * g + s), b >> 1) + (b & 1)];
+    }
+    __syncthreads();
+    p2_stage0_mfma<N, TC, DIR, MT, false>(x, buf, atab, tid);
+    __syncthreads();
+}
+
 // Trade values between the lanes of points q (even) and q + 1 (odd), which are
 // cp_lanes apart in the wave, so that the row-major layout (v0, v1) = (column
 // 2 cp, column 2 cp + 1) of the lane's own point and the column-major layout
@@ -395,6 +460,9 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
     for (int i = tid; i < N - 1; i += NT) twl[i] = tw[i];
     constexpr bool MC = MT == 1 || MT == 2;  // middle stage on the matrix cores
+    // stage 0 on the matrix cores too, fed from the load registers, where the
+    // input side is aligned rows (INP 0) or lines (INP 1)
+    constexpr bool MC0 = MC && (INP == 0 || INP == 1);
     typedef typename MfmaSplit<MC ? MT : 1>::vec avec;
     avec *atab = reinterpret_cast<avec *>(twl + N);  // matrix-core A operands (MC)
     if constexpr (MC) {
@@ -434,6 +502,30 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
     };
     auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
         const int tv = opaque_tid();
+        if constexpr (MC0) {
+            // matrix-core stage 0: group i of the wave in d0[4 i + s] (i < 4) or
+            // d1[4 (i - 4) + s], lane (b, g) point q + T (4 g + s) of its column
+            const int lane = tv & 63, w = tv >> 6, bl = lane & 15, g = lane >> 4;
+            int ncol;
+            const long long base = side_addr(a.in_s, t, 0, 0, ncol);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int col, q;
+                p2_mfma_group<N, INP == 1>(w, i, bl, col, q);
+                if (col < ncol) {
+                    const long long e = base + (long long)col * a.in_s.sc + (long long)q * a.in_s.sp;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const cx<float> *src = in + e + (long long)(4 * g + s) * in_step;
+                        const float2 v = INP == 1 ? gld<streamed<LD_C2C_POINTS>()>(src)
+                                                  : gld<streamed<LD_C2C_ROWS>()>(src);
+                        if (i < 4) d0[4 * i + s] = v;
+                        else d1[4 * (i - 4) + s] = v;
+                    }
+                }
+            }
+            return;
+        }
         const int cp_in = INP == 1 ? tv / T : tv % CP;
         const int q_in = INP == 1 ? tv % T : tv / CP;
         int ncol;
@@ -486,6 +578,10 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
 
     int t = blockIdx.x;
     cx<float> p0[16], p1[16];
+    if constexpr (MC0) {  // lanes of columns past the grid's edge compute on zeros
+#pragma unroll
+        for (int m = 0; m < 16; ++m) p0[m] = p1[m] = make_float2(0.f, 0.f);
+    }
     if (t < ntiles) load(p0, p1, xcd_tile(t, ntiles, a.xcd));
     __syncthreads();  // twiddle table in LDS
     for (; t < ntiles; t += gridDim.x) {
@@ -509,6 +605,15 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
         if constexpr (MT == 3) {  // no transform (the empty third transform): points keep their index
 #pragma unroll
             for (int m = 0; m < 16; ++m) buf[p2_slot<TC>(q_in + T * m, cp_in)] = pack2(v0[m], v1[m]);
+            __syncthreads();
+        } else if constexpr (MC0) {  // stage 0 on the matrix cores, from the load registers
+            cx<float> x[32];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                x[m] = v0[m];
+                x[16 + m] = v1[m];
+            }
+            p2_stage0_mfma<N, TC, DIR, MT, INP == 1>(x, buf, atab, tv);
             __syncthreads();
         } else {
             // stage 0: radix 16 on x[q + T r], outputs to points 16 q + r
@@ -812,6 +917,27 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
 
     auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
         const int tv = opaque_tid();
+        if constexpr (MT != 0) {
+            // matrix-core stage 0: group i in d0[4 i + s] (i < 4) or d1[4 (i - 4) + s];
+            // lane (b, g) holds complex point q + T (4 g + s) of its line
+            const int lane = tv & 63, w = tv >> 6, bl = lane & 15, g = lane >> 4;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int l, q;
+                p2_mfma_group<M, true>(w, i, bl, l, q);
+                if (16 * t + l < lines) {
+                    const float *pl = in + (long long)(16 * t + l) * a.ld_real + 2 * q;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float2 v =
+                            gld<streamed<LD_R2C>()>(reinterpret_cast<const float2 *>(pl + 2 * T * (4 * g + s)));
+                        if (i < 4) d0[4 * i + s] = v;
+                        else d1[4 * (i - 4) + s] = v;
+                    }
+                }
+            }
+            return;
+        }
         const int cp_in = tv / T, q_in = tv % T;  // lines: lanes along points
         const int ga = 16 * t + 2 * cp_in;
         const float *pa = in + (long long)ga * a.ld_real + 2 * q_in;
@@ -828,6 +954,10 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
 
     int t = blockIdx.x;
     cx<float> p0[16], p1[16];
+    if constexpr (MT != 0) {  // lanes of lines past the end compute on zeros
+#pragma unroll
+        for (int m = 0; m < 16; ++m) p0[m] = p1[m] = make_float2(0.f, 0.f);
+    }
     if (t < ntiles) load(p0, p1, t);
     __syncthreads();
     for (; t < ntiles; t += gridDim.x) {
@@ -844,10 +974,20 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
         if (tn < ntiles) load(p0, p1, tn);
         if (tid < 16 && 16 * t + tid < lines) rowoff[tid] = x_rowoff(a, 16 * t + tid);
 
-        Dft<float, 16, -1>::run(v0);
-        Dft<float, 16, -1>::run(v1);
+        if constexpr (MT != 0) {  // stage 0 on the matrix cores, from the load registers
+            cx<float> x[32];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
+            for (int m = 0; m < 16; ++m) {
+                x[m] = v0[m];
+                x[16 + m] = v1[m];
+            }
+            p2_stage0_mfma<M, TC, -1, MT, true>(x, buf, atab, tv);
+        } else {
+            Dft<float, 16, -1>::run(v0);
+            Dft<float, 16, -1>::run(v1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_in * 16 + r, cp_in)] = pack2(v0[r], v1[r]);
+        }
         __syncthreads();
         if constexpr (S == 3 && MT != 0) {
             p2_stage1_mfma<M, TC, -1, MT>(buf, twl + p2_twoff(M, 1), atab, tv);
@@ -1034,18 +1174,22 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
         __syncthreads();
 
         cx<float> v0[16], v1[16];
+        if constexpr (MT != 0) {  // stage 0 on the matrix cores, inputs from the LDS tile
+            p2_stage0_mfma_lds<M, TC, 1, MT>(buf, atab, tv);
+        } else {
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
-            v0[m] = make_float2(x.x, x.y);
-            v1[m] = make_float2(x.z, x.w);
+            for (int m = 0; m < 16; ++m) {
+                const float4 x = buf[p2_slot<TC>(q_mid + T * m, cp_mid)];
+                v0[m] = make_float2(x.x, x.y);
+                v1[m] = make_float2(x.z, x.w);
+            }
+            __syncthreads();
+            Dft<float, 16, 1>::run(v0);
+            Dft<float, 16, 1>::run(v1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_mid * 16 + r, cp_mid)] = pack2(v0[r], v1[r]);
+            __syncthreads();
         }
-        __syncthreads();
-        Dft<float, 16, 1>::run(v0);
-        Dft<float, 16, 1>::run(v1);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q_mid * 16 + r, cp_mid)] = pack2(v0[r], v1[r]);
-        __syncthreads();
         if constexpr (S == 3 && MT != 0) {
             p2_stage1_mfma<M, TC, 1, MT>(buf, twl + p2_twoff(M, 1), atab, tv);
         } else if constexpr (S == 3) {
