@@ -60,6 +60,7 @@ extern "C" {
 #define PF_ENOMEM (-5)        /* device allocation failed                     */
 #define PF_EWORKSPACE (-6)    /* workspace missing or too small               */
 #define PF_EHIP (-7)          /* a HIP runtime call or kernel launch failed   */
+#define PF_ETIMEOUT (-8)      /* a fused pass's bounded wait expired (pf_check_status) */
 
 /* ---- layout option values ---------------------------------------------- */
 #define PF_F32 0 /* single precision (Sec. 3.1: single and double supported) */
@@ -134,6 +135,21 @@ extern "C" {
  * rank's X-pencil block.  A 1 x 1 share is the whole transform.  Not
  * combinable with inplace (PF_EUNSUPPORTED).  The workspace holds the
  * global-layout arrays; zero fills stand in for the received blocks.
+ *
+ * fused_xy = 1 runs the X and Y stages of the transform as one pass, the
+ * slab form of the method (Sec. 4.3, Fig. 10: one exchange instead of two
+ * while the processor count does not exceed the grid edge, which always holds
+ * on one GPU): a persistent kernel transforms each z plane along X and then,
+ * once every X tile of the plane is done, along Y, while the plane's X output
+ * may still sit in the last-level caches.  A direction then takes two passes
+ * (forward: fused X-Y, Z; backward: Z, fused Y-X) and gives the same result
+ * up to rounding order (the same arithmetic; tested against the oracle).
+ * Built for FP32 plain-math 1 x 1 plans with nx in {1024, 2048} and ny in
+ * {512, 1024}; otherwise pf_setup returns PF_EUNSUPPORTED (also if the
+ * device's XCDs, which serve one work queue each, cannot be enumerated at
+ * setup).  The kernel's waits for other workgroups always end (they wait only
+ * for work taken earlier from the same queue) and are also bounded;
+ * pf_check_status reports a bound that expired.
  */
 typedef struct pf_layout {
     int m1, m2;     /* processor grid, each >= 1                            */
@@ -146,6 +162,7 @@ typedef struct pf_layout {
     int share_only; /* 0 (default) or 1: one rank's share, see below         */
     int r1, r2;     /* share_only: the rank, 0 <= r1 < m1, 0 <= r2 < m2;     */
                     /* otherwise 0                                            */
+    int fused_xy;   /* 0 (default) or 1: X and Y stages in one pass, below   */
 } pf_layout;
 
 typedef struct pf_plan pf_plan;
@@ -236,6 +253,14 @@ int pf_destroy(pf_plan *p);
 
 /* Static description of a status code. */
 const char *pf_strerror(int code);
+
+/*
+ * Waits for the device to finish all queued work, then returns PF_ETIMEOUT if
+ * a fused X-Y pass of the plan had a wait reach its bound since the last call
+ * (its output is then wrong), PF_OK otherwise, and clears the report.
+ * PF_OK for plans without fused passes; PF_EINVAL for NULL.
+ */
+int pf_check_status(pf_plan *p);
 
 /* ---- single passes, for stage-level testing ----------------------------- */
 

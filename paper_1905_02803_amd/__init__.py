@@ -29,6 +29,7 @@ PF_EALIAS = -4
 PF_ENOMEM = -5
 PF_EWORKSPACE = -6
 PF_EHIP = -7
+PF_ETIMEOUT = -8
 
 PF_F32, PF_F64 = 0, 1
 PF_PLAIN, PF_MFMA_FP16X2, PF_MFMA_BF16X2 = 0, 1, 2
@@ -42,7 +43,7 @@ EXPORTED = (
     "pf_set_workspace", "pf_ftran_r2c", "pf_btran_c2r", "pf_destroy", "pf_strerror", "pf_num_passes",
     "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
     "pf_batch_setup", "pf_batch_offset", "pf_batch_bytes", "pf_batch_set_mode", "pf_batch_ftran_r2c",
-    "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step", "pf_exec_noalloc",
+    "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step", "pf_exec_noalloc", "pf_check_status",
 )
 
 
@@ -54,7 +55,8 @@ class PfError(RuntimeError):
 
 class pf_layout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int) for name in (
-        "m1", "m2", "stride1", "useeven", "precision", "math", "inplace", "third", "share_only", "r1", "r2")]
+        "m1", "m2", "stride1", "useeven", "precision", "math", "inplace", "third", "share_only", "r1", "r2",
+        "fused_xy")]
 
 
 class pf_tune(ctypes.Structure):
@@ -75,6 +77,7 @@ class Layout:
     share_only: int = 0
     r1: int = 0
     r2: int = 0
+    fused_xy: int = 0
 
     def c(self) -> pf_layout:
         return pf_layout(*[int(getattr(self, f[0])) for f in pf_layout._fields_])
@@ -105,6 +108,7 @@ def lib():
             "pf_ftran_r2c": (i, [vp, vp, vp, vp]),
             "pf_btran_c2r": (i, [vp, vp, vp, vp]),
             "pf_exec_noalloc": (i, [vp, i, vp, vp, vp]),
+            "pf_check_status": (i, [vp]),
             "pf_destroy": (i, [vp]),
             "pf_strerror": (ctypes.c_char_p, [i]),
             "pf_num_passes": (i, [vp, i]),
@@ -187,6 +191,11 @@ PF_NOALLOC_MAX_BYTES = 256 << 20
 def pf_exec_noalloc(h, direction: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
     """Transform with the library's static device scratch as the workspace (no allocation)."""
     _raise(lib().pf_exec_noalloc(h, direction, in_ptr, out_ptr, stream), "pf_exec_noalloc")
+
+
+def pf_check_status(h) -> None:
+    """Wait for the device; raise PfError(PF_ETIMEOUT) if a fused pass of the plan hit its wait bound."""
+    _raise(lib().pf_check_status(h), "pf_check_status")
 
 
 def pf_run_pass(h, direction: int, pass_index: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:

@@ -74,6 +74,13 @@ struct pf_plan {
     // the spectral step's Z passes and product fused into one pass on W
     bool spec_fused;
     PassDesc spec;
+    // fused X-Y passes (pf_layout.fused_xy): their arguments per direction
+    // and the device counters they share (queue tickets, plane counts, status)
+    bool fused;
+    pf::FusedArgs fxy[2];
+    unsigned fused_blocks;
+    int fused_nq;  // work queues: the XCDs the fused launch's workgroups run on
+    unsigned *ctl;
     bool timing;
     PassTiming tim[2][kPasses];
     std::vector<EventPair> pool;
@@ -97,6 +104,7 @@ bool valid_layout_values(const pf_layout *l) {
     if (l->inplace != 0 && l->inplace != 1) return false;
     if (l->third != PF_THIRD_FFT && l->third != PF_THIRD_EMPTY && l->third != PF_THIRD_CHEB) return false;
     if (l->share_only != 0 && l->share_only != 1) return false;
+    if (l->fused_xy != 0 && l->fused_xy != 1) return false;
     if (l->share_only) {
         if (l->r1 < 0 || l->r1 >= l->m1 || l->r2 < 0 || l->r2 >= l->m2) return false;
     } else if (l->r1 != 0 || l->r2 != 0) {
@@ -213,10 +221,15 @@ int check_impl(int nx, int ny, int nz, const pf_layout *l) {
     return PF_OK;
 }
 
-// Options accepted by pf_check but not built into the transform yet.
-int built_options(const pf_layout *l) {
+// Options accepted by pf_check but not built for this grid / combination.
+int built_options(int nx, int ny, const pf_layout *l) {
     if (l->math != PF_PLAIN && l->precision != PF_F32) return PF_EUNSUPPORTED;
     if (l->share_only && l->inplace) return PF_EUNSUPPORTED;
+    if (l->fused_xy) {
+        if (!pf::p2_fused_supported(nx, ny, l->precision) || l->math != PF_PLAIN || l->share_only ||
+            l->m1 * l->m2 > 1)
+            return PF_EUNSUPPORTED;
+    }
     return PF_OK;
 }
 
@@ -505,6 +518,56 @@ void build_share_only(pf_plan *p) {
     }
 }
 
+// Fused plans: the X and Y passes of each direction become one pass (the
+// first forward, the last backward); the Z passes stay.  Items: 512 threads'
+// worth of 16-line X tiles or Y tiles (z, column block) of one plane.
+constexpr int kFusedLag = 2;         // planes of producer work a queue runs ahead of its consumer work
+constexpr long long kFusedSpin = 1LL << 22;  // polls before a wait gives up (a few seconds)
+
+void build_fused(pf_plan *p) {
+    for (int dir = 0; dir < 2; ++dir) {
+        const PassDesc &x = p->pass[dir][dir == 0 ? 0 : 2];
+        const PassDesc &y = p->pass[dir][1];
+        const PassDesc z = p->pass[dir][dir == 0 ? 2 : 0];
+        pf::FusedArgs &f = p->fxy[dir];
+        std::memset(&f, 0, sizeof(f));
+        f.x = x.a;
+        f.y = y.a;
+        f.ctl = p->ctl;
+        f.nq = p->fused_nq;
+        f.lag = kFusedLag;
+        f.nz = p->nz;
+        f.xtiles = p->ny / 16;
+        f.ytiles = (int)y.a.CB;
+        const int xt = pf::p2_fused_tiles_per_item(p->nx, 1), yt = pf::p2_fused_tiles_per_item(p->ny, 0);
+        f.xitems = (f.xtiles + xt - 1) / xt;
+        f.yitems = (f.ytiles + yt - 1) / yt;
+        f.spin_limit = kFusedSpin;
+        PassDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.kind = pf::PASS_FUSED_XY;
+        d.dir = dir == 0 ? -1 : 1;
+        d.prec = p->lay.precision;
+        d.blocks = p->fused_blocks;
+        d.threads = 512;
+        d.lds = pf::p2_fused_lds_bytes(p->nx, p->ny);
+        const double xb = p->pass_bytes[dir][dir == 0 ? 0 : 2];  // N s + M 2s
+        if (dir == 0) {
+            p->pass[0][0] = d;
+            p->pass[0][1] = z;
+            p->pass_names[0][0] = "fwd_xy_fused";
+            p->pass_names[0][1] = "fwd_z_c2c";
+            p->pass_bytes[0][1] = p->pass_bytes[0][2];
+            p->pass_bytes[0][0] = xb;
+        } else {
+            p->pass[1][1] = d;
+            p->pass_names[1][1] = "bwd_yx_fused";
+            p->pass_bytes[1][1] = xb;
+        }
+        p->npass[dir] = 2;
+    }
+}
+
 void build_passes(pf_plan *p) {
     const long long zstride = p->zrows * p->B;  // complex elements between z planes of W
     const double rs = p->lay.precision == PF_F64 ? 8.0 : 4.0;
@@ -620,6 +683,7 @@ void build_passes(pf_plan *p) {
         }
     }
     if (p->share) build_share_only(p);
+    if (p->fused) build_fused(p);
 }
 
 EventPair take_events(pf_plan *p) {
@@ -659,7 +723,20 @@ int run_one(pf_plan *p, int dir, int i, const void *in, void *out, hipStream_t s
         ev = take_events(p);
         timed = ev.start && ev.stop && hipEventRecord(ev.start, s) == hipSuccess;
     }
-    hipError_t e = pf::launch_pass(d, s);
+    hipError_t e;
+    if (d.kind == pf::PASS_FUSED_XY) {  // X reads / writes the user side, Y runs in place on the workspace
+        pf::FusedArgs f = p->fxy[dir];
+        if (dir == 0) {
+            f.x.in = in, f.x.out = out;
+            f.y.in = out, f.y.out = out;
+        } else {  // in is the workspace, transformed in place along y first
+            f.y.in = in, f.y.out = const_cast<void *>(in);
+            f.x.in = in, f.x.out = out;
+        }
+        e = pf::p2_fused_launch(f, dir == 0, p->nx, p->ny, d.blocks, s);
+    } else {
+        e = pf::launch_pass(d, s);
+    }
     // a pass whose events could not be recorded is left out of the timing
     if (timed && hipEventRecord(ev.stop, s) == hipSuccess)
         p->tim[dir][i].used.push_back(ev);
@@ -705,6 +782,11 @@ int run_chain_ws(pf_plan *p, int dir, const void *in, void *out, void *ws, hipSt
             if (!r) r = run_one(p, 1, 4, nullptr, w, s, untimed);
             if (!r) r = run_one(p, 1, 5, w + p->so_x, out, s, untimed);
         }
+        return r;
+    }
+    if (p->fused) {  // pass 0: user -> workspace; pass 1: workspace -> user
+        int r = run_one(p, dir, 0, in, ws, s, untimed);
+        if (!r) r = run_one(p, dir, 1, ws, out, s, untimed);
         return r;
     }
     if (!p->blocked) {
@@ -817,7 +899,7 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     *out = nullptr;
     int rc = check_impl(nx, ny, nz, l);
     if (rc) return rc;
-    rc = built_options(l);
+    rc = built_options(nx, ny, l);
     if (rc) return rc;
     pf_plan *p = new (std::nothrow) pf_plan();
     if (!p) return PF_ENOMEM;
@@ -909,6 +991,31 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
         delete p;
         return hip_status(e);
     }
+    p->fused = l->fused_xy != 0;
+    if (e == hipSuccess && p->fused) {
+        e = pf::p2_fused_prepare(nx, ny);
+        int nb = 0;
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pf::p2_fused_symbol(nx, ny, 1), 512,
+                                                             pf::p2_fused_lds_bytes(nx, ny));
+        p->fused_blocks = (unsigned)(p->ncu * (nb > 0 ? nb : 1));
+        // one queue per XCD; the launch's workgroups must cover XCDs 0 .. nq-1
+        if (e == hipSuccess) e = pf::p2_xcd_queues(p->fused_blocks, &p->fused_nq);
+        if (e == hipSuccess && p->fused_nq == 0) {
+            (void)hipFree(p->tw_dev);
+            delete p;
+            return PF_EUNSUPPORTED;
+        }
+        const size_t n = (size_t)p->fused_nq + nz + 1;
+        if (e == hipSuccess) e = hipMalloc(&p->ctl, n * sizeof(unsigned));
+        if (e == hipSuccess) e = hipMemset(p->ctl, 0, n * sizeof(unsigned));
+        if (e != hipSuccess) {
+            if (p->ctl) (void)hipFree(p->ctl);
+            (void)hipFree(p->tw_dev);
+            delete p;
+            return hip_status(e);
+        }
+    }
     p->share = l->share_only != 0;
     p->blocked = !p->share && l->m1 * l->m2 > 1;
     p->w_bytes = ((size_t)p->nz * p->nkb * p->ny * p->B * p->csize + 255) & ~(size_t)255;
@@ -929,6 +1036,7 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     }
     e = hipMalloc(&p->ws, p->ws_bytes);
     if (e != hipSuccess) {
+        if (p->ctl) (void)hipFree(p->ctl);
         (void)hipFree(p->tw_dev);
         delete p;
         return hip_status(e);
@@ -939,6 +1047,7 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     if (p->share) e = hipMemset((char *)p->ws + p->w_bytes, 0, p->ws_bytes - p->w_bytes);
     if (e != hipSuccess) {
         (void)hipFree(p->ws);
+        if (p->ctl) (void)hipFree(p->ctl);
         (void)hipFree(p->tw_dev);
         delete p;
         return hip_status(e);
@@ -992,9 +1101,22 @@ int pf_destroy(pf_plan *p) {
         if (e.stop) (void)hipEventDestroy(e.stop);
     }
     if (p->own_ws && p->ws) (void)hipFree(p->ws);
+    if (p->ctl) (void)hipFree(p->ctl);
     if (p->tw_dev) (void)hipFree(p->tw_dev);
     delete p;
     return PF_OK;
+}
+
+int pf_check_status(pf_plan *p) {
+    if (!p) return PF_EINVAL;
+    if (!p->fused || !p->ctl) return PF_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return PF_EHIP;
+    unsigned st = 0;
+    unsigned *word = p->ctl + p->fused_nq + p->nz;
+    if (hipMemcpy(&st, word, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return PF_EHIP;
+    if (st == 0) return PF_OK;
+    if (hipMemset(word, 0, sizeof(unsigned)) != hipSuccess) return PF_EHIP;
+    return PF_ETIMEOUT;
 }
 
 const char *pf_strerror(int code) {
@@ -1007,6 +1129,7 @@ const char *pf_strerror(int code) {
         case PF_ENOMEM: return "device allocation failed";
         case PF_EWORKSPACE: return "workspace missing or too small";
         case PF_EHIP: return "HIP runtime error";
+        case PF_ETIMEOUT: return "a fused pass's bounded wait expired";
         default: return "unknown error";
     }
 }
@@ -1043,7 +1166,7 @@ int pf_copy(void *dst, const void *src, size_t bytes, void *stream) {
 
 int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjoint, void *stream) {
     if (!p || !in || !spec || !out || (adjoint != 0 && adjoint != 1)) return PF_EINVAL;
-    if (p->lay.third != PF_THIRD_CHEB || p->blocked || p->share || p->lay.inplace) return PF_EUNSUPPORTED;
+    if (p->lay.third != PF_THIRD_CHEB || p->blocked || p->share || p->lay.inplace || p->fused) return PF_EUNSUPPORTED;
     if (!aligned16(in) || !aligned16(spec) || !aligned16(out)) return PF_EALIGN;
     if (in == spec || spec == out || in == out) return PF_EALIAS;
     hipStream_t s = (hipStream_t)stream;
@@ -1205,7 +1328,8 @@ int pf_batch_setup(int count, const int *dims, const pf_layout *l, const pf_tune
     if (!out) return PF_EINVAL;
     *out = nullptr;
     if (count < 1 || !dims || !l) return PF_EINVAL;
-    if (l->m1 != 1 || l->m2 != 1 || l->share_only || l->inplace || l->math != PF_PLAIN) return PF_EUNSUPPORTED;
+    if (l->m1 != 1 || l->m2 != 1 || l->share_only || l->inplace || l->math != PF_PLAIN || l->fused_xy)
+        return PF_EUNSUPPORTED;
     for (int i = 0; i < count; ++i) {
         const int rc = check_impl(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], l);
         if (rc) return rc;

@@ -793,6 +793,8 @@ hipError_t launch_pass(const PassDesc &d, hipStream_t s) {
             return launch_fill(d.f, s);
         case PASS_BOX:
             return launch_box(d.b, s);
+        case PASS_FUSED_XY:  // launched by the planner (p2_fused_launch), which holds its arguments
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -18,7 +18,10 @@
 // (whole lines) lanes run along points.  Middle stages always run along
 // columns.  The LDS tile uses a swizzle that keeps every one of these access
 // patterns free of bank conflicts for N = 1024.
+#include <vector>
+
 #include "fft_device.h"
+#include "fused_schedule.h"
 #include "pf_internal.h"
 
 namespace pf {
@@ -882,41 +885,62 @@ __device__ __forceinline__ long long x_rowoff(const PassArgs &a, int g) {
     return ((long long)z * a.zrows + a.y0 + y) << 4;
 }
 
+// The forward X stage split like C2cP2: tables, loads of one tile, transform,
+// split and stores of one tile.  tv: the thread's index among the NT threads
+// of one tile; buf, rowoff: that tile's LDS work area; tables: twiddles (the
+// M-point stage table, then the split table at M), A operands at 2 M + 2.
 template <int M, int MT>
-__global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
-    constexpr int TC = 16;
-    constexpr int T = M / 16;
-    constexpr int CP = 8;
-    constexpr int NT = T * CP;
-    constexpr int S = p2_stages(M);
-    constexpr int RL = p2_radix(M, S - 1);
-    constexpr int NSL = p2_ns(M, S - 1);
-    constexpr int NKB = M / 16 + 1;  // workspace column blocks for M + 1 modes
-    float4 *buf = reinterpret_cast<float4 *>(pf_smem);
-    cx<float> *twl = reinterpret_cast<cx<float> *>(buf + M * CP);
-    cx<float> *spl = twl + M;
-    __shared__ long long rowoff[16];
-    const int tid = threadIdx.x;
-    const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
-    for (int i = tid; i < 2 * M + 1; i += NT)
-        if (i != M - 1) twl[i] = tw[i];
+struct R2cP2 {
+    static constexpr int TC = 16;
+    static constexpr int T = M / 16;
+    static constexpr int CP = 8;
+    static constexpr int NT = T * CP;
+    static constexpr int S = p2_stages(M);
+    static constexpr int RL = p2_radix(M, S - 1);
+    static constexpr int NSL = p2_ns(M, S - 1);
+    static constexpr int NKB = M / 16 + 1;  // workspace column blocks for M + 1 modes
+    static constexpr size_t kTileLds = (size_t)M * CP * 16;
+    static constexpr size_t kTableLds = (size_t)(2 * M + 2) * 8 + (MT ? kMfmaTableBytes : 0);
     typedef typename MfmaSplit<MT == 0 ? 1 : MT>::vec avec;
-    avec *atab = reinterpret_cast<avec *>(twl + 2 * M + 2);  // matrix-core A operands (MT != 0)
-    if constexpr (MT != 0) {
-        if (tid < 64) {
-            MfmaDft16<-1, MT> d0;
-            d0.init(tid);
-            d0.store(atab, tid);
+
+    const PassArgs &a;
+    float4 *buf;
+    cx<float> *twl, *spl;
+    avec *atab;  // matrix-core A operands (MT != 0)
+    long long *rowoff;
+    const float *__restrict__ in;
+    cx<float> *__restrict__ out;
+    int lines, ntiles;
+    long long kbstride;
+
+    __device__ __forceinline__ R2cP2(const PassArgs &pa, float4 *tile_lds, cx<float> *tables, long long *rows) : a(pa) {
+        buf = tile_lds;
+        twl = tables;
+        spl = twl + M;
+        atab = reinterpret_cast<avec *>(twl + 2 * M + 2);
+        rowoff = rows;
+        in = reinterpret_cast<const float *>(a.in);
+        out = reinterpret_cast<cx<float> *>(a.out);
+        lines = (int)a.lines;
+        ntiles = (lines + 15) / 16;
+        kbstride = a.kbrows << 4;
+    }
+
+    // tables into LDS by nthr threads; the caller synchronises before use
+    __device__ __forceinline__ void init_tables(int tv, int nthr) const {
+        const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
+        for (int i = tv; i < 2 * M + 1; i += nthr)
+            if (i != M - 1) twl[i] = tw[i];
+        if constexpr (MT != 0) {
+            if (tv < 64) {
+                MfmaDft16<-1, MT> d0;
+                d0.init(tv);
+                d0.store(atab, tv);
+            }
         }
     }
-    const float *__restrict__ in = reinterpret_cast<const float *>(a.in);
-    cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(a.out);
-    const int lines = (int)a.lines;
-    const int ntiles = (lines + 15) / 16;
-    const long long kbstride = a.kbrows << 4;
 
-    auto load = [&](cx<float>(&d0)[16], cx<float>(&d1)[16], int t) {
-        const int tv = opaque_tid();
+    __device__ __forceinline__ void load(cx<float> (&d0)[16], cx<float> (&d1)[16], int t, int tv) const {
         if constexpr (MT != 0) {
             // matrix-core stage 0: group i in d0[4 i + s] (i < 4) or d1[4 (i - 4) + s];
             // lane (b, g) holds complex point q + T (4 g + s) of its line
@@ -950,29 +974,15 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
             for (int m = 0; m < 16; ++m)
                 d1[m] = gld<streamed<LD_R2C>()>(reinterpret_cast<const float2 *>(pa + a.ld_real + 2 * T * m));
         }
-    };
-
-    int t = blockIdx.x;
-    cx<float> p0[16], p1[16];
-    if constexpr (MT != 0) {  // lanes of lines past the end compute on zeros
-#pragma unroll
-        for (int m = 0; m < 16; ++m) p0[m] = p1[m] = make_float2(0.f, 0.f);
     }
-    if (t < ntiles) load(p0, p1, t);
-    __syncthreads();
-    for (; t < ntiles; t += gridDim.x) {
-        const int tv = opaque_tid();
+
+    // Transform, split and stores of tile t; ends with a barrier (the LDS tile
+    // and row offsets are reused by the next tile).
+    template <bool NTS = streamed<ST_R2C>()>
+    __device__ __forceinline__ void tile(cx<float> (&v0)[16], cx<float> (&v1)[16], int t, int tv) const {
         const int cp_in = tv / T, q_in = tv % T;     // lines: lanes along points
         const int cp_mid = tv % CP, q_mid = tv / CP; // exchanges: lanes along line pairs
-        cx<float> v0[16], v1[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            v0[m] = p0[m];
-            v1[m] = p1[m];
-        }
-        const int tn = t + gridDim.x;
-        if (tn < ntiles) load(p0, p1, tn);
-        if (tid < 16 && 16 * t + tid < lines) rowoff[tid] = x_rowoff(a, 16 * t + tid);
+        if (tv < 16 && 16 * t + tv < lines) rowoff[tv] = x_rowoff(a, 16 * t + tv);
 
         if constexpr (MT != 0) {  // stage 0 on the matrix cores, from the load registers
             cx<float> x[32];
@@ -1044,59 +1054,106 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
 #pragma unroll
             for (int e = 0; e < 2; ++e) split(k0 + e, pr, xa[e], xb[e]);
             const long long col = (long long)kb * kbstride + 2 * kp;
-            gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(out + rowoff[2 * pr] + col), pack2(xa[0], xa[1]));
+            gst<NTS>(reinterpret_cast<float4 *>(out + rowoff[2 * pr] + col), pack2(xa[0], xa[1]));
             if (ga + 1 < lines)
-                gst<streamed<ST_R2C>()>(reinterpret_cast<float4 *>(out + rowoff[2 * pr + 1] + col), pack2(xb[0], xb[1]));
+                gst<NTS>(reinterpret_cast<float4 *>(out + rowoff[2 * pr + 1] + col), pack2(xb[0], xb[1]));
             if (k0 == 0) {
                 float2 na, nb;
                 split(M, pr, na, nb);
                 const long long cm = (long long)(NKB - 1) * kbstride;
-                gst<streamed<ST_R2C>()>(out + rowoff[2 * pr] + cm, na);
-                if (ga + 1 < lines) gst<streamed<ST_R2C>()>(out + rowoff[2 * pr + 1] + cm, nb);
+                gst<NTS>(out + rowoff[2 * pr] + cm, na);
+                if (ga + 1 < lines) gst<NTS>(out + rowoff[2 * pr + 1] + cm, nb);
             }
         }
         __syncthreads();  // LDS tile and row offsets are reused by the next tile
     }
-}
+};
 
 template <int M, int MT>
-__global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
-    constexpr int TC = 16;
-    constexpr int T = M / 16;
-    constexpr int CP = 8;
-    constexpr int NT = T * CP;
-    constexpr int S = p2_stages(M);
-    constexpr int RL = p2_radix(M, S - 1);
-    constexpr int NSL = p2_ns(M, S - 1);
-    constexpr int NIT = M / 2 * 8 / NT;  // (mode k < M/2, line pair) items per thread per tile
-    static_assert(NT % 128 == 0, "an item's line pair depends on tid only");
+__global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
+    typedef R2cP2<M, MT> K;
+    __shared__ long long rowoff[16];
     float4 *buf = reinterpret_cast<float4 *>(pf_smem);
-    cx<float> *twl = reinterpret_cast<cx<float> *>(buf + M * CP);
-    cx<float> *spl = twl + M;
-    const int tid = threadIdx.x;
-    const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
-    for (int i = tid; i < 2 * M + 1; i += NT)
-        if (i != M - 1) twl[i] = tw[i];
+    K k(a, buf, reinterpret_cast<cx<float> *>(buf + M * K::CP), rowoff);
+    k.init_tables(threadIdx.x, K::NT);
+    int t = blockIdx.x;
+    cx<float> p0[16], p1[16];
+    if constexpr (MT != 0) {  // lanes of lines past the end compute on zeros
+#pragma unroll
+        for (int m = 0; m < 16; ++m) p0[m] = p1[m] = make_float2(0.f, 0.f);
+    }
+    if (t < k.ntiles) k.load(p0, p1, t, opaque_tid());
+    __syncthreads();
+    for (; t < k.ntiles; t += gridDim.x) {
+        cx<float> v0[16], v1[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            v0[m] = p0[m];
+            v1[m] = p1[m];
+        }
+        const int tn = t + gridDim.x;
+        if (tn < k.ntiles) k.load(p0, p1, tn, opaque_tid());
+        k.tile(v0, v1, t, opaque_tid());
+    }
+}
+
+// The backward X stage split like R2cP2 (loads of one tile's spectra, inverse
+// split, transform and stores of one tile).
+template <int M, int MT>
+struct C2rP2 {
+    static constexpr int TC = 16;
+    static constexpr int T = M / 16;
+    static constexpr int CP = 8;
+    static constexpr int NT = T * CP;
+    static constexpr int S = p2_stages(M);
+    static constexpr int RL = p2_radix(M, S - 1);
+    static constexpr int NSL = p2_ns(M, S - 1);
+    static constexpr int NIT = M / 2 * 8 / NT;  // (mode k < M/2, line pair) items per thread per tile
+    static_assert(NT % 128 == 0, "an item's line pair depends on tv only");
+    static constexpr size_t kTileLds = (size_t)M * CP * 16;
+    static constexpr size_t kTableLds = (size_t)(2 * M + 2) * 8 + (MT ? kMfmaTableBytes : 0);
     typedef typename MfmaSplit<MT == 0 ? 1 : MT>::vec avec;
-    avec *atab = reinterpret_cast<avec *>(twl + 2 * M + 2);  // matrix-core A operands (MT != 0)
-    if constexpr (MT != 0) {
-        if (tid < 64) {
-            MfmaDft16<1, MT> d0;
-            d0.init(tid);
-            d0.store(atab, tid);
+
+    const PassArgs &a;
+    float4 *buf;
+    cx<float> *twl, *spl;
+    avec *atab;  // matrix-core A operands (MT != 0)
+    const cx<float> *__restrict__ in;
+    float *__restrict__ out;
+    int lines, ntiles;
+
+    __device__ __forceinline__ C2rP2(const PassArgs &pa, float4 *tile_lds, cx<float> *tables) : a(pa) {
+        buf = tile_lds;
+        twl = tables;
+        spl = twl + M;
+        atab = reinterpret_cast<avec *>(twl + 2 * M + 2);
+        in = reinterpret_cast<const cx<float> *>(a.in);
+        out = reinterpret_cast<float *>(a.out);
+        lines = (int)a.lines;
+        ntiles = (lines + 15) / 16;
+    }
+
+    __device__ __forceinline__ void init_tables(int tv, int nthr) const {
+        const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
+        for (int i = tv; i < 2 * M + 1; i += nthr)
+            if (i != M - 1) twl[i] = tw[i];
+        if constexpr (MT != 0) {
+            if (tv < 64) {
+                MfmaDft16<1, MT> d0;
+                d0.init(tv);
+                d0.store(atab, tv);
+            }
         }
     }
-    const cx<float> *__restrict__ in = reinterpret_cast<const cx<float> *>(a.in);
-    float *__restrict__ out = reinterpret_cast<float *>(a.out);
-    const int lines = (int)a.lines;
-    const int ntiles = (lines + 15) / 16;
 
-    // item i of this thread: f = tid + NT i -> mode k = 16 kb + j (k < M/2) and line
+    // item i of this thread: f = tv + NT i -> mode k = 16 kb + j (k < M/2) and line
     // pair pr; it holds X[k] and X[M-k] of both lines (for k = 0 the partner is
     // X[M], the first slot of the last column block), and threads 0..15 hold
-    // X[M/2] of line tid.  A wave reads whole 128-byte rows of the workspace.
+    // X[M/2] of line tv.  A wave reads whole 128-byte rows of the workspace.
     // Addresses: one 64-bit tile base (uniform) plus offsets from it.
-    auto load = [&](float4(&xk)[NIT], float4(&xm)[NIT], float2 &xh, int t) {
+    // xk[2 i], xk[2 i + 1]: X[k] of the item's two lines; xm likewise X[M - k]
+    __device__ __forceinline__ void load(cx<float> (&xk)[2 * NIT], cx<float> (&xm)[2 * NIT], float2 &xh, int t,
+                                         int tv) const {
         const int g0 = 16 * t;
         const int z0 = g0 / a.ny;
         const int y0 = g0 - z0 * a.ny;
@@ -1114,46 +1171,40 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
         auto col = [&](int k) { return (long long)(k >> 4) * kbs + (k & 15); };
         // lines past the end load the last line instead; their results are never stored
         const int lmax = lines - 1 - g0;
-        const int pr = (tid >> 4) & 7;  // the same line pair for every item (NT is a multiple of 128)
+        const int pr = (tv >> 4) & 7;  // the same line pair for every item (NT is a multiple of 128)
         const cx<float> *ra = tb + rowrel(min(2 * pr, lmax));
         const cx<float> *rb = tb + rowrel(min(2 * pr + 1, lmax));
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
-            const int f = tid + NT * i;
+            const int f = tv + NT * i;
             const int k = ((f >> 7) << 4) + (f & 15);
             const int ck = col(k), cm = col(M - k);
-            const float2 ak = gld<streamed<LD_C2R>()>(ra + ck), am = gld<streamed<LD_C2R>()>(ra + cm);
-            const float2 bk = gld<streamed<LD_C2R>()>(rb + ck), bm = gld<streamed<LD_C2R>()>(rb + cm);
-            xk[i] = make_float4(ak.x, ak.y, bk.x, bk.y);
-            xm[i] = make_float4(am.x, am.y, bm.x, bm.y);
+            xk[2 * i] = gld<streamed<LD_C2R>()>(ra + ck);
+            xm[2 * i] = gld<streamed<LD_C2R>()>(ra + cm);
+            xk[2 * i + 1] = gld<streamed<LD_C2R>()>(rb + ck);
+            xm[2 * i + 1] = gld<streamed<LD_C2R>()>(rb + cm);
         }
-        if (tid < 16) xh = gld<streamed<LD_C2R>()>(tb + rowrel(min(tid, lmax)) + col(M / 2));
-    };
+        if (tv < 16) xh = gld<streamed<LD_C2R>()>(tb + rowrel(min(tv, lmax)) + col(M / 2));
+    }
 
     // Zb[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) W_nx^-k, one line
-    auto zb = [](float2 Xk, float2 Xm, float2 w) {
+    __device__ __forceinline__ static float2 zb(float2 Xk, float2 Xm, float2 w) {
         const float2 E = make_float2(Xk.x + Xm.x, Xk.y - Xm.y);
         const float2 O = cmul(make_float2(Xk.x - Xm.x, Xk.y + Xm.y), w);
         return make_float2(E.x - O.y, E.y + O.x);
-    };
+    }
 
-    int t = blockIdx.x;
-    float4 pk[NIT], pm[NIT];
-    float2 ph;
-    if (t < ntiles) load(pk, pm, ph, t);
-    __syncthreads();
-    for (; t < ntiles; t += gridDim.x) {
-        const int tv = opaque_tid();
-        const int cp_mid = tv % CP, q_mid = tv / CP;
-        const int cp_out = tv / T, q_out = tv % T;
-        // inverse split from registers into LDS: item (k, pair) writes Zb[k] and
-        // Zb[M-k] of both lines; modes 0 and M contribute their real parts only
+    // inverse split from registers into LDS: item (k, pair) writes Zb[k] and
+    // Zb[M-k] of both lines; modes 0 and M contribute their real parts only.
+    // The caller synchronises before the transform reads the tile.
+    __device__ __forceinline__ void split(const cx<float> (&pk)[2 * NIT], const cx<float> (&pm)[2 * NIT], float2 ph,
+                                          int tv) const {
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int f = tv + NT * i;
             const int k = ((f >> 7) << 4) + (f & 15), pr = (f >> 4) & 7;
-            float2 Ak = make_float2(pk[i].x, pk[i].y), Bk = make_float2(pk[i].z, pk[i].w);
-            float2 Am = make_float2(pm[i].x, pm[i].y), Bm = make_float2(pm[i].z, pm[i].w);
+            float2 Ak = pk[2 * i], Bk = pk[2 * i + 1];
+            float2 Am = pm[2 * i], Bm = pm[2 * i + 1];
             if (k == 0) Ak.y = Bk.y = Am.y = Bm.y = 0.f;
             const cx<float> w = spl[k];
             const float2 wc = make_float2(w.x, -w.y);  // W_nx^-k
@@ -1169,10 +1220,13 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
             reinterpret_cast<float2 *>(buf)[2 * p2_slot<TC>(M / 2, tv >> 1) + (tv & 1)] =
                 zb(ph, ph, make_float2(w.x, -w.y));
         }
-        const int tn = t + gridDim.x;
-        if (tn < ntiles) load(pk, pm, ph, tn);
-        __syncthreads();
+    }
 
+    // The inverse transform of tile t (its spectra split into the LDS tile and
+    // synchronised) and the stores of its real lines; ends with a barrier.
+    __device__ __forceinline__ void tile(int t, int tv) const {
+        const int cp_mid = tv % CP, q_mid = tv / CP;
+        const int cp_out = tv / T, q_out = tv % T;
         cx<float> v0[16], v1[16];
         if constexpr (MT != 0) {  // stage 0 on the matrix cores, inputs from the LDS tile
             p2_stage0_mfma_lds<M, TC, 1, MT>(buf, atab, tv);
@@ -1229,6 +1283,396 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
         }
         __syncthreads();
     }
+};
+
+template <int M, int MT>
+__global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
+    typedef C2rP2<M, MT> K;
+    float4 *buf = reinterpret_cast<float4 *>(pf_smem);
+    K k(a, buf, reinterpret_cast<cx<float> *>(buf + M * K::CP));
+    k.init_tables(threadIdx.x, K::NT);
+    int t = blockIdx.x;
+    cx<float> pk[2 * K::NIT], pm[2 * K::NIT];
+    float2 ph;
+    if (t < k.ntiles) k.load(pk, pm, ph, t, threadIdx.x);
+    __syncthreads();
+    for (; t < k.ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        k.split(pk, pm, ph, tv);
+        const int tn = t + gridDim.x;
+        if (tn < k.ntiles) k.load(pk, pm, ph, tn, threadIdx.x);
+        __syncthreads();
+        k.tile(t, tv);
+    }
+}
+
+// ---- fused X-Y pass: the slab form of the method (Sec. 4.3, Fig. 10) --------
+// The X and Y stages of one z plane need no data from other planes, so one
+// persistent kernel can run both, plane after plane, and the Y stage then
+// reads the X stage's output of a plane shortly after it was written, while
+// it can still be in the caches (one exchange instead of two, as in the
+// paper's slab decomposition).  Work items: X tiles (producers) and Y tiles
+// (consumers) of each plane, dealt to nq queues, one per XCD (plane z to
+// queue z mod nq; a workgroup serves the queue of the XCD it runs on, read
+// from the hardware), so that a plane's producers and consumers share one L2.
+// Within a queue the items are ordered
+//   X(P0) .. X(P(lag-1)), then X(P(j+lag)), Y(Pj) for j = 0, 1, ..., then the
+//   remaining Y,
+// and each block takes the next ticket of its queue.  A consumer item waits
+// until every producer item of its plane has finished; those took earlier
+// tickets of the same queue, so they are held by running blocks, and producer
+// items never wait: the waits always end (no co-residency needed).  Each wait
+// is also bounded (spin_limit polls); on expiry the status word is set, the
+// item runs anyway and the host reports the timeout.  Hand-off: a producer's
+// waves wait until their stores are complete (written to the XCD's L2; the
+// L1 is write-through), then the item is counted with an atomic; a consumer
+// polls the count and then loads the plane through the same L2.  No other
+// work item reads those lines before (a tile's rows belong to one item), so
+// no L1 holds a stale copy, and no L2 write-back or invalidation is needed.  The backward pass is the
+// mirror: Y tiles (producers, sign +1), then the complex-to-real X tiles.
+// The counters are zeroed by k_fused_reset before every launch.
+
+// In-place Y tile on the blocked workspace (rows of 16 modes, 16 columns per
+// tile, plain FP32): the k_c2c_p2 tile for two row sides, without its options.
+template <int N, int DIR>
+struct YRowsP2 {
+    static constexpr int TC = 16;
+    static constexpr int T = N / 16;
+    static constexpr int CP = 8;
+    static constexpr int NT = T * CP;
+    static constexpr int S = p2_stages(N);
+    static constexpr int RL = p2_radix(N, S - 1);
+    static constexpr int NSL = p2_ns(N, S - 1);
+    static constexpr size_t kTileLds = (size_t)N * CP * 16;
+    static constexpr size_t kTableLds = (size_t)N * 8;
+    float4 *buf;
+    cx<float> *twl;
+    cx<float> *ws;
+    const cx<float> *tw;
+    long long sa, sblk;  // workspace elements between z planes / column blocks
+    int CB, C;
+
+    __device__ __forceinline__ YRowsP2(const PassArgs &a, float4 *tile_lds, cx<float> *tables) {
+        buf = tile_lds;
+        twl = tables;
+        ws = reinterpret_cast<cx<float> *>(a.out);
+        tw = reinterpret_cast<const cx<float> *>(a.tw);
+        sa = a.in_s.sa;
+        sblk = a.in_s.sblk;
+        CB = (int)a.CB;
+        C = a.C;
+    }
+    __device__ __forceinline__ void init_tables(int tv, int nthr) const {
+        for (int i = tv; i < N - 1; i += nthr) twl[i] = tw[i];
+    }
+    // element (column 2 cp, row 0) of tile t = (z, column block), valid columns
+    __device__ __forceinline__ long long base(int t, int cp, int &ncol) const {
+        const int z = t / CB, cb = t - z * CB;
+        ncol = min(TC, C - cb * TC);
+        return (long long)z * sa + (long long)cb * sblk + 2 * cp;
+    }
+    // live = false: a tile past the plane's last column block (no memory accesses)
+    __device__ __forceinline__ void load(cx<float> (&d0)[16], cx<float> (&d1)[16], int t, int tv, bool live) const {
+        const int cp = tv % CP, q = tv / CP;
+        int ncol;
+        const long long b = base(t, cp, ncol) + (long long)q * TC;
+        if (live && 2 * cp < ncol) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const float4 x = *reinterpret_cast<const float4 *>(ws + b + (long long)m * T * TC);
+                d0[m] = make_float2(x.x, x.y);
+                d1[m] = make_float2(x.z, x.w);
+            }
+        }
+    }
+    template <bool NTS>
+    __device__ __forceinline__ void tile(cx<float> (&v0)[16], cx<float> (&v1)[16], int t, int tv, bool live) const {
+        const int cp = tv % CP, q = tv / CP;
+        Dft<float, 16, DIR>::run(v0);
+        Dft<float, 16, DIR>::run(v1);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q * 16 + r, cp)] = pack2(v0[r], v1[r]);
+        __syncthreads();
+        if constexpr (S == 3) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const float4 x = buf[p2_slot<TC>(q + T * m, cp)];
+                v0[m] = make_float2(x.x, x.y);
+                v1[m] = make_float2(x.z, x.w);
+            }
+            __syncthreads();
+            p2_butterflies2<N, 16, 16, DIR>(v0, v1, q, twl + p2_twoff(N, 1));
+            const int k = q & 15;
+            const int bse = (q - k) * 16 + k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(bse + r * 16, cp)] = pack2(v0[r], v1[r]);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const float4 x = buf[p2_slot<TC>(q + T * m, cp)];
+            v0[m] = make_float2(x.x, x.y);
+            v1[m] = make_float2(x.z, x.w);
+        }
+        p2_butterflies2<N, RL, NSL, DIR>(v0, v1, q, twl + p2_twoff(N, S - 1));
+        int ncol;
+        const long long b = base(t, cp, ncol) + (long long)q * TC;
+        if (live && 2 * cp < ncol) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+                gst<NTS>(reinterpret_cast<float4 *>(ws + b + (long long)m * T * TC), pack2(v0[m], v1[m]));
+        }
+        __syncthreads();  // the next item reuses the LDS tile
+    }
+};
+
+// s_getreg_b32 operand for the XCC_ID hardware register (id 20, bits 0..3):
+// the XCD a workgroup runs on
+constexpr int kHwRegXccId = (3 << 11) | 20;
+// s_waitcnt operand that waits for every vector memory access of the wave
+// (vmcnt 0; expcnt and lgkmcnt left at their maxima)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Counters of one fused launch: [0, nq) queue tickets, [nq, nq + nz) finished
+// producer items per plane; the status word after them is left alone.
+__global__ __launch_bounds__(256) void k_fused_reset(unsigned *ctl, int n) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) ctl[i] = 0u;
+}
+
+// Forward (FWD = 1): X stage (R2cP2<M>) then Y stage (sign -1) per plane.
+// Backward (FWD = 0): Y stage (sign +1) then X stage (C2rP2<M>).  A block has
+// 512 threads; an X item is XT = 512 / (M/2) tiles of 16 lines run side by
+// side, a Y item YT = 512 / (NY/2) tiles (z, column block).
+template <int M, int NY, int FWD>
+__global__ __launch_bounds__(512) void k_xy_fused(FusedArgs f) {
+    typedef R2cP2<M, 0> XF;
+    typedef C2rP2<M, 0> XB;
+    typedef YRowsP2<NY, FWD ? -1 : 1> Y;
+    constexpr int XNT = XF::NT, XT = 512 / XNT;
+    constexpr int YT = 512 / Y::NT;
+    static_assert(XT * XNT == 512 && YT * Y::NT == 512 && XB::NT == XNT, "items fill the block");
+    static_assert(2 * XB::NIT == 16, "the backward X loads fit the item registers");
+    constexpr size_t XAREA = XT * XF::kTileLds, YAREA = YT * Y::kTileLds;
+    constexpr size_t AREA = XAREA > YAREA ? XAREA : YAREA;
+    __shared__ long long rowoff[XT][16];
+    __shared__ int s_item[4];  // kind, plane, index, next item's loads issued early
+    unsigned char *lds = pf_smem;
+    cx<float> *xtab = reinterpret_cast<cx<float> *>(lds + AREA);
+    cx<float> *ytab = reinterpret_cast<cx<float> *>(lds + AREA + XF::kTableLds);
+    const int tid = threadIdx.x;
+    const int xh = tid / XNT, yh = tid / Y::NT;  // X / Y tile of the item the thread works on
+    float4 *xbuf = reinterpret_cast<float4 *>(lds + xh * XF::kTileLds);
+    float4 *ybuf = reinterpret_cast<float4 *>(lds + yh * Y::kTileLds);
+    const XF xf(f.x, xbuf, xtab, rowoff[xh]);
+    const XB xb(f.x, xbuf, xtab);
+    const Y yk(f.y, ybuf, ytab);
+    if constexpr (FWD) xf.init_tables(tid, 512);
+    else xb.init_tables(tid, 512);
+    yk.init_tables(tid, 512);
+
+    // the block's queue is its XCD: producer and consumer items of a plane then
+    // share one L2, which holds the producers' stores once they are complete,
+    // so the hand-off needs no cache write-back or invalidation
+    const int q = (int)(__builtin_amdgcn_s_getreg(kHwRegXccId) & 15u);
+    if (q >= f.nq) return;  // no XCD beyond the queues the host found (its plan would be refused)
+    const int np = (f.nz - q + f.nq - 1) / f.nq;  // planes q, q + nq, ... of this queue
+    unsigned *tickets = f.ctl;
+    unsigned *done = f.ctl + f.nq;
+    unsigned *status = f.ctl + f.nq + f.nz;
+    const int pitems = FWD ? f.xitems : f.yitems;  // producer / consumer items per plane
+    const int citems = FWD ? f.yitems : f.xitems;
+    const int xall = f.nz * f.xtiles, yall = f.nz * f.ytiles;  // tiles of the X / Y stage
+
+    // thread 0: take the next ticket of the queue and decode it into s_item
+    // (kind -1 past the end)
+    auto fetch = [&]() {
+        if (tid == 0) {
+            const int k = (int)__hip_atomic_fetch_add(tickets + q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int kind = -1, j = 0, idx = 0;
+            if (!fused_item(k, np, f.lag, pitems, citems, kind, j, idx)) kind = -1;
+            s_item[0] = kind;
+            s_item[1] = q + j * f.nq;
+            s_item[2] = idx;
+        }
+    };
+    // thread 0: has every producer item of the plane finished?  With wait, poll
+    // until it has (bounded: past spin_limit polls the status word is set)
+    auto ready = [&](int plane, bool wait) -> bool {
+        unsigned *c = done + plane;
+        long long polls = 0;
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)pitems) {
+            if (!wait) return false;
+            if (++polls > f.spin_limit) {
+                __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        return true;
+    };
+    auto is_x = [](int kind) { return (kind == 0) == (FWD != 0); };
+    // this thread's tile of an item, and whether it exists (the plane's last
+    // item may be partly empty)
+    auto item_tile = [&](int kind, int plane, int idx, bool &live) {
+        if (is_x(kind)) {
+            const int r = idx * XT + xh;
+            live = r < f.xtiles;
+            return live ? plane * f.xtiles + r : xall;
+        }
+        const int r = idx * YT + yh;
+        live = r < f.ytiles;
+        return live ? plane * f.ytiles + r : yall;
+    };
+    cx<float> p0[16], p1[16];  // loads of the next item
+    float2 ph = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) p0[m] = p1[m] = make_float2(0.f, 0.f);
+    // thread indices are re-derived per use from an opaque copy of threadIdx.x:
+    // held across the item loop, the LDS addresses built from them would not
+    // fit the registers
+    auto load = [&](int kind, int plane, int idx) {
+        const int tv = opaque_tid();
+        bool live;
+        const int t = item_tile(kind, plane, idx, live);
+        if (is_x(kind)) {
+            if (live) {
+                if constexpr (FWD) xf.load(p0, p1, t, tv % XNT);
+                else xb.load(p0, p1, ph, t, tv % XNT);
+            }
+        } else {
+            yk.load(p0, p1, t, tv % Y::NT, live);
+        }
+    };
+
+    fetch();
+    __syncthreads();  // tables in LDS, first item in s_item
+    int kind = s_item[0], plane = s_item[1], idx = s_item[2];
+    if (kind == 1 && tid == 0) ready(plane, true);
+    __syncthreads();
+    if (kind >= 0) load(kind, plane, idx);
+    while (kind >= 0) {
+        cx<float> v0[16], v1[16];
+        const float2 vh = ph;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v0[m] = p0[m], v1[m] = p1[m];
+        // the next item: its loads go out now if it is a producer or its plane is complete
+        __syncthreads();  // every thread has read s_item
+        fetch();
+        __syncthreads();
+        const int nkind = s_item[0], nplane = s_item[1], nidx = s_item[2];
+        if (tid == 0) s_item[3] = nkind == 0 ? 1 : (nkind == 1 && ready(nplane, false) ? 1 : 0);
+        __syncthreads();
+        const bool early = nkind >= 0 && s_item[3];
+        if (early) load(nkind, nplane, nidx);
+        // the current item
+        const int tv = opaque_tid();
+        bool live;
+        const int t = item_tile(kind, plane, idx, live);
+        if (is_x(kind)) {
+            if constexpr (FWD) {
+                xf.template tile<false>(v0, v1, t, tv % XNT);  // t past the end stores nothing
+            } else {
+                xb.split(v0, v1, vh, tv % XNT);
+                __syncthreads();
+                xb.tile(t, tv % XNT);
+            }
+        } else {
+            // plain stores: with the nontemporal hint here the compiler keeps the
+            // tile's registers in scratch memory
+            yk.template tile<false>(v0, v1, t, tv % Y::NT, live);
+        }
+        if (kind == 0) {  // a producer item: its stores complete (in the L2), then publish it
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(done + plane, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        kind = nkind, plane = nplane, idx = nidx;
+        if (kind >= 0 && !early) {
+            if (kind == 1 && tid == 0) ready(plane, true);
+            __syncthreads();
+            load(kind, plane, idx);
+        }
+    }
+}
+
+// nx: 1024 or 2048 (X half length 512 / 1024); ny: 512 or 1024
+bool p2_fused_supported(int nx, int ny, int prec) {
+    return prec == 0 && (nx == 1024 || nx == 2048) && (ny == 512 || ny == 1024);
+}
+
+template <int M, int NY>
+static constexpr size_t fused_lds() {
+    constexpr size_t xa = (512 / R2cP2<M, 0>::NT) * R2cP2<M, 0>::kTileLds;
+    constexpr size_t ya = (512 / YRowsP2<NY, 1>::NT) * YRowsP2<NY, 1>::kTileLds;
+    return (xa > ya ? xa : ya) + R2cP2<M, 0>::kTableLds + YRowsP2<NY, 1>::kTableLds;
+}
+
+size_t p2_fused_lds_bytes(int nx, int ny) {
+    if (nx == 1024) return ny == 512 ? fused_lds<512, 512>() : fused_lds<512, 1024>();
+    return ny == 512 ? fused_lds<1024, 512>() : fused_lds<1024, 1024>();
+}
+
+int p2_fused_tiles_per_item(int n, int x) { return x ? 512 / (n / 2 / 16 * 8) : 512 / (n / 16 * 8); }
+
+static const void *fused_pick(int nx, int ny, int fwd) {
+#define PF_FUSED_PICK(NXV, NYV)                                                                       \
+    if (nx == NXV && ny == NYV)                                                                       \
+        return fwd ? (const void *)&k_xy_fused<NXV / 2, NYV, 1> : (const void *)&k_xy_fused<NXV / 2, NYV, 0>;
+    PF_FUSED_PICK(1024, 512)
+    PF_FUSED_PICK(1024, 1024)
+    PF_FUSED_PICK(2048, 512)
+    PF_FUSED_PICK(2048, 1024)
+#undef PF_FUSED_PICK
+    return nullptr;
+}
+
+const void *p2_fused_symbol(int nx, int ny, int fwd) { return fused_pick(nx, ny, fwd); }
+
+// XCD of every workgroup of a launch of `blocks` workgroups
+__global__ __launch_bounds__(64) void k_xcc_probe(unsigned *out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg(kHwRegXccId) & 15u;
+}
+
+hipError_t p2_xcd_queues(unsigned blocks, int *nq) {
+    *nq = 0;
+    unsigned *d = nullptr;
+    hipError_t e = hipMalloc(&d, blocks * sizeof(unsigned));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_xcc_probe, dim3(blocks), dim3(64), 0, 0, d);
+    std::vector<unsigned> h(blocks);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(h.data(), d, blocks * sizeof(unsigned), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return e;
+    unsigned seen = 0;
+    for (unsigned v : h) seen |= 1u << v;
+    int n = 0;
+    while (n < 16 && (seen >> n) & 1u) ++n;
+    if (n > 0 && seen == (1u << n) - 1u) *nq = n;  // XCDs 0 .. n-1, each with workgroups
+    return hipSuccess;
+}
+
+hipError_t p2_fused_prepare(int nx, int ny) {
+    for (int fwd : {0, 1}) {
+        const void *k = fused_pick(nx, ny, fwd);
+        if (!k) return hipErrorInvalidValue;
+        const hipError_t e =
+            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2_fused_lds_bytes(nx, ny));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t p2_fused_launch(const FusedArgs &f, int fwd, int nx, int ny, unsigned blocks, hipStream_t s) {
+    const void *k = fused_pick(nx, ny, fwd);
+    if (!k) return hipErrorInvalidDeviceFunction;
+    const int n = f.nq + f.nz;
+    hipLaunchKernelGGL(k_fused_reset, dim3((n + 255) / 256), dim3(256), 0, s, f.ctl, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    FusedArgs a = f;
+    void *args[] = {&a};
+    return hipLaunchKernel(k, dim3(blocks), dim3(512), args, p2_fused_lds_bytes(nx, ny), s);
 }
 
 bool p2x_supported(int nx, int prec) { return prec == 0 && (nx == 512 || nx == 1024 || nx == 2048); }

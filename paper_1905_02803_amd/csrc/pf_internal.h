@@ -43,7 +43,8 @@ enum PassKind {
     PASS_C2R_P2 = 5,
     PASS_REMAP = 6,
     PASS_FILL = 7,
-    PASS_BOX = 8
+    PASS_BOX = 8,
+    PASS_FUSED_XY = 9  // launched by the planner from its FusedArgs (p2_fused_launch)
 };
 
 // Reorder between the global arrays and the concatenated Table 1 pencil
@@ -176,6 +177,29 @@ hipError_t launch_fill(const FillArgs &f, hipStream_t s);
 hipError_t launch_box(const BoxArgs &b, hipStream_t s);
 // Plain 16-byte-per-lane device copy (bytes a multiple of 16).
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// Fused X-Y pass (kernels_p2.hip, k_xy_fused): the X and Y stages of every z
+// plane in one persistent launch.  x / y: the X and Y passes' arguments (the
+// Y side is the blocked workspace, in place).  nq: work queues, one per XCD.
+// ctl: nq + nz counters, zeroed before each launch, then a status word (bit
+// 0: a wait reached spin_limit).
+struct FusedArgs {
+    PassArgs x, y;
+    unsigned *ctl;
+    int nq, lag, nz;
+    int xtiles, ytiles;  // 16-line X tiles / Y tiles per plane
+    int xitems, yitems;  // work items per plane (an item is 512 threads' worth of tiles)
+    long long spin_limit;
+};
+bool p2_fused_supported(int nx, int ny, int prec);
+size_t p2_fused_lds_bytes(int nx, int ny);
+int p2_fused_tiles_per_item(int n, int x);  // tiles per item: X (x = 1, n = nx) or Y (x = 0, n = ny)
+hipError_t p2_fused_prepare(int nx, int ny);
+const void *p2_fused_symbol(int nx, int ny, int fwd);
+// Number of XCDs the workgroups of a `blocks`-workgroup launch run on, if they
+// are numbered 0 .. n-1 (each a work queue of the fused pass), else 0.
+hipError_t p2_xcd_queues(unsigned blocks, int *nq);
+hipError_t p2_fused_launch(const FusedArgs &f, int fwd, int nx, int ny, unsigned blocks, hipStream_t s);
 
 // Power-of-two FP32 C2C pass (kernels_p2.hip).
 bool p2_supported(int n, int prec);

@@ -103,11 +103,11 @@ int main() {
                             }
                         }
     // option values outside their ranges
-    const int bad_fields = 11;
+    const int bad_fields = 12;
     for (int f = 0; f < bad_fields; ++f)
         for (int i = 0; i < 3; ++i) {
             // fields in declaration order: m1, m2, stride1, useeven, precision, math, inplace,
-            // third, share_only, r1, r2 (r1 / r2 must be 0 without share_only)
+            // third, share_only, r1, r2, fused_xy (r1 / r2 must be 0 without share_only)
             const int grid_bad[3] = {-3, 0, 100}, enum3_bad[3] = {-3, 3, 7}, flag_bad[3] = {-3, 2, 7};
             const int v = f < 2 ? grid_bad[i] : (f == 5 || f == 7) ? enum3_bad[i] : flag_bad[i];
             pf_layout_init(&l);

@@ -75,6 +75,16 @@ def check_grid(shape, seed, tol, maths=()):
         # staged rounding bound of errbounds.py
         for lo, hi, m, e, bound in errbounds.check_shells(got, ref, nx, ny, nz, tol):
             print(f"  shell [{lo:g}, {hi:g}): {m} modes, rel L2 {e:.3e} (bound {bound:.3e})", flush=True)
+        if nx in (1024, 2048) and ny in (512, 1024):  # the fused X-Y plan gives the same bits
+            with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F32, stride1=1, fused_xy=1)) as pfz:
+                Uz = pfz.ftran(ud)
+                assert np.array_equal(Uz.cpu().numpy(), got)
+                bz = pfz.btran(Uz)
+                pf.pf_check_status(pfz.handle)
+                rtz = (torch.linalg.vector_norm(bz.double() / N - ud.double()) /
+                       torch.linalg.vector_norm(ud.double())).item()
+                assert abs(rtz - rt) <= 1e-3 * rt, (rtz, rt)
+                del Uz, bz
         del got
         for mth in maths:  # the matrix-core variants against the same oracle result
             with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F32, stride1=1, math=mth)) as pm:
