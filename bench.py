@@ -270,7 +270,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, n: int, commands) -> None:
     out = {"kernels_sha256": kernels_digest(), "grid": n, "commands": commands, "passes": {}}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = [r for r in read(path) if r["Counter_Name"] == counter]
-        copies = [float(r["Counter_Value"]) * 1024.0 for r in rows if "k_copy" in r["Kernel_Name"]]
+        copies = [float(r["Counter_Value"]) * 1024.0 for r in rows if "k_copy(" in r["Kernel_Name"]]
         ours = [r for r in rows if "pf::k_" in r["Kernel_Name"] and "k_copy" not in r["Kernel_Name"]]
         period = [r["Kernel_Name"] for r in ours[:len(PASS_ORDER)]]
         run = 0
@@ -442,6 +442,49 @@ def other_grid_timings(pf, args, dev, stream):
         out[f"{nx}x{ny}x{nz}"] = {"ms_per_pair": ms, "gflops": 5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9,
                                   "alg_GBps": nbytes / (ms * 1e-3) / 1e9}
         plan.destroy()
+    return out
+
+
+def fused_timing(pf, nx, ny, nz, args, dev, stream, u, plain_passes):
+    """The slab form (pf_layout.fused_xy): X and Y stages in one persistent pass per direction.  Pair time,
+    per-pass times, and the fused pass's bandwidth under two accountings: its own algorithmic bytes (the
+    real array and the complex array once each, what a two-pass transform must move) and the bytes the
+    separate X and Y passes move (the three-pass accounting)."""
+    import torch
+
+    plan = pf.Plan(nx, ny, nz, pf.Layout(fused_xy=1))
+    U = plan.empty_complex(dev)
+    r = plan.empty_real(dev)
+    for _ in range(args.warmup):
+        plan.ftran(u, U)
+        plan.btran(U, r)
+    plan.set_timing(True)
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s0.record(stream)
+    for _ in range(args.steps):
+        plan.ftran(u, U)
+        plan.btran(U, r)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    pf.pf_check_status(plan.handle)
+    three = {p["pass"]: p["alg_bytes"] for p in plain_passes}
+    out = {"ms_per_step": s0.elapsed_time(s1) / args.steps, "passes": []}
+    for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD):
+        for i in range(plan.num_passes(d)):
+            tot, cnt = plan.get_timing(d, i)
+            avg = tot / max(cnt, 1)
+            name = plan.pass_name(d, i)
+            e = {"pass": name, "avg_ms": avg, "alg_bytes": plan.pass_bytes(d, i)}
+            e["alg_GBps"] = e["alg_bytes"] / (avg * 1e-3) / 1e9
+            if "fused" in name:
+                sep = three["fwd_x_r2c"] + three["fwd_y_c2c"] if d == 0 else three["bwd_y_c2c"] + three["bwd_x_c2r"]
+                e["three_pass_bytes"] = sep
+                e["three_pass_GBps"] = sep / (avg * 1e-3) / 1e9
+            out["passes"].append(e)
+    plan.set_timing(False)
+    plan.destroy()
     return out
 
 
@@ -700,17 +743,23 @@ def main():
     Nf = float(nx) * ny * nz
     rt_err = (torch.linalg.vector_norm((r.double() / Nf - u.double())) / torch.linalg.vector_norm(u.double())).item()
 
-    # HBM ceiling: a plain copy of the real array (the same bytes in and out as one pass of it)
-    copy_reps = 5
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    pf.pf_copy(r.data_ptr(), u.data_ptr(), COPY_BYTES(n), stream.cuda_stream)
-    c0.record(stream)
-    for _ in range(copy_reps):
-        pf.pf_copy(r.data_ptr(), u.data_ptr(), COPY_BYTES(n), stream.cuda_stream)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_GBps = 2.0 * COPY_BYTES(n) / (c0.elapsed_time(c1) / copy_reps * 1e-3) / 1e9
+    # HBM ceilings: copies of the real array (the same bytes in and out as one pass of it) in the
+    # passes' access shapes -- the one-shot copy, 128 KB tiles between two arrays (the X and Z passes),
+    # 128 KB tiles in place (the Y pass)
+    probes = {}
+    for pname, kind, dst in (("copy", pf.PF_PROBE_COPY, r), ("tiles", pf.PF_PROBE_TILES, r),
+                             ("tiles_inplace", pf.PF_PROBE_TILES_INPLACE, u)):
+        copy_reps = 5
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        pf.pf_probe(kind, dst.data_ptr(), u.data_ptr(), COPY_BYTES(n), stream.cuda_stream)
+        c0.record(stream)
+        for _ in range(copy_reps):
+            pf.pf_probe(kind, dst.data_ptr(), u.data_ptr(), COPY_BYTES(n), stream.cuda_stream)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        probes[pname] = 2.0 * COPY_BYTES(n) / (c0.elapsed_time(c1) / copy_reps * 1e-3) / 1e9
+    copy_GBps = probes["copy"]
 
     plan.set_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -738,6 +787,9 @@ def main():
             passes.append({"pass": plan.pass_name(d, i), "avg_ms": avg, "launches": cnt,
                            "alg_bytes": nbytes, "alg_GBps": nbytes / (avg * 1e-3) / 1e9 if avg > 0 else None})
     plan.set_timing(False)
+    for p_ in passes:  # against the probe of the pass's own access shape
+        own = probes["tiles_inplace"] if "_y_" in p_["pass"] else probes["tiles"]
+        p_["frac_of_own_probe"] = p_["alg_GBps"] / own if p_["alg_GBps"] else None
     dom = max(passes, key=lambda p: p["avg_ms"])
     keep_host = not args.no_cpu_baseline
     fwd_host = {"plain": U.cpu().numpy() if keep_host else None}
@@ -768,6 +820,7 @@ def main():
             fwd_host[name] = Um.cpu().numpy()
         del Um
         pm.destroy()
+    fused = fused_timing(pf, nx, ny, nz, args, dev, stream, u, passes)
     layouts = layout_timings(pf, nx, ny, nz, args, dev, stream, u)
     batched = batch_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
     spectral = spectral_timing(pf, args, dev, stream)
@@ -802,6 +855,7 @@ def main():
                    "grid": [nx, ny, nz], "precision": "f32", "math": "plain", "layout": "1x1"},
         "hbm_GBps_alg": alg_bytes / (ms * 1e-3) / 1e9,
         "copy_probe_GBps": copy_GBps,
+        "probes_GBps": probes,
         "ms_per_step_median": statistics.median(step_ms),
         "ms_per_step_min": min(step_ms),
         "round_trip_rel_l2": rt_err,
@@ -816,9 +870,11 @@ def main():
             "unit": "GB/s",
             "frac": dom["alg_GBps"] / HBM_PEAK_GBS,
             "frac_of_copy_probe": dom["alg_GBps"] / copy_GBps,
+            "frac_of_own_probe": dom["frac_of_own_probe"],
             "traffic": traffic_from_profile(dom["pass"], n),
         },
         "passes": passes,
+        "fused_xy": fused,
         "share_only": share,
         "layouts": layouts,
         "other_grids": other_grids,

@@ -312,6 +312,24 @@ double pf_pass_bytes(const pf_plan *p, int dir, int pass);
  */
 int pf_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/*
+ * Bandwidth probes for the memory term of Eq. 3, in the access shapes of the
+ * transform passes (bytes a multiple of 16, pointers 16-byte aligned):
+ *   PF_PROBE_COPY           pf_copy's one-shot copy (dst != src);
+ *   PF_PROBE_TILES          persistent workgroups copy 128 KB tiles, the next
+ *                           tile's loads in flight while the current one is
+ *                           stored, nontemporal accesses (dst != src): the
+ *                           shape of a pass between two arrays;
+ *   PF_PROBE_TILES_INPLACE  the same with dst == src, each tile read and
+ *                           written back: the shape of the in-place Y pass.
+ * Returns PF_EINVAL (NULL pointers, unknown kind), PF_EALIGN, PF_EALIAS (dst
+ * and src equal or not as the kind requires), PF_EHIP.
+ */
+#define PF_PROBE_COPY 0
+#define PF_PROBE_TILES 1
+#define PF_PROBE_TILES_INPLACE 2
+int pf_probe(int kind, void *dst, const void *src, size_t bytes, void *stream);
+
 /* ---- per-pass timing with HIP events ------------------------------------ */
 
 /*

@@ -37,6 +37,7 @@ PF_THIRD_FFT, PF_THIRD_EMPTY, PF_THIRD_CHEB = 0, 1, 2
 PF_PENCIL_X, PF_PENCIL_Y, PF_PENCIL_Z = 0, 1, 2
 PF_DIR_FORWARD, PF_DIR_BACKWARD = 0, 1
 PF_BATCH_SERIAL, PF_BATCH_FUSED, PF_BATCH_GRAPH = 0, 1, 2
+PF_PROBE_COPY, PF_PROBE_TILES, PF_PROBE_TILES_INPLACE = 0, 1, 2
 
 EXPORTED = (
     "pf_layout_init", "pf_check", "pf_query_dims", "pf_setup", "pf_get_dims", "pf_workspace_bytes",
@@ -44,6 +45,7 @@ EXPORTED = (
     "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
     "pf_batch_setup", "pf_batch_offset", "pf_batch_bytes", "pf_batch_set_mode", "pf_batch_ftran_r2c",
     "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step", "pf_exec_noalloc", "pf_check_status",
+    "pf_probe",
 )
 
 
@@ -109,6 +111,7 @@ def lib():
             "pf_btran_c2r": (i, [vp, vp, vp, vp]),
             "pf_exec_noalloc": (i, [vp, i, vp, vp, vp]),
             "pf_check_status": (i, [vp]),
+            "pf_probe": (i, [i, vp, vp, sz, vp]),
             "pf_destroy": (i, [vp]),
             "pf_strerror": (ctypes.c_char_p, [i]),
             "pf_num_passes": (i, [vp, i]),
@@ -191,6 +194,11 @@ PF_NOALLOC_MAX_BYTES = 256 << 20
 def pf_exec_noalloc(h, direction: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
     """Transform with the library's static device scratch as the workspace (no allocation)."""
     _raise(lib().pf_exec_noalloc(h, direction, in_ptr, out_ptr, stream), "pf_exec_noalloc")
+
+
+def pf_probe(kind: int, dst_ptr: int, src_ptr: int, nbytes: int, stream: int = 0) -> None:
+    """Bandwidth probe kernels (PF_PROBE_*): copies in the transform passes' access shapes."""
+    _raise(lib().pf_probe(kind, dst_ptr, src_ptr, nbytes, stream), "pf_probe")
 
 
 def pf_check_status(h) -> None:

@@ -1164,6 +1164,25 @@ int pf_copy(void *dst, const void *src, size_t bytes, void *stream) {
     return hip_status(pf::launch_copy(src, dst, bytes, (hipStream_t)stream));
 }
 
+int pf_probe(int kind, void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return PF_EINVAL;
+    if (!aligned16(dst) || !aligned16(src) || (bytes & 15u)) return PF_EALIGN;
+    hipStream_t s = (hipStream_t)stream;
+    switch (kind) {
+        case PF_PROBE_COPY:
+            if (dst == src) return PF_EALIAS;
+            return hip_status(pf::launch_copy(src, dst, bytes, s));
+        case PF_PROBE_TILES:
+            if (dst == src) return PF_EALIAS;
+            return hip_status(pf::launch_copy_tiles(src, dst, bytes, s));
+        case PF_PROBE_TILES_INPLACE:
+            if (dst != src) return PF_EALIAS;
+            return hip_status(pf::launch_copy_tiles(src, dst, bytes, s));
+        default:
+            return PF_EINVAL;
+    }
+}
+
 int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjoint, void *stream) {
     if (!p || !in || !spec || !out || (adjoint != 0 && adjoint != 1)) return PF_EINVAL;
     if (p->lay.third != PF_THIRD_CHEB || p->blocked || p->share || p->lay.inplace || p->fused) return PF_EUNSUPPORTED;

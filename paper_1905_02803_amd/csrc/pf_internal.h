@@ -177,6 +177,8 @@ hipError_t launch_fill(const FillArgs &f, hipStream_t s);
 hipError_t launch_box(const BoxArgs &b, hipStream_t s);
 // Plain 16-byte-per-lane device copy (bytes a multiple of 16).
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+// Copy in 128 KB tiles by persistent workgroups (src == dst: in place).
+hipError_t launch_copy_tiles(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // Fused X-Y pass (kernels_p2.hip, k_xy_fused): the X and Y stages of every z
 // plane in one persistent launch.  x / y: the X and Y passes' arguments (the

@@ -165,6 +165,19 @@ def test_null_handles():
     pf.pf_destroy(None)
     assert pf.lib().pf_num_passes(None, 0) == pf.PF_EINVAL
     assert pf.lib().pf_copy(None, None, 16, None) == pf.PF_EINVAL
+    assert pf.lib().pf_check_status(None) == pf.PF_EINVAL
+
+
+def test_probe_arguments_are_checked_before_any_launch():
+    """pf_probe refuses bad arguments on the host (the pointer values below are never dereferenced)."""
+    L = pf.lib()
+    assert L.pf_probe(pf.PF_PROBE_TILES, None, 256, 16, None) == pf.PF_EINVAL
+    assert L.pf_probe(pf.PF_PROBE_TILES, 256, 264, 16, None) == pf.PF_EALIGN      # src not 16-byte aligned
+    assert L.pf_probe(pf.PF_PROBE_TILES, 256, 512, 24, None) == pf.PF_EALIGN      # size not a multiple of 16
+    assert L.pf_probe(pf.PF_PROBE_COPY, 256, 256, 16, None) == pf.PF_EALIAS       # copies need two buffers
+    assert L.pf_probe(pf.PF_PROBE_TILES, 256, 256, 16, None) == pf.PF_EALIAS
+    assert L.pf_probe(pf.PF_PROBE_TILES_INPLACE, 256, 512, 16, None) == pf.PF_EALIAS  # in place needs one
+    assert L.pf_probe(7, 256, 512, 16, None) == pf.PF_EINVAL
 
 
 def test_batch_setup_rejects_bad_arguments_before_touching_the_gpu():

@@ -233,6 +233,24 @@ def test_inplace_buffer_is_checked_before_the_call():
             p_in.ftran_inplace(ok[4:])
 
 
+@pytest.mark.parametrize("nbytes", [16, 4096, (1 << 20) + 48, 3 * 131072 + 16])
+def test_probes_move_the_bytes(nbytes):
+    """The bandwidth probes copy exactly the bytes asked for (partial last tile included); the in-place
+    probe leaves the data as it was; nothing beyond the range is touched."""
+    src = torch.randint(0, 2 ** 31 - 1, (nbytes // 4 + 64,), dtype=torch.int32, device="cuda")
+    for kind in (pf.PF_PROBE_COPY, pf.PF_PROBE_TILES):
+        dst = torch.full_like(src, -1)
+        pf.pf_probe(kind, dst.data_ptr(), src.data_ptr(), nbytes, 0)
+        torch.cuda.synchronize()
+        n = nbytes // 4
+        assert torch.equal(dst[:n], src[:n]), kind
+        assert bool((dst[n:] == -1).all()), kind
+    keep = src.clone()
+    pf.pf_probe(pf.PF_PROBE_TILES_INPLACE, src.data_ptr(), src.data_ptr(), nbytes, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(src, keep)
+
+
 def test_call_errors_are_reported():
     with pf.Plan(16, 8, 4) as plan:
         u = plan.empty_real()
