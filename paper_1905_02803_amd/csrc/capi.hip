@@ -237,7 +237,7 @@ int built_options(int nx, int ny, const pf_layout *l) {
 // 16-column blocks, 16-byte aligned rows), contiguous lines, and unaligned
 // rows (Side::v8).
 void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc,
-                    int tuned_tc = 0) {
+                    int tuned_tc = 0, bool plain_fft = true) {
     if (tuned_tc > 0 && tuned_tc < max_tc) max_tc = tuned_tc;
     d.dir = dir;
     d.prec = p->lay.precision;
@@ -254,6 +254,17 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
         a.wpc_log2 = ilog2(fs.n / 16);
         d.threads = (unsigned)pf::p2_threads(fs.n);
         d.lds = pf::p2_lds_bytes(fs.n, a.math);
+        return;
+    }
+    if (!p->opt.generic_only && p->lay.precision == PF_F64 && plain_fft && pf::p2d_supported(fs.n) &&
+        p->B <= max_tc) {
+        // FP64 compile-time radix plan: 8 columns (one 128-byte row) per tile, persistent blocks
+        d.kind = pf::PASS_C2C_P2;
+        a.math = 0;
+        a.tc_log2 = ilog2(p->B);
+        a.wpc_log2 = ilog2(fs.n / 16);
+        d.threads = (unsigned)pf::p2d_threads(fs.n);
+        d.lds = pf::p2d_lds_bytes(fs.n);
         return;
     }
     d.kind = pf::PASS_C2C;
@@ -324,7 +335,7 @@ Side user_side(const pf_plan *p, long long CB) {
     // [nz][ny][nxh] rows of nxh modes: neither 16-byte aligned nor whole column
     // pairs in general, so the power-of-two kernel reads / writes them one column
     // (8 or 16 bytes) at a time
-    s.v8 = p->lay.stride1 ? 0 : 1;
+    s.v8 = p->lay.stride1 || p->csize == 16 ? 0 : 1;
     return s;
 }
 
@@ -627,7 +638,7 @@ void build_passes(pf_plan *p) {
         FftSpec fz = p->fz;
         if (empty) fz.nstages = 0;
         const bool cheb = p->lay.third == PF_THIRD_CHEB;  // type-I DCT by the even extension
-        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2]);
+        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], !empty && !cheb);
         if (cheb) z.a.cheb = p->nz;
         if (cheb && z.kind == pf::PASS_C2C_P2) z.a.math = 4;  // mirrored loads, the first nz points stored
         if (empty && z.kind == pf::PASS_C2C_P2) z.a.math = 3;  // the power-of-two kernel's reorder-only form
@@ -667,7 +678,7 @@ void build_passes(pf_plan *p) {
         }
         p->npass[dir] = 3;
         if (p->blocked) add_remaps(p, dir);
-        if (dir == 0 && cheb && z.kind == pf::PASS_C2C_P2 && !p->blocked && !p->share) {
+        if (dir == 0 && cheb && z.kind == pf::PASS_C2C_P2 && p->lay.precision == PF_F32 && !p->blocked && !p->share) {
             // fused spectral step: the forward Z pass's tiles, W on both sides
             PassDesc f = z;
             f.a.in_s = f.a.out_s = wsz;
@@ -973,8 +984,10 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     int dev = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    for (int n : {ny, p->fz.n})
+    for (int n : {ny, p->fz.n}) {
         if (e == hipSuccess && pf::p2_supported(n, l->precision)) e = pf::p2_prepare(n);
+        if (e == hipSuccess && l->precision == PF_F64 && !o.generic_only && pf::p2d_supported(n)) e = pf::p2d_prepare(n);
+    }
     const bool cheb_p2 = l->third == PF_THIRD_CHEB && !o.generic_only && pf::p2_supported(p->fz.n, l->precision);
     if (e == hipSuccess && cheb_p2) e = pf::p2_spec_prepare(p->fz.n);
     if (e == hipSuccess && p->fast_x) e = pf::p2x_prepare(nx);

@@ -116,6 +116,26 @@ __device__ __forceinline__ float2 gld(const float2 *p) {
     }
 }
 
+typedef double pf_d2 __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ void gst_d(double2 *p, double2 v) {
+    if constexpr (NT) {
+        const pf_d2 u = {v.x, v.y};
+        __builtin_nontemporal_store(u, reinterpret_cast<pf_d2 *>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ double2 gld_d(const double2 *p) {
+    if constexpr (NT) {
+        const pf_d2 u = __builtin_nontemporal_load(reinterpret_cast<const pf_d2 *>(p));
+        return make_double2(u.x, u.y);
+    } else {
+        return *p;
+    }
+}
+
 extern __shared__ __align__(16) unsigned char pf_smem[];
 
 __host__ __device__ constexpr int p2_stages(int N) { return N <= 256 ? 2 : 3; }
@@ -689,6 +709,137 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_c2c_p2(PassArgs a) {
                     if (!CH || q_out + T * m < nsrc)
                         gst<streamed<INP == 1 ? ST_C2C_ROWS_INP : ST_C2C_ROWS>()>(
                             reinterpret_cast<float4 *>(out + b + m * out_step), pack2(v0[m], v1[m]));
+            }
+        }
+        __syncthreads();  // the next tile's stage 0 overwrites the LDS tile
+    }
+}
+
+// ---- FP64: the same column-tile pass with one column per thread ------------
+// A 128-byte workspace row holds 8 complex doubles, so an FP64 tile is 8
+// columns; each thread owns one column (16-byte accesses) and the 16 points
+// q + (N/16) m of it in every stage, as the FP32 kernel owns a column pair.
+// The LDS slot map is the FP32 kernel's with the column in place of the pair
+// (16-byte slots, 8 per row).  Rows (INP / OUTP 0) and lines (1); FP64 rows
+// are always 16-byte aligned.
+template <int N, int R, int NS, int DIR>
+__device__ __forceinline__ void p2_butterflies1(cx<double> (&v)[16], int q, const cx<double> *tws) {
+    constexpr int T = N / 16;
+    constexpr int BPT = 16 / R;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int j = q + i * T;
+        const int k = j & (NS - 1);
+        cx<double> w[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[r] = v[i + r * BPT];
+        if (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<double> t = tws[k * (R - 1) + r - 1];
+                if (DIR > 0) t.y = -t.y;
+                w[r] = cmul(w[r], t);
+            }
+        }
+        Dft<double, R, DIR>::run(w);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i + r * BPT] = w[r];
+    }
+}
+
+template <int N, int DIR, int INP, int OUTP>
+__global__ __launch_bounds__(N / 16 * 8) void k_c2c_p2d(PassArgs a) {
+    constexpr int TC = 8;
+    constexpr int T = N / 16;
+    constexpr int NT = T * TC;
+    constexpr int S = p2_stages(N);
+    constexpr int RL = p2_radix(N, S - 1);
+    constexpr int NSL = p2_ns(N, S - 1);
+    typedef cx<double> cd;
+    cd *buf = reinterpret_cast<cd *>(pf_smem);  // N x 8 slots of 16 bytes
+    cd *twl = buf + N * TC;
+    const int tid = threadIdx.x;
+    const cd *__restrict__ tw = reinterpret_cast<const cd *>(a.tw);
+    for (int i = tid; i < N - 1; i += NT) twl[i] = tw[i];
+    const cd *__restrict__ in = reinterpret_cast<const cd *>(a.in);
+    cd *__restrict__ out = reinterpret_cast<cd *>(a.out);
+    const int CB = (int)a.CB, A = (int)a.A;
+    const int ntiles = (int)(a.A * a.CB);
+    const long long in_step = a.in_s.sp * T;
+    const long long out_step = a.out_s.sp * T;
+    // slot of (point p, column c): the FP32 map with 8 slots per row
+    auto slot = [](int p, int c) { return p2_slot<16>(p, c); };
+    // element (column c, point q) of tile t on a side, and the valid column count
+    auto side_addr = [&](const Side &sd, int t, int c, int q, int &ncol) -> long long {
+        const int ta = a.tile_order ? t % A : t / CB;
+        const int cb = a.tile_order ? t / A : t - ta * CB;
+        ncol = min(TC, a.C - cb * TC);
+        return (long long)ta * sd.sa + (long long)(cb / sd.cpb) * sd.sblk + (long long)(cb % sd.cpb) * TC * sd.sc +
+               (long long)c * sd.sc + (long long)q * sd.sp;
+    };
+    auto load = [&](cd(&d)[16], int t) {
+        const int tv = opaque_tid();
+        const int c = INP == 1 ? tv / T : tv % TC;
+        const int q = INP == 1 ? tv % T : tv / TC;
+        int ncol;
+        const long long b = side_addr(a.in_s, t, c, q, ncol);
+        if (c < ncol) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const double2 *src = reinterpret_cast<const double2 *>(in + b + m * in_step);
+                d[m] = INP == 1 ? *src : gld_d<streamed<LD_C2C_ROWS>()>(src);
+            }
+        }
+    };
+
+    int t = blockIdx.x;
+    cd p[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) p[m] = make_double2(0.0, 0.0);
+    if (t < ntiles) load(p, xcd_tile(t, ntiles, a.xcd));
+    __syncthreads();  // twiddle table in LDS
+    for (; t < ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        const int c_in = INP == 1 ? tv / T : tv % TC;
+        const int q_in = INP == 1 ? tv % T : tv / TC;
+        const int c_mid = tv % TC, q_mid = tv / TC;
+        const int c_out = OUTP == 1 ? tv / T : tv % TC;
+        const int q_out = OUTP == 1 ? tv % T : tv / TC;
+        cd v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = p[m];
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(p, xcd_tile(tn, ntiles, a.xcd));
+        // stage 0: radix 16 on x[q + T r], outputs to points 16 q + r
+        Dft<double, 16, DIR>::run(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[slot(q_in * 16 + r, c_in)] = v[r];
+        __syncthreads();
+        if constexpr (S == 3) {  // stage 1: radix 16, NS = 16
+#pragma unroll
+            for (int m = 0; m < 16; ++m) v[m] = buf[slot(q_mid + T * m, c_mid)];
+            __syncthreads();
+            p2_butterflies1<N, 16, 16, DIR>(v, q_mid, twl + p2_twoff(N, 1));
+            const int k = q_mid & 15;
+            const int base = (q_mid - k) * 16 + k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[slot(base + r * 16, c_mid)] = v[r];
+            __syncthreads();
+        }
+        // last stage: outputs land on points q + T m of the thread's column
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = buf[slot(q_out + T * m, c_out)];
+        p2_butterflies1<N, RL, NSL, DIR>(v, q_out, twl + p2_twoff(N, S - 1));
+        {
+            int ncol;
+            const long long b = side_addr(a.out_s, xcd_tile(t, ntiles, a.xcd), c_out, q_out, ncol);
+            if (c_out < ncol) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    double2 *dst = reinterpret_cast<double2 *>(out + b + m * out_step);
+                    if constexpr (OUTP == 1) gst_d<streamed<ST_C2C_POINTS>()>(dst, v[m]);
+                    else gst_d<streamed<INP == 1 ? ST_C2C_ROWS_INP : ST_C2C_ROWS>()>(dst, v[m]);
+                }
             }
         }
         __syncthreads();  // the next tile's stage 0 overwrites the LDS tile
@@ -1722,6 +1873,38 @@ bool p2_supported(int n, int prec) {
     return prec == 0 && (n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096);
 }
 
+bool p2d_supported(int n) { return n == 256 || n == 512 || n == 1024; }
+size_t p2d_lds_bytes(int n) { return (size_t)n * 8 * 16 + (size_t)n * 16; }
+int p2d_threads(int n) { return n / 16 * 8; }
+
+template <int N, int DIR>
+static const void *p2d_pick_dir(int inp, int outp) {
+    if (inp == 0 && outp == 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 0, 0>);
+    if (inp == 0 && outp == 1) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 0, 1>);
+    if (inp == 1 && outp == 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 1, 0>);
+    return nullptr;
+}
+
+static const void *p2d_pick(int n, int dir, int inp, int outp) {
+    switch (n) {
+        case 256: return dir < 0 ? p2d_pick_dir<256, -1>(inp, outp) : p2d_pick_dir<256, 1>(inp, outp);
+        case 512: return dir < 0 ? p2d_pick_dir<512, -1>(inp, outp) : p2d_pick_dir<512, 1>(inp, outp);
+        case 1024: return dir < 0 ? p2d_pick_dir<1024, -1>(inp, outp) : p2d_pick_dir<1024, 1>(inp, outp);
+        default: return nullptr;
+    }
+}
+
+hipError_t p2d_prepare(int n) {
+    for (int dir : {-1, 1})
+        for (int io = 0; io < 3; ++io) {
+            const void *k = p2d_pick(n, dir, io == 2 ? 1 : 0, io == 1 ? 1 : 0);
+            if (!k) return hipErrorInvalidValue;
+            const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2d_lds_bytes(n));
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
 template <int N, int TC, int DIR, int INP, int OUTP, int MT>
 static const void *p2_kernel() {
     return reinterpret_cast<const void *>(&k_c2c_p2<N, TC, DIR, INP, OUTP, MT>);
@@ -1778,6 +1961,7 @@ static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
 }
 
 const void *p2_symbol(const PassDesc &d) {
+    if (d.kind == PASS_C2C_P2 && d.prec == 1) return p2d_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
     if (d.kind == PASS_R2C_P2) return p2x_pick(2 * d.a.fft.n, 1, d.a.math);
     if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0, d.a.math);
     return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);

@@ -203,6 +203,13 @@ const void *p2_fused_symbol(int nx, int ny, int fwd);
 hipError_t p2_xcd_queues(unsigned blocks, int *nq);
 hipError_t p2_fused_launch(const FusedArgs &f, int fwd, int nx, int ny, unsigned blocks, hipStream_t s);
 
+// Power-of-two FP64 C2C pass (kernels_p2.hip, k_c2c_p2d): plain FFT along Y or
+// Z, 8 columns per tile, n = 256, 512, 1024; launched by p2_launch.
+bool p2d_supported(int n);
+size_t p2d_lds_bytes(int n);
+int p2d_threads(int n);
+hipError_t p2d_prepare(int n);
+
 // Power-of-two FP32 C2C pass (kernels_p2.hip).
 bool p2_supported(int n, int prec);
 bool p2_has_mfma(int n);  // a matrix-core variant of the length-n pass exists
