@@ -85,7 +85,8 @@ def traffic_from_profile(pass_name: str, n: int):
 def section_starts(names):
     """Dispatch indices where the benchmark's sections start, from the kernel names in launch order:
     the batch (first generic-kernel launch), the spectral step (its first k_r2c_p2<256, ...>), the
-    share-only leg (its first fill) and the other grids (the next k_r2c_p2<256, ...>)."""
+    share-only leg (its first fill), the FP64 512^3 plan (its first FP64 kernel) and the other grids
+    (the next k_r2c_p2<256, ...>)."""
 
     def first(pred, start=0):
         return next((i for i in range(start, len(names)) if pred(names[i])), len(names))
@@ -95,7 +96,9 @@ def section_starts(names):
     s0 = first(lambda k: "k_r2c_p2<256" in k, b0)
     h0 = first(lambda k: "k_fill" in k, s0)
     o0 = first(lambda k: "k_r2c_p2<256" in k, h0)
-    return b0, s0, h0, o0
+    # the FP64 512^3 plan runs between the share-only leg and the other grids
+    f0 = first(lambda k: "k_c2c_p2d" in k or "<double" in k, h0)
+    return b0, s0, h0, min(f0, o0), o0
 
 
 def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> None:
@@ -111,7 +114,7 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
 
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-    b0, s0, h0, o0 = section_starts([r["Kernel_Name"] for r in rows])
+    b0, s0, h0, f0, o0 = section_starts([r["Kernel_Name"] for r in rows])
 
     def table(rs):
         d = {}
@@ -140,7 +143,11 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
             *table(rows[:b0]), "",
             "share-only leg: rank (0, 3) of a 1 x 8 grid, X-pencil [128][1024][1024] -> Z-pencil [513][128][1024],",
             f"{pairs} pairs (the same transform kernels on the rank's share, plus fills and block copies)",
-            *table(rows[h0:o0])],
+            *table(rows[h0:f0])],
+        "kernels_fft_512cubed_f64.txt": [
+            "rocprofv3 kernel-trace statistics, FP64 R2C+C2R at 512^3, STRIDE1, out-of-place", *head,
+            f"{pairs} pairs (k_c2c_p2d: the FP64 power-of-two Y / Z kernel; k_r2c_x / k_c2r_x <double>: the X "
+            "passes), then one forward for the oracle comparison", *table(rows[f0:o0])],
         "kernels_fft_512cubed_480x360x250.txt": [
             "rocprofv3 kernel-trace statistics, FP32 R2C+C2R at 512^3 (power-of-two kernels) and "
             "480 x 360 x 250 (mixed-radix kernels), STRIDE1, out-of-place", *head,
@@ -194,7 +201,7 @@ def summarize_sq(counter_csv: str, command: str) -> None:
             "scratch": r.get("Scratch_Size", ""), "c": {}})
         d["c"][r["Counter_Name"]] = float(r["Counter_Value"])
     ds = [disp[k] for k in sorted(disp)]
-    b0, s0, h0, o0 = section_starts([d["name"] for d in ds])
+    b0, s0, h0, f0, o0 = section_starts([d["name"] for d in ds])
 
     def modes(nx, ny, nz):
         return (nx // 2 + 1) * ny * nz
@@ -207,6 +214,7 @@ def summarize_sq(counter_csv: str, command: str) -> None:
          "dispatch)", ds[b0:s0], lambda k: None),
         ("Chebyshev spectral step on 512 x 512 x 257 (M = 257 x 512 x 257)", ds[s0:h0],
          lambda k: modes(512, 512, 257)),
+        ("FP64 512^3 (M = 257 x 512 x 512)", ds[f0:o0], lambda k: m512),
         ("other grids: 512^3 on the power-of-two kernels (M = 257 x 512 x 512), 480 x 360 x 250 on the "
          "mixed-radix kernels <float> (M = 241 x 360 x 250)", ds[o0:],
          lambda k: modes(480, 360, 250) if "<float" in k else m512),
@@ -484,6 +492,61 @@ def fused_timing(pf, nx, ny, nz, args, dev, stream, u, plain_passes):
                 e["three_pass_GBps"] = sep / (avg * 1e-3) / 1e9
             out["passes"].append(e)
     plan.set_timing(False)
+    plan.destroy()
+    return out
+
+
+def f64_timing(pf, args, dev, stream, n=512, check=True):
+    """FP64 R2C+C2R at n^3 (uniform[-1, 1] data, STRIDE1, out-of-place; the paper's runs are double
+    precision): ms per pair, GFLOP/s, per-pass algorithmic GB/s and fraction of 8 TB/s, and the forward
+    relative L2 error against the FP64 oracle."""
+    import torch
+
+    plan = pf.Plan(n, n, n, pf.Layout(precision=pf.PF_F64))
+    g = torch.Generator(device=dev)
+    g.manual_seed(64)
+    u = torch.empty((n, n, n), device=dev, dtype=torch.float64).uniform_(-1.0, 1.0, generator=g)
+    U = plan.empty_complex(dev)
+    r = plan.empty_real(dev)
+    for _ in range(args.warmup):
+        plan.ftran(u, U)
+        plan.btran(U, r)
+    plan.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.ftran(u, U)
+        plan.btran(U, r)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    N = float(n) ** 3
+    passes, nbytes = [], 0.0
+    for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD):
+        for i in range(plan.num_passes(d)):
+            tot, cnt = plan.get_timing(d, i)
+            avg = tot / max(cnt, 1)
+            b = plan.pass_bytes(d, i)
+            nbytes += b
+            gbs = b / (avg * 1e-3) / 1e9
+            passes.append({"pass": plan.pass_name(d, i), "avg_ms": avg, "alg_GBps": gbs,
+                           "frac_of_peak": gbs / HBM_PEAK_GBS})
+    plan.set_timing(False)
+    out = {"grid": [n, n, n], "precision": "f64", "ms_per_pair": ms,
+           "gflops": 5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, "alg_GBps": nbytes / (ms * 1e-3) / 1e9,
+           "frac_of_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "passes": passes}
+    rt = (torch.linalg.vector_norm(r / N - u) / torch.linalg.vector_norm(u)).item()
+    out["round_trip_rel_l2"] = rt
+    if check:
+        import oracle
+
+        plan.ftran(u, U)
+        torch.cuda.synchronize()
+        ref = oracle.to_stride1(oracle.r2c3d(u.cpu().numpy()))
+        got = U.cpu().numpy()
+        out["rel_l2_fwd_vs_fp64_oracle"] = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
     plan.destroy()
     return out
 
@@ -825,6 +888,7 @@ def main():
     batched = batch_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
     spectral = spectral_timing(pf, args, dev, stream)
     share = share_only_timing(pf, nx, ny, nz, args, dev, stream)
+    f64 = f64_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
     other_grids = other_grid_timings(pf, args, dev, stream)  # last: the trace summary splits on its first launch
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
@@ -878,6 +942,7 @@ def main():
         "share_only": share,
         "layouts": layouts,
         "other_grids": other_grids,
+        "f64_512cubed": f64,
         "batched": batched,
         "spectral_step": spectral,
         "cpu_baseline": cpu,
