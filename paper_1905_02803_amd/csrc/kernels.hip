@@ -169,7 +169,11 @@ __device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp
             constexpr int EM = Stage<T>::value;
             const long long step = (long long)dp * sp;
             for (int p1 = p0; p1 < n; p1 += EM * dp) {
+                // zeroed first: with only the in-range entries written the compiler
+                // kept the FP64 array in scratch memory
                 cx<T> r[EM];
+#pragma unroll
+                for (int i = 0; i < EM; ++i) r[i] = cmk<T>(T(0), T(0));
                 const cx<T> *q = base + (long long)p1 * sp;
 #pragma unroll
                 for (int i = 0; i < EM; ++i) {
@@ -202,6 +206,8 @@ __device__ __forceinline__ void c2c_tile_body(const PassArgs &a, const void *inp
             constexpr int EM = Stage<T>::value;
             for (int p1 = p0; p1 < nout; p1 += EM * dp, q += EM * step) {
                 cx<T> r[EM];
+#pragma unroll
+                for (int i = 0; i < EM; ++i) r[i] = cmk<T>(T(0), T(0));
 #pragma unroll
                 for (int i = 0; i < EM; ++i) {
                     const int p = p1 + i * dp;
