@@ -726,14 +726,17 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) 
 }
 
 // The transform passes' access shape without the transform: persistent
-// workgroups of 512 threads move 128 KB tiles (16 loads of 16 bytes per
-// thread), tile t, t + gridDim.x, ...; the next tile's loads are in flight
-// while the current one is stored; nontemporal loads and stores.  src == dst
-// reads and writes back each tile in place (the Y pass's pattern).
-__global__ __launch_bounds__(512) void k_copy_tiles(const float4 *src, float4 *dst, size_t n) {
+// workgroups (one per CU) of 1024 threads move 128 KB tiles (8 loads of 16
+// bytes per thread), tile t, t + gridDim.x, ...; the next tile's loads are in
+// flight while the current one is stored; nontemporal loads and stores.
+// src == dst reads and writes back each tile in place (the Y pass's pattern).
+// Of the shapes measured (256 .. 1024 threads, 4 .. 32 loads per thread, with
+// and without prefetch or hints, 1 .. 8 workgroups per CU) this one was the
+// fastest.
+__global__ __launch_bounds__(1024) void k_copy_tiles(const float4 *src, float4 *dst, size_t n) {
     typedef float f4v __attribute__((ext_vector_type(4)));
-    constexpr int U = 16;
-    const size_t tile = (size_t)512 * U;  // 16-byte words per tile
+    constexpr int U = 8, TPB = 1024;
+    const size_t tile = (size_t)TPB * U;  // 16-byte words per tile
     const size_t ntiles = (n + tile - 1) / tile;
     const f4v *s = reinterpret_cast<const f4v *>(src);
     f4v *d = reinterpret_cast<f4v *>(dst);
@@ -741,7 +744,7 @@ __global__ __launch_bounds__(512) void k_copy_tiles(const float4 *src, float4 *d
     auto load = [&](f4v(&v)[U], size_t t) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const size_t i = t * tile + (size_t)u * 512 + threadIdx.x;
+            const size_t i = t * tile + (size_t)u * TPB + threadIdx.x;
             if (i < n) v[u] = __builtin_nontemporal_load(s + i);
         }
     };
@@ -753,7 +756,7 @@ __global__ __launch_bounds__(512) void k_copy_tiles(const float4 *src, float4 *d
         if (t + gridDim.x < ntiles) load(nxt, t + gridDim.x);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const size_t i = t * tile + (size_t)u * 512 + threadIdx.x;
+            const size_t i = t * tile + (size_t)u * TPB + threadIdx.x;
             if (i < n) __builtin_nontemporal_store(cur[u], d + i);
         }
     }
@@ -762,16 +765,13 @@ __global__ __launch_bounds__(512) void k_copy_tiles(const float4 *src, float4 *d
 hipError_t launch_copy_tiles(const void *src, void *dst, size_t bytes, hipStream_t s) {
     const size_t n = bytes / 16;
     if (n == 0) return hipSuccess;
-    int dev = 0, ncu = 0, nb = 0;
+    int dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_copy_tiles), 512, 0);
     if (e != hipSuccess) return e;
-    const size_t tiles = (n + 512 * 16 - 1) / (512 * 16);
-    const size_t resident = (size_t)ncu * (nb > 0 ? nb : 1);
-    const unsigned blocks = (unsigned)(tiles < resident ? tiles : resident);
-    hipLaunchKernelGGL(k_copy_tiles, dim3(blocks), dim3(512), 0, s, reinterpret_cast<const float4 *>(src),
+    const size_t tiles = (n + 1024 * 8 - 1) / (1024 * 8);
+    const unsigned blocks = (unsigned)(tiles < (size_t)ncu ? tiles : (size_t)ncu);
+    hipLaunchKernelGGL(k_copy_tiles, dim3(blocks), dim3(1024), 0, s, reinterpret_cast<const float4 *>(src),
                        reinterpret_cast<float4 *>(dst), n);
     return hipGetLastError();
 }
