@@ -295,6 +295,18 @@ int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *
 const char *pf_pass_name(const pf_plan *p, int dir, int pass);
 
 /*
+ * Kernel family that runs pass `pass` of direction `dir` (a short static
+ * string, "" for an invalid plan / dir / pass): "c2c_generic", "r2c_generic",
+ * "c2r_generic" (radix plan read at run time, Sec. 2's 1D transforms as a
+ * stage loop); "c2c_pow2", "r2c_pow2", "c2r_pow2" (power-of-two lengths, radix
+ * plan fixed at compile time, persistent workgroups); "c2c_mixed",
+ * "r2c_mixed", "c2r_mixed" (7-smooth lengths with a compile-time two-step
+ * plan, FP32); "xy_fused" (fused_xy); "remap", "fill", "box" (reorders of
+ * the processor-grid and share-only plans).  Introspection only.
+ */
+const char *pf_pass_kernel(const pf_plan *p, int dir, int pass);
+
+/*
  * Algorithmic HBM bytes of one pass: every element read once and written once
  * (real side N * s, complex side nx/2+1 modes * ny * nz * 2s).
  */

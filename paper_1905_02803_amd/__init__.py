@@ -45,7 +45,7 @@ EXPORTED = (
     "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
     "pf_batch_setup", "pf_batch_offset", "pf_batch_bytes", "pf_batch_set_mode", "pf_batch_ftran_r2c",
     "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step", "pf_exec_noalloc", "pf_check_status",
-    "pf_probe",
+    "pf_probe", "pf_pass_kernel",
 )
 
 
@@ -117,6 +117,7 @@ def lib():
             "pf_num_passes": (i, [vp, i]),
             "pf_run_pass": (i, [vp, i, i, vp, vp, vp]),
             "pf_pass_name": (ctypes.c_char_p, [vp, i, i]),
+            "pf_pass_kernel": (ctypes.c_char_p, [vp, i, i]),
             "pf_pass_bytes": (ctypes.c_double, [vp, i, i]),
             "pf_set_timing": (i, [vp, i]),
             "pf_copy": (i, [vp, vp, sz, vp]),
@@ -224,6 +225,10 @@ def pf_num_passes(h, direction: int) -> int:
 
 def pf_pass_name(h, direction: int, pass_index: int) -> str:
     return lib().pf_pass_name(h, direction, pass_index).decode()
+
+
+def pf_pass_kernel(h, direction: int, pass_index: int) -> str:
+    return lib().pf_pass_kernel(h, direction, pass_index).decode()
 
 
 def pf_pass_bytes(h, direction: int, pass_index: int) -> float:
@@ -385,6 +390,9 @@ class Plan:
 
     def pass_name(self, direction: int, index: int) -> str:
         return pf_pass_name(self.handle, direction, index)
+
+    def pass_kernel(self, direction: int, index: int) -> str:
+        return pf_pass_kernel(self.handle, direction, index)
 
     def pass_bytes(self, direction: int, index: int) -> float:
         return pf_pass_bytes(self.handle, direction, index)

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpencilfft.so")
-SOURCES = ["capi.hip", "kernels.hip", "kernels_p2.hip"]
+SOURCES = ["capi.hip", "kernels.hip", "kernels_p2.hip", "kernels_mr.hip",
+           "kernels_mr_p0.hip", "kernels_mr_p1.hip", "kernels_mr_p2.hip", "kernels_mr_p3.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -40,6 +40,7 @@ struct PassTiming {
 // tile, else at most `tile` line pairs (x) or columns (y, z) per tile.
 struct PlanOpts {
     bool generic_only = false;
+    bool no_mr = false;  // keep the runtime-radix kernels where a compile-time mixed-radix one exists
     bool external_ws = false;
     int radix_order[3] = {0, 0, 0};
     int tile[3] = {0, 0, 0};
@@ -57,6 +58,10 @@ struct pf_plan {
     FftSpec fx, fy, fz;
     void *tw_dev;  // one allocation holding the x, y, z tables (+ the half-length X table)
     size_t tw_off[4];
+    // x, y, z: a compile-time mixed-radix kernel serves the axis (FP32), and the
+    // offset of its table W_n^m, m < n, in tw_dev
+    bool mr[3];
+    size_t tw_mr[3];
     FftSpec fxh;   // nx / 2 plan of the even power-of-two X stage
     bool fast_x;
     void *ws;          // the workspace: W, then (m1 m2 > 1) the global-array buffer
@@ -237,7 +242,7 @@ int built_options(int nx, int ny, const pf_layout *l) {
 // 16-column blocks, 16-byte aligned rows), contiguous lines, and unaligned
 // rows (Side::v8).
 void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t twoff, int dir, int max_tc,
-                    int tuned_tc = 0, bool plain_fft = true) {
+                    int tuned_tc = 0, bool plain_fft = true, int axis = -1) {
     if (tuned_tc > 0 && tuned_tc < max_tc) max_tc = tuned_tc;
     d.dir = dir;
     d.prec = p->lay.precision;
@@ -265,6 +270,16 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
         a.wpc_log2 = ilog2(fs.n / 16);
         d.threads = (unsigned)pf::p2d_threads(fs.n);
         d.lds = pf::p2d_lds_bytes(fs.n);
+        return;
+    }
+    if (axis >= 0 && p->mr[axis] && plain_fft && max_tc >= 16) {
+        // compile-time mixed-radix plan: 16 columns per tile, one tile per workgroup
+        d.kind = pf::PASS_C2C_MR;
+        a.tw = (const char *)p->tw_dev + p->tw_mr[axis];
+        a.tc_log2 = 4;
+        a.wpc_log2 = 0;
+        d.threads = (unsigned)pf::mr_threads_of(fs.n);
+        d.lds = pf::mr_lds_bytes(fs.n, 0);
         return;
     }
     d.kind = pf::PASS_C2C;
@@ -611,6 +626,15 @@ void build_passes(pf_plan *p) {
         const long long pairs = (x.a.lines + 1) / 2;
         const long long tcx = 1LL << x.a.tc_log2;
         x.blocks = (unsigned)((pairs + tcx - 1) / tcx);
+        if (p->mr[0] && xmax >= 16) {  // compile-time mixed-radix plan, 16 line pairs per tile
+            x.kind = dir == 0 ? pf::PASS_R2C_MR : pf::PASS_C2R_MR;
+            x.a.tw = (const char *)p->tw_dev + p->tw_mr[0];
+            x.a.tc_log2 = 4;
+            x.a.wpc_log2 = 0;
+            x.threads = (unsigned)pf::mr_threads_of(p->nx);
+            x.lds = pf::mr_lds_bytes(p->nx, 1);
+            x.blocks = (unsigned)((pairs + 15) / 16);
+        }
         if (p->fast_x) {  // half-length complex transform, 16 lines per tile, persistent blocks
             x.kind = dir == 0 ? pf::PASS_R2C_P2 : pf::PASS_C2R_P2;
             x.a.fft = p->fxh;
@@ -624,7 +648,7 @@ void build_passes(pf_plan *p) {
         }
         // Y stage: in place on the workspace, tile (z, column block)
         PassDesc y;
-        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B, p->opt.tile[1]);
+        set_c2c_common(y, p, p->fy, p->tw_off[1], sgn, p->B, p->opt.tile[1], true, 1);
         y.a.in_s = ws_side(p, zstride, p->B, y.a.tc_log2);
         y.a.out_s = y.a.in_s;
         y.a.A = p->nz;
@@ -638,7 +662,7 @@ void build_passes(pf_plan *p) {
         FftSpec fz = p->fz;
         if (empty) fz.nstages = 0;
         const bool cheb = p->lay.third == PF_THIRD_CHEB;  // type-I DCT by the even extension
-        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], !empty && !cheb);
+        set_c2c_common(z, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], !empty && !cheb, 2);
         if (cheb) z.a.cheb = p->nz;
         if (cheb && z.kind == pf::PASS_C2C_P2) z.a.math = 4;  // mirrored loads, the first nz points stored
         if (empty && z.kind == pf::PASS_C2C_P2) z.a.math = 3;  // the power-of-two kernel's reorder-only form
@@ -974,6 +998,26 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
         host.insert(host.end(), b, b + t.size() * sizeof(float));
         host.resize((host.size() + 255) & ~(size_t)255, 0);
     }
+    // mixed-radix tables W_n^m, m < n (FP32 plain transforms; the Chebyshev and
+    // empty third transforms keep the runtime-radix kernel)
+    const int axis_n[3] = {nx, ny, nz};
+    for (int i = 0; i < 3; ++i) {
+        p->mr[i] = !o.no_mr && pf::mr_supported(axis_n[i], l->precision) && !(i == 0 && p->fast_x) &&
+                   !(i == 2 && l->third != PF_THIRD_FFT);
+        p->tw_mr[i] = 0;
+        if (!p->mr[i]) continue;
+        p->tw_mr[i] = host.size();
+        std::vector<float> t(2 * (size_t)axis_n[i]);
+        const double two_pi = 6.283185307179586476925286766559;
+        for (int m = 0; m < axis_n[i]; ++m) {
+            const double ang = two_pi * (double)m / (double)axis_n[i];
+            t[2 * (size_t)m] = (float)std::cos(ang);
+            t[2 * (size_t)m + 1] = (float)(-std::sin(ang));
+        }
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
+        host.insert(host.end(), b, b + t.size() * sizeof(float));
+        host.resize((host.size() + 255) & ~(size_t)255, 0);
+    }
     hipError_t e = hipMalloc(&p->tw_dev, host.size());
     if (e != hipSuccess) {
         delete p;
@@ -1164,6 +1208,26 @@ int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *
 const char *pf_pass_name(const pf_plan *p, int dir, int pass) {
     if (!p || dir < 0 || dir > 1 || pass < 0 || pass >= p->npass[dir]) return "";
     return p->pass_names[dir][pass];
+}
+
+const char *pf_pass_kernel(const pf_plan *p, int dir, int pass) {
+    if (!p || dir < 0 || dir > 1 || pass < 0 || pass >= p->npass[dir]) return "";
+    switch (p->pass[dir][pass].kind) {
+        case pf::PASS_C2C: return "c2c_generic";
+        case pf::PASS_R2C_X: return "r2c_generic";
+        case pf::PASS_C2R_X: return "c2r_generic";
+        case pf::PASS_C2C_P2: return "c2c_pow2";
+        case pf::PASS_R2C_P2: return "r2c_pow2";
+        case pf::PASS_C2R_P2: return "c2r_pow2";
+        case pf::PASS_C2C_MR: return "c2c_mixed";
+        case pf::PASS_R2C_MR: return "r2c_mixed";
+        case pf::PASS_C2R_MR: return "c2r_mixed";
+        case pf::PASS_FUSED_XY: return "xy_fused";
+        case pf::PASS_REMAP: return "remap";
+        case pf::PASS_FILL: return "fill";
+        case pf::PASS_BOX: return "box";
+    }
+    return "";
 }
 
 double pf_pass_bytes(const pf_plan *p, int dir, int pass) {
@@ -1429,25 +1493,44 @@ int pf_batch_setup(int count, const int *dims, const pf_layout *l, const pf_tune
             // arrays; forward Z writes / backward Z reads the complex arrays
             const bool xpass = (dir == 0 && k == 0) || (dir == 1 && k == 2);
             const int in_user = k == 0, out_user = k == 2;
+            // launch groups: runtime-radix passes by block size; compile-time
+            // mixed-radix passes by length (one kernel per length)
+            auto is_mr = [](pf::PassKind kd) {
+                return kd == pf::PASS_C2C_MR || kd == pf::PASS_R2C_MR || kd == pf::PASS_C2R_MR;
+            };
+            auto mr_len = [&](int i) {
+                const PassDesc &d = b->plans[i]->pass[dir][k];
+                return is_mr(d.kind) ? d.a.fft.n : 0;
+            };
+            auto same_group = [&](int u, int v) {
+                const PassDesc &du = b->plans[u]->pass[dir][k], &dv = b->plans[v]->pass[dir][k];
+                return du.kind == dv.kind && mr_len(u) == mr_len(v) && du.threads == dv.threads;
+            };
             for (int i = 0; i < count; ++i) {
                 order[i] = i;
-                if (b->plans[i]->pass[dir][k].kind != b->plans[0]->pass[dir][k].kind) {
+                const pf::PassKind kd = b->plans[i]->pass[dir][k].kind;
+                if (kd != pf::PASS_C2C && kd != pf::PASS_R2C_X && kd != pf::PASS_C2R_X && !is_mr(kd)) {
                     batch_free(b);
                     return PF_EUNSUPPORTED;
                 }
             }
             std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
-                return b->plans[u]->pass[dir][k].threads > b->plans[v]->pass[dir][k].threads;
+                const PassDesc &du = b->plans[u]->pass[dir][k], &dv = b->plans[v]->pass[dir][k];
+                if (du.kind != dv.kind) return du.kind < dv.kind;
+                if (mr_len(u) != mr_len(v)) return mr_len(u) > mr_len(v);
+                return du.threads > dv.threads;
             });
             int f = 0;  // next free prefix slot
             for (int j = 0; j < count;) {
-                const unsigned thr = b->plans[order[j]]->pass[dir][k].threads;
+                const int lead = order[j];
+                const unsigned thr = b->plans[lead]->pass[dir][k].threads;
                 pf::BatchLaunch L;
                 std::memset(&L, 0, sizeof(L));
                 const PassDesc &d0 = b->plans[order[j]]->pass[dir][k];
                 L.kind = d0.kind;
                 L.dir = d0.dir;
                 L.prec = d0.prec;
+                L.n = mr_len(lead);
                 L.threads = thr;
                 L.b.in_user = in_user;
                 L.b.out_user = out_user;
@@ -1455,7 +1538,7 @@ int pf_batch_setup(int count, const int *dims, const pf_layout *l, const pf_tune
                 L.b.first = Fdev + f;
                 long long blocks = 0;
                 int n = 0;
-                for (; j < count && b->plans[order[j]]->pass[dir][k].threads == thr; ++j, ++n) {
+                for (; j < count && same_group(order[j], lead); ++j, ++n) {
                     const int i = order[j];
                     const PassDesc &d = b->plans[i]->pass[dir][k];
                     A[j] = d.a;

@@ -467,6 +467,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_c2r_x_b(BatchArgs b) {
 
 hipError_t launch_batch(const BatchLaunch &L, hipStream_t s) {
     if (L.blocks == 0) return hipSuccess;
+    if (L.kind == PASS_C2C_MR || L.kind == PASS_R2C_MR || L.kind == PASS_C2R_MR) return mr_launch_batch(L, s);
     if (L.threads == 0 || L.threads > (unsigned)kGenericThreads) return hipErrorInvalidConfiguration;
     const dim3 g(L.blocks), bl(L.threads);
     const bool f64 = L.prec != 0;
@@ -850,6 +851,10 @@ hipError_t launch_pass(const PassDesc &d, hipStream_t s) {
             return launch_fill(d.f, s);
         case PASS_BOX:
             return launch_box(d.b, s);
+        case PASS_C2C_MR:
+        case PASS_R2C_MR:
+        case PASS_C2R_MR:
+            return mr_launch(d, s);
         case PASS_FUSED_XY:  // launched by the planner (p2_fused_launch), which holds its arguments
             return hipErrorInvalidValue;
     }

@@ -44,7 +44,10 @@ enum PassKind {
     PASS_REMAP = 6,
     PASS_FILL = 7,
     PASS_BOX = 8,
-    PASS_FUSED_XY = 9  // launched by the planner from its FusedArgs (p2_fused_launch)
+    PASS_FUSED_XY = 9,  // launched by the planner from its FusedArgs (p2_fused_launch)
+    PASS_C2C_MR = 10,   // compile-time mixed-radix passes (kernels_mr.h), FP32
+    PASS_R2C_MR = 11,
+    PASS_C2R_MR = 12
 };
 
 // Reorder between the global arrays and the concatenated Table 1 pencil
@@ -148,6 +151,7 @@ struct BatchArgs {
 struct BatchLaunch {
     PassKind kind;
     int dir, prec;
+    int n;  // mixed-radix passes: the transform length shared by the launch's transforms
     unsigned blocks, threads;
     size_t lds;
     BatchArgs b;
@@ -202,6 +206,16 @@ const void *p2_fused_symbol(int nx, int ny, int fwd);
 // are numbered 0 .. n-1 (each a work queue of the fused pass), else 0.
 hipError_t p2_xcd_queues(unsigned blocks, int *nq);
 hipError_t p2_fused_launch(const FusedArgs &f, int fwd, int nx, int ny, unsigned blocks, hipStream_t s);
+
+// Compile-time mixed-radix passes, FP32 (kernels_mr.hip): the C2C column pass
+// (PASS_C2C_MR, 16 columns per tile, a.tc_log2 = 4) and the X passes
+// (PASS_R2C_MR / PASS_C2R_MR, 16 line pairs per tile) of a length n the table
+// holds; one tile per workgroup.  a.tw: W_n^m, m < n (forward sign).
+bool mr_supported(int n, int prec);
+int mr_threads_of(int n);
+size_t mr_lds_bytes(int n, int xpass);
+hipError_t mr_launch(const PassDesc &d, hipStream_t s);
+hipError_t mr_launch_batch(const BatchLaunch &L, hipStream_t s);
 
 // Power-of-two FP64 C2C pass (kernels_p2.hip, k_c2c_p2d): plain FFT along Y or
 // Z, 8 columns per tile, n = 256, 512, 1024; launched by p2_launch.

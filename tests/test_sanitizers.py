@@ -71,7 +71,7 @@ def test_host_planner_under_asan_ubsan(tmp_path):
     from paper_1905_02803_amd import build
 
     bdir = os.path.join(build.HERE, "_build")
-    objs = [os.path.join(bdir, n) for n in ("kernels.o", "kernels_p2.o")]
+    objs = [os.path.join(bdir, n.replace(".hip", ".o")) for n in build.SOURCES if n != "capi.hip"]
     if not all(os.path.exists(o) for o in objs):
         build.build()
     inc = ["-I", os.path.join(ROOT, "include"), "-I", build.CSRC]
