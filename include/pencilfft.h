@@ -410,6 +410,7 @@ typedef struct pf_batch pf_batch;
 #define PF_BATCH_SERIAL 0  /* transform after transform, three launches each   */
 #define PF_BATCH_FUSED 1   /* per pass, one launch per block size over all transforms (default) */
 #define PF_BATCH_GRAPH 2   /* flag: replay the direction from a captured hipGraph */
+#define PF_BATCH_STREAMS 4 /* flag: spread independent launches over the batch's own streams */
 
 /*
  * dims: count triples (nx, ny, nz).  l: precision, stride1 and third as for
@@ -435,9 +436,17 @@ size_t pf_batch_bytes(const pf_batch *b, int which);
  * first call of a direction with given buffers captures its launches into a
  * hipGraph (on a stream of the batch's own) and every call replays it on the
  * caller's stream; new buffers or a new mode are captured again (after the
- * caller's stream has drained the old graph).  Returns PF_EINVAL for other
- * values.
+ * caller's stream has drained the old graph).  PF_BATCH_STREAMS (not with
+ * PF_BATCH_GRAPH): the call forks PF_BATCH_NSTREAMS streams of the batch's
+ * own from the caller's stream (an event recorded there), runs independent
+ * work on them -- whole transforms, largest first, each on the least loaded
+ * stream (serial), or the launch groups of one pass (fused; the streams join
+ * between passes) -- and joins them back into the caller's stream, so that
+ * small launches of different transforms overlap.  Work queued on the
+ * caller's stream afterwards sees the results.  Returns PF_EINVAL for values
+ * outside 0 .. 7, PF_EUNSUPPORTED for PF_BATCH_GRAPH | PF_BATCH_STREAMS.
  */
+#define PF_BATCH_NSTREAMS 4
 int pf_batch_set_mode(pf_batch *b, int mode);
 
 /*

@@ -36,7 +36,8 @@ PF_PLAIN, PF_MFMA_FP16X2, PF_MFMA_BF16X2 = 0, 1, 2
 PF_THIRD_FFT, PF_THIRD_EMPTY, PF_THIRD_CHEB = 0, 1, 2
 PF_PENCIL_X, PF_PENCIL_Y, PF_PENCIL_Z = 0, 1, 2
 PF_DIR_FORWARD, PF_DIR_BACKWARD = 0, 1
-PF_BATCH_SERIAL, PF_BATCH_FUSED, PF_BATCH_GRAPH = 0, 1, 2
+PF_BATCH_SERIAL, PF_BATCH_FUSED, PF_BATCH_GRAPH, PF_BATCH_STREAMS = 0, 1, 2, 4
+PF_BATCH_NSTREAMS = 4
 PF_PROBE_COPY, PF_PROBE_TILES, PF_PROBE_TILES_INPLACE = 0, 1, 2
 
 EXPORTED = (

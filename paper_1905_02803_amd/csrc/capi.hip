@@ -1336,6 +1336,13 @@ struct pf_batch {
     std::vector<pf::BatchLaunch> launch[2][3];
     int mode = PF_BATCH_FUSED;
     hipStream_t cap = nullptr;  // capture stream for the graph modes
+    // PF_BATCH_STREAMS: the streams, the fork event (recorded on the caller's
+    // stream) and one join event per stream
+    hipStream_t aux[PF_BATCH_NSTREAMS] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[PF_BATCH_NSTREAMS] = {};
+    std::vector<int> order;  // transforms by decreasing size
+    std::vector<int> home;   // stream of each transform (serial | streams)
     struct Graph {
         const void *in = nullptr;
         void *out = nullptr;
@@ -1353,30 +1360,72 @@ void batch_free(pf_batch *b) {
     for (auto &g : b->graph)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int j = 0; j < PF_BATCH_NSTREAMS; ++j) {
+        if (b->aux[j]) (void)hipStreamDestroy(b->aux[j]);
+        if (b->join_ev[j]) (void)hipEventDestroy(b->join_ev[j]);
+    }
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     for (pf_plan *p : b->plans) pf_destroy(p);
     if (b->tables) (void)hipFree(b->tables);
     if (b->ws) (void)hipFree(b->ws);
     delete b;
 }
 
+// PF_BATCH_STREAMS: the batch's streams wait for what the caller's stream s
+// has queued (fork), and s waits for everything queued on them (join).
+hipError_t batch_fork(pf_batch *b, hipStream_t s) {
+    hipError_t e = hipEventRecord(b->fork_ev, s);
+    for (int j = 0; j < PF_BATCH_NSTREAMS && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->aux[j], b->fork_ev, 0);
+    return e;
+}
+hipError_t batch_join(pf_batch *b, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < PF_BATCH_NSTREAMS && e == hipSuccess; ++j) {
+        e = hipEventRecord(b->join_ev[j], b->aux[j]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join_ev[j], 0);
+    }
+    return e;
+}
+
 // Enqueue one direction of the batch on stream s in the current mode (graphs aside).
 int batch_issue(pf_batch *b, int dir, const void *in, void *out, hipStream_t s) {
+    const bool streams = (b->mode & PF_BATCH_STREAMS) != 0;
     if (b->mode & PF_BATCH_FUSED) {
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k) {
+            if (streams) {
+                const hipError_t e = batch_fork(b, s);
+                if (e != hipSuccess) return hip_status(e);
+            }
+            int j = 0;
             for (pf::BatchLaunch L : b->launch[dir][k]) {
                 L.b.user_in = (const char *)in;
                 L.b.user_out = (char *)out;
-                const hipError_t e = pf::launch_batch(L, s);
+                // groups dealt round-robin in their order (largest blocks / lengths first)
+                const hipError_t e = pf::launch_batch(L, streams ? b->aux[j] : s);
+                if (e != hipSuccess) return hip_status(e);
+                j = (j + 1) % PF_BATCH_NSTREAMS;
+            }
+            if (streams) {
+                const hipError_t e = batch_join(b, s);
                 if (e != hipSuccess) return hip_status(e);
             }
+        }
         return PF_OK;
     }
     const bool fwd = dir == 0;
-    for (int i = 0; i < b->count; ++i) {
+    if (streams) {
+        const hipError_t e = batch_fork(b, s);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    for (int i : b->order) {
         const char *src = (const char *)in + (fwd ? b->roff[i] : b->coff[i]);
         char *dst = (char *)out + (fwd ? b->coff[i] : b->roff[i]);
-        const int r = run_chain(b->plans[i], dir, src, dst, s);
+        const int r = run_chain(b->plans[i], dir, src, dst, streams ? b->aux[b->home[i]] : s);
         if (r) return r;
+    }
+    if (streams) {
+        const hipError_t e = batch_join(b, s);
+        if (e != hipSuccess) return hip_status(e);
     }
     return PF_OK;
 }
@@ -1562,9 +1611,30 @@ int pf_batch_setup(int count, const int *dims, const pf_layout *l, const pf_tune
             }
         }
     if (hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) {
         batch_free(b);
         return PF_EHIP;
+    }
+    for (int j = 0; j < PF_BATCH_NSTREAMS; ++j)  // default priority, as every stream here
+        if (hipStreamCreateWithFlags(&b->aux[j], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join_ev[j], hipEventDisableTiming) != hipSuccess) {
+            batch_free(b);
+            return PF_EHIP;
+        }
+    // serial order: largest transform first, each to the stream with the fewest points so far
+    b->order.resize(count);
+    b->home.assign(count, 0);
+    for (int i = 0; i < count; ++i) b->order[i] = i;
+    auto points = [&](int i) { return (double)b->plans[i]->nx * b->plans[i]->ny * b->plans[i]->nz; };
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int u, int v) { return points(u) > points(v); });
+    double load[PF_BATCH_NSTREAMS] = {};
+    for (int i : b->order) {
+        int j = 0;
+        for (int q = 1; q < PF_BATCH_NSTREAMS; ++q)
+            if (load[q] < load[j]) j = q;
+        b->home[i] = j;
+        load[j] += points(i);
     }
     *out = b;
     return PF_OK;
@@ -1581,7 +1651,8 @@ size_t pf_batch_bytes(const pf_batch *b, int which) {
 }
 
 int pf_batch_set_mode(pf_batch *b, int mode) {
-    if (!b || mode < 0 || mode > 3) return PF_EINVAL;
+    if (!b || mode < 0 || mode > 7) return PF_EINVAL;
+    if ((mode & PF_BATCH_GRAPH) && (mode & PF_BATCH_STREAMS)) return PF_EUNSUPPORTED;
     b->mode = mode;
     return PF_OK;
 }

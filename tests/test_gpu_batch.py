@@ -3,8 +3,9 @@ in [48, 320], odd ones included; the paper's arbitrary grid sizes, Sec. 3.1).
 
 Every transform of a batch must match the oracle (FP32 1e-6, FP64 1e-12),
 in every execution mode (one transform at a time, one fused launch per pass,
-and both replayed from a captured hipGraph) and with tuned radix orders and
-tile widths; the modes run the same arithmetic and must agree bit for bit.
+both replayed from a captured hipGraph, and both spread over the batch's own
+streams) and with tuned radix orders and tile widths; the modes run the same
+arithmetic and must agree bit for bit.
 Graph replays are checked one by one, with eager work between them.
 """
 import numpy as np
@@ -86,7 +87,8 @@ def test_all_modes_agree_bitwise_and_graph_replays():
         R, C, Cin, Rout = check_batch(b, 1e-6)
         ref_c, ref_r = C.clone(), Rout.clone()
         for mode in (pf.PF_BATCH_SERIAL, pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH,
-                     pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH):
+                     pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH, pf.PF_BATCH_SERIAL | pf.PF_BATCH_STREAMS,
+                     pf.PF_BATCH_FUSED | pf.PF_BATCH_STREAMS):
             b.set_mode(mode)
             for rep in range(3):  # replays of the captured graph, eager work in between
                 C2 = torch.zeros_like(C)
@@ -147,6 +149,9 @@ def test_batch_argument_errors():
         with pytest.raises(pf.PfError) as e:
             b.set_mode(9)
         assert e.value.code == pf.PF_EINVAL
+        with pytest.raises(pf.PfError) as e:
+            b.set_mode(pf.PF_BATCH_GRAPH | pf.PF_BATCH_STREAMS)
+        assert e.value.code == pf.PF_EUNSUPPORTED
 
 
 @pytest.mark.timeout(900)
