@@ -84,14 +84,14 @@ def traffic_from_profile(pass_name: str, n: int):
 
 def section_starts(names):
     """Dispatch indices where the benchmark's sections start, from the kernel names in launch order:
-    the batch (first generic-kernel launch), the spectral step (its first k_r2c_p2<256, ...>), the
+    the batch (first runtime-radix or mixed-radix launch), the spectral step (its first k_r2c_p2<256, ...>), the
     share-only leg (its first fill), the FP64 512^3 plan (its first FP64 kernel) and the other grids
     (the next k_r2c_p2<256, ...>)."""
 
     def first(pred, start=0):
         return next((i for i in range(start, len(names)) if pred(names[i])), len(names))
 
-    generic = ("k_c2c_tile", "k_r2c_x", "k_c2r_x")
+    generic = ("k_c2c_tile", "k_r2c_x", "k_c2r_x", "k_mr_")
     b0 = first(lambda k: any(g in k for g in generic))
     s0 = first(lambda k: "k_r2c_p2<256" in k, b0)
     h0 = first(lambda k: "k_fill" in k, s0)
@@ -155,10 +155,13 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
         "kernels_batch64_mixed.txt": [
             "rocprofv3 kernel-trace statistics, 64 batched FP32 R2C+C2R transforms "
             "(synth.batch_sizes(4, 64), 7-smooth sizes in [48, 320]^3)", *head,
-            f"modes serial, serial + hipGraph, fused, fused + hipGraph, with default and tuned plans: "
-            f"{pairs} pairs each; k_*_b are the fused launches",
-            "(one per pass and block size), k_c2c_tile / k_r2c_x / k_c2r_x the serial ones (one per transform "
-            "and pass)", *table(rows[b0:s0])],
+            f"modes serial, serial + hipGraph, serial on 4 streams, fused, fused + hipGraph, fused on 4 "
+            f"streams, with default and tuned plans: {pairs} pairs each;",
+            "k_mr_c2c<N1, N2, DIR> / k_mr_x<N1, N2, FWD>: the compile-time mixed-radix passes (length N1 N2; "
+            "one launch per transform and pass in",
+            "the serial modes, per pass and length in the fused ones); k_*_b: fused launches of the runtime-radix "
+            "passes (one per pass and block size),",
+            "k_c2c_tile / k_r2c_x / k_c2r_x their serial launches", *table(rows[b0:s0])],
         "kernels_cheb_spectral_512x512x257.txt": [
             "rocprofv3 kernel-trace statistics, Chebyshev spectral step on 512 x 512 x 257 FP32 "
             "(type-I DCT along z)", *head,
@@ -216,8 +219,8 @@ def summarize_sq(counter_csv: str, command: str) -> None:
          lambda k: modes(512, 512, 257)),
         ("FP64 512^3 (M = 257 x 512 x 512)", ds[f0:o0], lambda k: m512),
         ("other grids: 512^3 on the power-of-two kernels (M = 257 x 512 x 512), 480 x 360 x 250 on the "
-         "mixed-radix kernels <float> (M = 241 x 360 x 250)", ds[o0:],
-         lambda k: modes(480, 360, 250) if "<float" in k else m512),
+         "compile-time mixed-radix kernels k_mr_* (M = 241 x 360 x 250)", ds[o0:],
+         lambda k: modes(480, 360, 250) if "k_mr_" in k else m512),
     ]
     lines = ["rocprofv3 SQ instruction counters per dispatch, FP32 R2C+C2R workloads of the benchmark, MI355X",
              f"command: {command}",
@@ -419,8 +422,9 @@ def cpu_baseline_one_core(n: int):
 
 def other_grid_timings(pf, args, dev, stream):
     """The other FP32 grids of the plain path (STRIDE1, out-of-place, uniform[-1, 1] data): 512^3, all on
-    the power-of-two kernels, and the uneven 480 x 360 x 250, all on the mixed-radix ones: ms per pair,
-    GFLOP/s and algorithmic HBM GB/s."""
+    the power-of-two kernels, and the uneven 480 x 360 x 250, all on the compile-time mixed-radix ones: ms
+    per pair, GFLOP/s and algorithmic HBM GB/s; then, in a second timed loop with events between the
+    passes, each pass's kernel family, average ms and algorithmic GB/s."""
     import torch
 
     out = {}
@@ -447,8 +451,23 @@ def other_grid_timings(pf, args, dev, stream):
         N = float(nx) * ny * nz
         nbytes = sum(plan.pass_bytes(d, i) for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD)
                      for i in range(plan.num_passes(d)))
-        out[f"{nx}x{ny}x{nz}"] = {"ms_per_pair": ms, "gflops": 5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9,
-                                  "alg_GBps": nbytes / (ms * 1e-3) / 1e9}
+        rec = {"ms_per_pair": ms, "gflops": 5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9,
+               "alg_GBps": nbytes / (ms * 1e-3) / 1e9}
+        plan.set_timing(True)
+        for _ in range(args.steps):
+            plan.ftran(u, U)
+            plan.btran(U, r)
+        torch.cuda.synchronize()
+        passes = []
+        for d in (pf.PF_DIR_FORWARD, pf.PF_DIR_BACKWARD):
+            for i in range(plan.num_passes(d)):
+                tot, cnt = plan.get_timing(d, i)
+                pms = tot / max(cnt, 1)
+                passes.append({"pass": plan.pass_name(d, i), "kernel": plan.pass_kernel(d, i), "avg_ms": pms,
+                               "alg_GBps": plan.pass_bytes(d, i) / (pms * 1e-3) / 1e9})
+        plan.set_timing(False)
+        rec["passes"] = passes
+        out[f"{nx}x{ny}x{nz}"] = rec
         plan.destroy()
     return out
 
@@ -614,8 +633,10 @@ def batch_timing(pf, args, dev, stream, count=64, seed=4, check=True):
     flops = sum(5.0 * N * math.log2(N) for N in Ns)
     nbytes = sum(2 * (N * 4 + (nx // 2 + 1) * ny * nz * 8) + 8 * (nx // 2 + 1) * ny * nz * 8
                  for N, (nx, ny, nz) in zip(Ns, dims))  # both directions: X, Y, Z passes
-    serial_modes = (("serial", pf.PF_BATCH_SERIAL), ("serial_graph", pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH))
-    fused_modes = (("fused", pf.PF_BATCH_FUSED), ("fused_graph", pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH))
+    serial_modes = (("serial", pf.PF_BATCH_SERIAL), ("serial_graph", pf.PF_BATCH_SERIAL | pf.PF_BATCH_GRAPH),
+                    ("serial_streams", pf.PF_BATCH_SERIAL | pf.PF_BATCH_STREAMS))
+    fused_modes = (("fused", pf.PF_BATCH_FUSED), ("fused_graph", pf.PF_BATCH_FUSED | pf.PF_BATCH_GRAPH),
+                   ("fused_streams", pf.PF_BATCH_FUSED | pf.PF_BATCH_STREAMS))
     # the cached plans of each mode: radix orders and tiles (serial), radix orders alone (fused)
     runs = (("default", None, serial_modes + fused_modes),
             ("tuned", autotune.tune_for(dims, mode="serial"), serial_modes),

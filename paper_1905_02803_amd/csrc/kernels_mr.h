@@ -113,6 +113,39 @@ struct DftMR {
 };
 
 // ---- tile geometry -----------------------------------------------------------
+#ifndef PF_MR_SPZ_RES
+#define PF_MR_SPZ_RES 2
+#endif
+// global accesses with the nontemporal hint: bit 0 stores, bit 1 loads
+#ifndef PF_MR_NT
+#define PF_MR_NT 0
+#endif
+typedef float mr_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 mr_ld(const float2 *p) {
+    if constexpr ((PF_MR_NT & 2) != 0) {
+        const mr_f2 u = __builtin_nontemporal_load(reinterpret_cast<const mr_f2 *>(p));
+        return make_float2(u.x, u.y);
+    } else {
+        return *p;
+    }
+}
+__device__ __forceinline__ float mr_ld(const float *p) {
+    if constexpr ((PF_MR_NT & 2) != 0) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+__device__ __forceinline__ void mr_st(float2 *p, float2 v) {
+    if constexpr ((PF_MR_NT & 1) != 0) {
+        const mr_f2 u = {v.x, v.y};
+        __builtin_nontemporal_store(u, reinterpret_cast<mr_f2 *>(p));
+    } else {
+        *p = v;
+    }
+}
+__device__ __forceinline__ void mr_st(float *p, float v) {
+    if constexpr ((PF_MR_NT & 1) != 0) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 __host__ __device__ constexpr int mr_threads(int n1, int n2) {
     return 16 * (((n1 > n2 ? n1 : n2) + 3) / 4 * 4);  // 16 columns x max(N1, N2) items, whole waves
 }
@@ -129,9 +162,9 @@ struct MrShape {
     // X passes: one complex line per column at pitch SP (= 16 mod 32, >= N)
     static constexpr int SP = N + ((16 - N % 32) % 32 + 32) % 32;
     static constexpr int XLDS = XCH > 16 * SP ? XCH : 16 * SP;
-    // C2C pass with a line side: line-major tile copy at pitch SPZ (= 2 mod
-    // 32, >= N), written and read by lanes along the columns without conflicts
-    static constexpr int SPZ = N + ((2 - N % 32) % 32 + 32) % 32;
+    // C2C pass with a line side: line-major tile copy at pitch SPZ (= PF_MR_SPZ_RES
+    // mod 32, >= N), written and read by lanes along the columns
+    static constexpr int SPZ = N + ((PF_MR_SPZ_RES - N % 32) % 32 + 32) % 32;
     static constexpr int CLDS = XCH > 16 * SPZ ? XCH : 16 * SPZ;
 };
 
@@ -188,7 +221,7 @@ __device__ __forceinline__ void mr_c2c_body(const MrC2C &t) {
             const int f = tid + i * S::THREADS;
             const int cc = f / N, p = f - cc * N;
             r[i] = make_float2(0.f, 0.f);
-            if (f < 16 * N && cc < t.ncol) r[i] = t.in[t.ib + cc * t.isc + p];
+            if (f < 16 * N && cc < t.ncol) r[i] = mr_ld(t.in + t.ib + cc * t.isc + p);
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
@@ -209,7 +242,7 @@ __device__ __forceinline__ void mr_c2c_body(const MrC2C &t) {
             const cx<float> *src = t.in + t.ib + c * t.isc + j * t.isp;
             const long long step = (long long)N2 * t.isp;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) x[m] = src[m * step];
+            for (int m = 0; m < N1; ++m) x[m] = mr_ld(src + m * step);
         }
         DftMR<N1, DIR>::run(x);
 #pragma unroll
@@ -249,13 +282,13 @@ __device__ __forceinline__ void mr_c2c_body(const MrC2C &t) {
         for (int i = 0; i < ITEMS; ++i) {
             const int f = tid + i * S::THREADS;
             const int cc = f / N, p = f - cc * N;
-            if (f < 16 * N && cc < t.ncol) t.out[t.ob + cc * t.osc + p] = r[i];
+            if (f < 16 * N && cc < t.ncol) mr_st(t.out + t.ob + cc * t.osc + p, r[i]);
         }
     } else if (j < N1 && cv) {
         cx<float> *dst = t.out + t.ob + c * t.osc + j * t.osp;
         const long long step = (long long)N1 * t.osp;
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) dst[k2 * step] = y[k2];
+        for (int k2 = 0; k2 < N2; ++k2) mr_st(dst + k2 * step, y[k2]);
     }
 }
 
@@ -317,12 +350,12 @@ __device__ __forceinline__ void mr_r2c_body(const MrX &t) {
         if (ga < t.lines) {
             const float *pa = in + ga * t.ld_real + q;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) x[m].x = pa[N2 * m];
+            for (int m = 0; m < N1; ++m) x[m].x = mr_ld(pa + N2 * m);
         }
         if (ga + 1 < t.lines) {
             const float *pb = in + (ga + 1) * t.ld_real + q;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) x[m].y = pb[N2 * m];
+            for (int m = 0; m < N1; ++m) x[m].y = mr_ld(pb + N2 * m);
         }
         DftMR<N1, -1>::run(x);
 #pragma unroll
@@ -355,8 +388,8 @@ __device__ __forceinline__ void mr_r2c_body(const MrX &t) {
             const cx<float> z = lds[cc * S::SP + k];
             const cx<float> w = lds[cc * S::SP + (k == 0 ? 0 : N - k)];
             const long long o = kb * t.kbstride + kk;
-            out[rowoff[2 * cc] + o] = make_float2((z.x + w.x) * 0.5f, (z.y - w.y) * 0.5f);
-            if (ga + 1 < t.lines) out[rowoff[2 * cc + 1] + o] = make_float2((z.y + w.y) * 0.5f, (w.x - z.x) * 0.5f);
+            mr_st(out + rowoff[2 * cc] + o, make_float2((z.x + w.x) * 0.5f, (z.y - w.y) * 0.5f));
+            if (ga + 1 < t.lines) mr_st(out + rowoff[2 * cc + 1] + o, make_float2((z.y + w.y) * 0.5f, (w.x - z.x) * 0.5f));
         }
     }
 }
@@ -388,8 +421,8 @@ __device__ __forceinline__ void mr_c2r_body(const MrX &t) {
             const long long ga = t.g0 + 2 * cc;
             if (f < total && k < t.nxh && ga < t.lines) {
                 const long long o = kb * t.kbstride + kk;
-                ra[i] = in[rowoff[2 * cc] + o];
-                if (ga + 1 < t.lines) rb[i] = in[rowoff[2 * cc + 1] + o];
+                ra[i] = mr_ld(in + rowoff[2 * cc] + o);
+                if (ga + 1 < t.lines) rb[i] = mr_ld(in + rowoff[2 * cc + 1] + o);
             }
         }
 #pragma unroll
@@ -439,12 +472,12 @@ __device__ __forceinline__ void mr_c2r_body(const MrX &t) {
         if (ga < t.lines) {
             float *pa = out + ga * t.ld_real + k1;
 #pragma unroll
-            for (int k2 = 0; k2 < N2; ++k2) pa[N1 * k2] = y[k2].x;
+            for (int k2 = 0; k2 < N2; ++k2) mr_st(pa + N1 * k2, y[k2].x);
         }
         if (ga + 1 < t.lines) {
             float *pb = out + (ga + 1) * t.ld_real + k1;
 #pragma unroll
-            for (int k2 = 0; k2 < N2; ++k2) pb[N1 * k2] = y[k2].y;
+            for (int k2 = 0; k2 < N2; ++k2) mr_st(pb + N1 * k2, y[k2].y);
         }
     }
 }

@@ -54,13 +54,16 @@ int mr_threads_of(int n) {
 }
 
 size_t mr_lds_bytes(int n, int xpass) {
-    int a = 0, b = 0;
-    if (!mr_factors(n, &a, &b)) return 0;
-    // MrShape's XCH, SP, SPZ
-    const int p2 = b % 2 == 0 ? b + 1 : b;
-    const size_t xch = (size_t)16 * a * p2;
-    const size_t sp = (size_t)n + (size_t)(((xpass ? 16 : 2) - n % 32) % 32 + 32) % 32;
-    return (xch > 16 * sp ? xch : 16 * sp) * sizeof(float2);
+    // the kernels' own tile constants, so that host and device sizes agree
+#define PF_MR_CASE(N, N1, N2) \
+    case N:                   \
+        return (size_t)(xpass ? MrShape<N1, N2>::XLDS : MrShape<N1, N2>::CLDS) * sizeof(float2);
+    switch (n) {
+        PF_MR_LENGTHS(PF_MR_CASE)
+        default:
+            return 0;
+    }
+#undef PF_MR_CASE
 }
 
 hipError_t mr_launch(const PassDesc &d, hipStream_t s) {
