@@ -109,7 +109,7 @@ def test_sq_summary_normalises_by_each_sections_grid(tmp_root):
             ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 1e6),                     # the spectral step
             ("pf::k_fill(pf::FillArgs)", 1e6),                                    # the share-only leg
             ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 1e6),                     # the other grids
-            ("void pf::k_c2c_tile<float, -1>(pf::PassArgs)", m480 * 150 / 64)]
+            ("void pf::k_mr_c2c<18, 20, -1>(pf::MrArgs)", m480 * 150 / 64)]
     path = tmp_root / "sq.csv"
     with open(path, "w", newline="") as f:
         w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp",
@@ -131,7 +131,7 @@ def test_sq_summary_normalises_by_each_sections_grid(tmp_root):
 
     r = row("void pf::k_c2c_p2<1024", "1024^3")
     assert float(r[-4]) == pytest.approx(40.0, abs=0.05)
-    r = row("void pf::k_c2c_tile<float, -1>", "other grids")
+    r = row("void pf::k_mr_c2c<18, 20, -1>", "other grids")
     assert float(r[-4]) == pytest.approx(150.0, abs=0.05)
     assert "k_fill" not in text  # the share-only leg is not summarised
     # the batch has no fixed grid: no per-element figure
