@@ -151,7 +151,8 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
         "kernels_fft_512cubed_480x360x250.txt": [
             "rocprofv3 kernel-trace statistics, FP32 R2C+C2R at 512^3 (power-of-two kernels) and "
             "480 x 360 x 250 (mixed-radix kernels), STRIDE1, out-of-place", *head,
-            f"{pairs} pairs each", *table(rows[o0:])],
+            f"{warmup + 2 * steps} pairs each ({warmup} warm-up, {steps} timed, {steps} timed with events "
+            "between the passes)", *table(rows[o0:])],
         "kernels_batch64_mixed.txt": [
             "rocprofv3 kernel-trace statistics, 64 batched FP32 R2C+C2R transforms "
             "(synth.batch_sizes(4, 64), 7-smooth sizes in [48, 320]^3)", *head,
@@ -904,12 +905,22 @@ def main():
             fwd_host[name] = Um.cpu().numpy()
         del Um
         pm.destroy()
+    def step(name):  # a progress line per section, on stderr (the JSON line is the only stdout)
+        print(f"bench: {name}", file=sys.stderr, flush=True)
+
+    step("fused X-Y plan")
     fused = fused_timing(pf, nx, ny, nz, args, dev, stream, u, passes)
+    step("layout variants")
     layouts = layout_timings(pf, nx, ny, nz, args, dev, stream, u)
+    step("batch")
     batched = batch_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
+    step("spectral step")
     spectral = spectral_timing(pf, args, dev, stream)
+    step("share-only rank")
     share = share_only_timing(pf, nx, ny, nz, args, dev, stream)
+    step("FP64 512^3")
     f64 = f64_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
+    step("other grids")
     other_grids = other_grid_timings(pf, args, dev, stream)  # last: the trace summary splits on its first launch
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
