@@ -98,7 +98,9 @@ def section_starts(names):
     o0 = first(lambda k: "k_r2c_p2<256" in k, h0)
     # the FP64 512^3 plan runs between the share-only leg and the other grids
     f0 = first(lambda k: "k_c2c_p2d" in k or "<double" in k, h0)
-    return b0, s0, h0, min(f0, o0), o0
+    # the fused comparison at 2048 x 512 x 512 (its X kernel k_r2c_p2<1024, ...>) runs last
+    c0 = first(lambda k: "k_r2c_p2<1024" in k, o0)
+    return b0, s0, h0, min(f0, o0), o0, c0
 
 
 def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> None:
@@ -114,7 +116,7 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
 
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
-    b0, s0, h0, f0, o0 = section_starts([r["Kernel_Name"] for r in rows])
+    b0, s0, h0, f0, o0, c0 = section_starts([r["Kernel_Name"] for r in rows])
 
     def table(rs):
         d = {}
@@ -152,7 +154,11 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
             "rocprofv3 kernel-trace statistics, FP32 R2C+C2R at 512^3 (power-of-two kernels) and "
             "480 x 360 x 250 (mixed-radix kernels), STRIDE1, out-of-place", *head,
             f"{warmup + 2 * steps} pairs each ({warmup} warm-up, {steps} timed, {steps} timed with events "
-            "between the passes)", *table(rows[o0:])],
+            "between the passes)", *table(rows[o0:c0])],
+        "kernels_fft_2048x512x512_fused.txt": [
+            "rocprofv3 kernel-trace statistics, FP32 R2C+C2R at 2048 x 512 x 512, STRIDE1, out-of-place: "
+            "the three-pass plan, then the fused X-Y plan", *head,
+            f"{pairs} pairs each; k_xy_fused<1024, 512, FWD>: the fused X-Y pass", *table(rows[c0:])],
         "kernels_batch64_mixed.txt": [
             "rocprofv3 kernel-trace statistics, 64 batched FP32 R2C+C2R transforms "
             "(synth.batch_sizes(4, 64), 7-smooth sizes in [48, 320]^3)", *head,
@@ -205,7 +211,7 @@ def summarize_sq(counter_csv: str, command: str) -> None:
             "scratch": r.get("Scratch_Size", ""), "c": {}})
         d["c"][r["Counter_Name"]] = float(r["Counter_Value"])
     ds = [disp[k] for k in sorted(disp)]
-    b0, s0, h0, f0, o0 = section_starts([d["name"] for d in ds])
+    b0, s0, h0, f0, o0, c0 = section_starts([d["name"] for d in ds])
 
     def modes(nx, ny, nz):
         return (nx // 2 + 1) * ny * nz
@@ -220,8 +226,10 @@ def summarize_sq(counter_csv: str, command: str) -> None:
          lambda k: modes(512, 512, 257)),
         ("FP64 512^3 (M = 257 x 512 x 512)", ds[f0:o0], lambda k: m512),
         ("other grids: 512^3 on the power-of-two kernels (M = 257 x 512 x 512), 480 x 360 x 250 on the "
-         "compile-time mixed-radix kernels k_mr_* (M = 241 x 360 x 250)", ds[o0:],
+         "compile-time mixed-radix kernels k_mr_* (M = 241 x 360 x 250)", ds[o0:c0],
          lambda k: modes(480, 360, 250) if "k_mr_" in k else m512),
+        ("2048 x 512 x 512, three-pass and fused X-Y plans (M = 1025 x 512 x 512)", ds[c0:],
+         lambda k: modes(2048, 512, 512)),
     ]
     lines = ["rocprofv3 SQ instruction counters per dispatch, FP32 R2C+C2R workloads of the benchmark, MI355X",
              f"command: {command}",
@@ -513,6 +521,35 @@ def fused_timing(pf, nx, ny, nz, args, dev, stream, u, plain_passes):
             out["passes"].append(e)
     plan.set_timing(False)
     plan.destroy()
+    return out
+
+
+def fused_compare_timing(pf, args, dev, stream, nx=2048, ny=512, nz=512):
+    """Pair times of the three-pass and the fused X-Y plans on a grid whose X pass (2048-point lines)
+    outweighs its Y pass.  Runs last: the trace summary splits on its first launch."""
+    import torch
+
+    u = torch.empty((nz, ny, nx), device=dev, dtype=torch.float32).uniform_(-1.0, 1.0)
+    out = {"grid": [nx, ny, nz]}
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    for name, lay in (("three_pass_ms", pf.Layout()), ("fused_ms", pf.Layout(fused_xy=1))):
+        plan = pf.Plan(nx, ny, nz, lay)
+        U = plan.empty_complex(dev)
+        r = plan.empty_real(dev)
+        for _ in range(args.warmup):
+            plan.ftran(u, U)
+            plan.btran(U, r)
+        torch.cuda.synchronize()
+        s0.record(stream)
+        for _ in range(args.steps):
+            plan.ftran(u, U)
+            plan.btran(U, r)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        pf.pf_check_status(plan.handle)
+        out[name] = s0.elapsed_time(s1) / args.steps
+        plan.destroy()
     return out
 
 
@@ -921,7 +958,9 @@ def main():
     step("FP64 512^3")
     f64 = f64_timing(pf, args, dev, stream, check=not args.no_cpu_baseline)
     step("other grids")
-    other_grids = other_grid_timings(pf, args, dev, stream)  # last: the trace summary splits on its first launch
+    other_grids = other_grid_timings(pf, args, dev, stream)  # the trace summary splits on its first launch
+    step("fused X-Y against three passes at 2048 x 512 x 512")
+    fused_cmp = fused_compare_timing(pf, args, dev, stream)  # last, likewise
     flops = 5.0 * Nf * math.log2(Nf)
     alg_bytes = sum(p["alg_bytes"] for p in passes)
     gflops = flops / (ms * 1e-3) / 1e9
@@ -974,6 +1013,7 @@ def main():
         "share_only": share,
         "layouts": layouts,
         "other_grids": other_grids,
+        "fused_xy_2048x512x512": fused_cmp,
         "f64_512cubed": f64,
         "batched": batched,
         "spectral_step": spectral,

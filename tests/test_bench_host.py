@@ -46,7 +46,9 @@ def test_trace_summary_splits_the_workloads(tmp_root):
              ("pf::k_fill(pf::FillArgs)", 0.09),                            # the share-only leg begins
              (KERNELS[0], 0.28),
              ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 0.4),              # the other grids begin
-             ("void pf::k_r2c_x<float>(pf::PassArgs)", 0.1)]
+             ("void pf::k_mr_x<20, 24, 1>(pf::MrArgs)", 0.1),
+             ("void pf::k_r2c_p2<1024, 0>(pf::PassArgs)", 0.9),             # the fused comparison begins
+             ("void pf::k_xy_fused<1024, 512, 1>(pf::FusedArgs)", 1.7)]
     write_trace(trace, names)
     bench.summarize_trace(str(trace), "CMD", steps=10, warmup=2)
     prof = tmp_root / "profiles"
@@ -62,8 +64,11 @@ def test_trace_summary_splits_the_workloads(tmp_root):
     assert "k_c2c_tile_b" in batch and "k_spec_p2" not in batch and "k_r2c_p2<512" not in batch
     assert "k_spec_p2" in spec and "k_fill" not in spec
     other = (prof / "kernels_fft_512cubed_480x360x250.txt").read_text()
-    assert "k_r2c_p2<256" in other and "k_r2c_x<float>" in other and "k_fill" not in other
-    assert "k_r2c_x<float>" not in share
+    assert "k_r2c_p2<256" in other and "k_mr_x<20, 24, 1>" in other and "k_fill" not in other
+    assert "k_xy_fused" not in other and "k_r2c_p2<1024" not in other
+    assert "k_mr_x" not in share
+    fused = (prof / "kernels_fft_2048x512x512_fused.txt").read_text()
+    assert "k_r2c_p2<1024" in fused and "k_xy_fused<1024, 512, 1>" in fused and "k_mr_x" not in fused
 
 
 def write_counters(path, counter, rows):

@@ -44,8 +44,10 @@ def test_noalloc_matches_existing_entry_point_large_then_small(prec):
     rdt = np.float64 if prec == pf.PF_F64 else np.float32
     cdt = np.complex128 if prec == pf.PF_F64 else np.complex64
     tol = 1e-12 if prec == pf.PF_F64 else 1e-6
-    # first a grid on the power-of-two kernels (FP32), then a smaller mixed-radix one
-    for step, shape in enumerate([(64, 256, 512), (24, 20, 36)]):
+    # first a grid on the power-of-two kernels (FP32), then smaller ones on the
+    # compile-time mixed-radix kernels (FP32: lengths 96, 60, 50) and on the
+    # runtime-radix kernels (lengths 36, 20, 24)
+    for step, shape in enumerate([(64, 256, 512), (50, 60, 96), (24, 20, 36)]):
         nz, ny, nx = shape
         print(f"case no-alloc call {step} shape={shape} prec={prec}", flush=True)
         with pf.Plan(nx, ny, nz, pf.Layout(precision=prec)) as plan:
