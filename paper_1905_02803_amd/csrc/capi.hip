@@ -278,7 +278,7 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
         a.tw = (const char *)p->tw_dev + p->tw_mr[axis];
         a.tc_log2 = 4;
         a.wpc_log2 = 0;
-        d.threads = (unsigned)pf::mr_threads_of(fs.n);
+        d.threads = (unsigned)pf::mr_threads_of(fs.n, 0);
         d.lds = pf::mr_lds_bytes(fs.n, 0);
         return;
     }
@@ -631,7 +631,7 @@ void build_passes(pf_plan *p) {
             x.a.tw = (const char *)p->tw_dev + p->tw_mr[0];
             x.a.tc_log2 = 4;
             x.a.wpc_log2 = 0;
-            x.threads = (unsigned)pf::mr_threads_of(p->nx);
+            x.threads = (unsigned)pf::mr_threads_of(p->nx, 1);
             x.lds = pf::mr_lds_bytes(p->nx, 1);
             x.blocks = (unsigned)((pairs + 15) / 16);
         }

@@ -116,6 +116,10 @@ struct DftMR {
 #ifndef PF_MR_SPZ_RES
 #define PF_MR_SPZ_RES 2
 #endif
+// C2C kernel: two step-1 items per thread for strongly unbalanced factor pairs
+#ifndef PF_MR_HALF
+#define PF_MR_HALF 1
+#endif
 // global accesses with the nontemporal hint: bit 0 stores, bit 1 loads
 #ifndef PF_MR_NT
 #define PF_MR_NT 0
@@ -149,6 +153,19 @@ __device__ __forceinline__ void mr_st(float *p, float v) {
 __host__ __device__ constexpr int mr_threads(int n1, int n2) {
     return 16 * (((n1 > n2 ? n1 : n2) + 3) / 4 * 4);  // 16 columns x max(N1, N2) items, whole waves
 }
+// Threads per column of the C2C kernel: max(N1, N2) rounded up to 4, or, where
+// N2 >= 2 N1 and N2 >= 24, max(N1, ceil(N2 / 2)) with up to two step-1 items
+// per thread -- smaller workgroups, of which more fit on a CU, where step 2
+// would leave most threads idle.  Measured per length on the Y pass: faster
+// for N2 of 25 and more (lengths 125, 175, 243, 250; 245 even), slower by
+// 4-8% for N2 of 21 and less.
+__host__ __device__ constexpr int mr_c2c_cols(int n1, int n2) {
+    const int full = ((n1 > n2 ? n1 : n2) + 3) / 4 * 4;
+    const int half2 = (n2 + 1) / 2;
+    const int half = ((n1 > half2 ? n1 : half2) + 3) / 4 * 4;
+    return PF_MR_HALF && n2 >= 2 * n1 && n2 >= 24 && half < full ? half : full;
+}
+__host__ __device__ constexpr int mr_c2c_threads(int n1, int n2) { return 16 * mr_c2c_cols(n1, n2); }
 
 template <int N1, int N2>
 struct MrShape {
@@ -166,6 +183,10 @@ struct MrShape {
     // mod 32, >= N), written and read by lanes along the columns
     static constexpr int SPZ = N + ((PF_MR_SPZ_RES - N % 32) % 32 + 32) % 32;
     static constexpr int CLDS = XCH > 16 * SPZ ? XCH : 16 * SPZ;
+    // C2C kernel: threads per column, threads, step-1 items per thread
+    static constexpr int CT = mr_c2c_cols(N1, N2);
+    static constexpr int CTHREADS = 16 * CT;
+    static constexpr int I1 = (N2 + CT - 1) / CT;
 };
 
 // ---- C2C column tile -----------------------------------------------------------
@@ -204,7 +225,8 @@ template <int N1, int N2, int DIR>
 __device__ __forceinline__ void mr_c2c_body(const MrC2C &t) {
     using S = MrShape<N1, N2>;
     constexpr int N = S::N;
-    constexpr int ITEMS = (16 * N + S::THREADS - 1) / S::THREADS;  // tile points per thread
+    constexpr int NT = S::CTHREADS;
+    constexpr int ITEMS = (16 * N + NT - 1) / NT;  // tile points per thread
     cx<float> *lds = reinterpret_cast<cx<float> *>(pf_smem);
     const int tid = threadIdx.x;
     const int c = tid & 15, j = tid >> 4;
@@ -218,44 +240,60 @@ __device__ __forceinline__ void mr_c2c_body(const MrC2C &t) {
         cx<float> r[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int f = tid + i * S::THREADS;
+            const int f = tid + i * NT;
             const int cc = f / N, p = f - cc * N;
             r[i] = make_float2(0.f, 0.f);
             if (f < 16 * N && cc < t.ncol) r[i] = mr_ld(t.in + t.ib + cc * t.isc + p);
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int f = tid + i * S::THREADS;
+            const int f = tid + i * NT;
             const int cc = f / N, p = f - cc * N;
             if (f < 16 * N) lds[cc * S::SPZ + p] = r[i];
         }
         __syncthreads();
     }
-    cx<float> x[N1];
-    if (j < N2) {  // step 1, item q = j: the N1 points q + N2 m of column c
+    // step 1, items q = j + it CT (it < I1): the N1 points q + N2 m of column c;
+    // every item's loads are issued before the first transform
+    cx<float> x[S::I1][N1];
 #pragma unroll
-        for (int m = 0; m < N1; ++m) x[m] = make_float2(0.f, 0.f);
-        if (in_lines) {
+    for (int it = 0; it < S::I1; ++it) {
+        const int q = j + it * S::CT;
 #pragma unroll
-            for (int m = 0; m < N1; ++m) x[m] = lds[c * S::SPZ + j + N2 * m];
-        } else if (cv) {
-            const cx<float> *src = t.in + t.ib + c * t.isc + j * t.isp;
-            const long long step = (long long)N2 * t.isp;
+        for (int m = 0; m < N1; ++m) x[it][m] = make_float2(0.f, 0.f);
+        if (q < N2) {
+            if (in_lines) {
 #pragma unroll
-            for (int m = 0; m < N1; ++m) x[m] = mr_ld(src + m * step);
+                for (int m = 0; m < N1; ++m) x[it][m] = lds[c * S::SPZ + q + N2 * m];
+            } else if (cv) {
+                const cx<float> *src = t.in + t.ib + c * t.isc + q * t.isp;
+                const long long step = (long long)N2 * t.isp;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) x[it][m] = mr_ld(src + m * step);
+            }
         }
-        DftMR<N1, DIR>::run(x);
+    }
 #pragma unroll
-        for (int k1 = 1; k1 < N1; ++k1) {
-            cx<float> w = t.tw[j * k1];
-            if (DIR > 0) w.y = -w.y;
-            x[k1] = cmul(x[k1], w);
+    for (int it = 0; it < S::I1; ++it) {
+        const int q = j + it * S::CT;
+        if (q < N2) {
+            DftMR<N1, DIR>::run(x[it]);
+#pragma unroll
+            for (int k1 = 1; k1 < N1; ++k1) {
+                cx<float> w = t.tw[q * k1];
+                if (DIR > 0) w.y = -w.y;
+                x[it][k1] = cmul(x[it][k1], w);
+            }
         }
     }
     if (in_lines) __syncthreads();  // the staged lines are read before the exchange tile overwrites them
-    if (j < N2) {
 #pragma unroll
-        for (int k1 = 0; k1 < N1; ++k1) lds[(k1 * S::P2 + j) * 16 + c] = x[k1];
+    for (int it = 0; it < S::I1; ++it) {
+        const int q = j + it * S::CT;
+        if (q < N2) {
+#pragma unroll
+            for (int k1 = 0; k1 < N1; ++k1) lds[(k1 * S::P2 + q) * 16 + c] = x[it][k1];
+        }
     }
     __syncthreads();
     cx<float> y[N2];
@@ -274,13 +312,13 @@ __device__ __forceinline__ void mr_c2c_body(const MrC2C &t) {
         cx<float> r[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int f = tid + i * S::THREADS;
+            const int f = tid + i * NT;
             const int cc = f / N, p = f - cc * N;
             if (f < 16 * N) r[i] = lds[cc * S::SPZ + p];
         }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int f = tid + i * S::THREADS;
+            const int f = tid + i * NT;
             const int cc = f / N, p = f - cc * N;
             if (f < 16 * N && cc < t.ncol) mr_st(t.out + t.ob + cc * t.osc + p, r[i]);
         }
@@ -501,7 +539,7 @@ __device__ __forceinline__ int mr_find(const BatchArgs &b, long long blk) {
 }
 
 template <int N1, int N2, int DIR>
-__global__ __launch_bounds__(mr_threads(N1, N2)) void k_mr_c2c(MrArgs m) {
+__global__ __launch_bounds__(mr_c2c_threads(N1, N2)) void k_mr_c2c(MrArgs m) {
     const long long blk = blockIdx.x;
     MrC2C t;
     if (m.b.count == 0) {

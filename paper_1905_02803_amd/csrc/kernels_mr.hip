@@ -48,9 +48,10 @@ bool mr_supported(int n, int prec) {
     return prec == 0 && mr_factors(n, &a, &b);
 }
 
-int mr_threads_of(int n) {
+int mr_threads_of(int n, int xpass) {
     int a = 0, b = 0;
-    return mr_factors(n, &a, &b) ? mr_threads(a, b) : 0;
+    if (!mr_factors(n, &a, &b)) return 0;
+    return xpass ? mr_threads(a, b) : mr_c2c_threads(a, b);
 }
 
 size_t mr_lds_bytes(int n, int xpass) {

@@ -212,7 +212,7 @@ hipError_t p2_fused_launch(const FusedArgs &f, int fwd, int nx, int ny, unsigned
 // (PASS_R2C_MR / PASS_C2R_MR, 16 line pairs per tile) of a length n the table
 // holds; one tile per workgroup.  a.tw: W_n^m, m < n (forward sign).
 bool mr_supported(int n, int prec);
-int mr_threads_of(int n);
+int mr_threads_of(int n, int xpass);  // threads per workgroup of the C2C (xpass 0) or X kernel
 size_t mr_lds_bytes(int n, int xpass);
 hipError_t mr_launch(const PassDesc &d, hipStream_t s);
 hipError_t mr_launch_batch(const BatchLaunch &L, hipStream_t s);
