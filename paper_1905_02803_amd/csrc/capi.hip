@@ -626,14 +626,15 @@ void build_passes(pf_plan *p) {
         const long long pairs = (x.a.lines + 1) / 2;
         const long long tcx = 1LL << x.a.tc_log2;
         x.blocks = (unsigned)((pairs + tcx - 1) / tcx);
-        if (p->mr[0] && xmax >= 16) {  // compile-time mixed-radix plan, 16 line pairs per tile
+        if (p->mr[0] && xmax >= 16) {  // compile-time mixed-radix plan, mr_x_pairs() line pairs per tile
+            const int xp = pf::mr_x_pairs();
             x.kind = dir == 0 ? pf::PASS_R2C_MR : pf::PASS_C2R_MR;
             x.a.tw = (const char *)p->tw_dev + p->tw_mr[0];
-            x.a.tc_log2 = 4;
+            x.a.tc_log2 = ilog2(xp);
             x.a.wpc_log2 = 0;
             x.threads = (unsigned)pf::mr_threads_of(p->nx, 1);
             x.lds = pf::mr_lds_bytes(p->nx, 1);
-            x.blocks = (unsigned)((pairs + 15) / 16);
+            x.blocks = (unsigned)((pairs + xp - 1) / xp);
         }
         if (p->fast_x) {  // half-length complex transform, 16 lines per tile, persistent blocks
             x.kind = dir == 0 ? pf::PASS_R2C_P2 : pf::PASS_C2R_P2;

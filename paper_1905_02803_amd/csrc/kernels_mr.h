@@ -116,6 +116,11 @@ struct DftMR {
 #ifndef PF_MR_SPZ_RES
 #define PF_MR_SPZ_RES 2
 #endif
+// X kernels: line pairs per tile (a power of two; the lines' workspace rows are
+// separate, so the tile width does not change the row accesses)
+#ifndef PF_MR_XP
+#define PF_MR_XP 4
+#endif
 // C2C kernel: two step-1 items per thread for strongly unbalanced factor pairs
 #ifndef PF_MR_HALF
 #define PF_MR_HALF 1
@@ -166,6 +171,10 @@ __host__ __device__ constexpr int mr_c2c_cols(int n1, int n2) {
     return PF_MR_HALF && n2 >= 2 * n1 && n2 >= 24 && half < full ? half : full;
 }
 __host__ __device__ constexpr int mr_c2c_threads(int n1, int n2) { return 16 * mr_c2c_cols(n1, n2); }
+// X kernels: PF_MR_XP pairs x max(N1, N2) items, whole waves
+__host__ __device__ constexpr int mr_x_threads(int n1, int n2) {
+    return (PF_MR_XP * (n1 > n2 ? n1 : n2) + 63) / 64 * 64;
+}
 
 template <int N1, int N2>
 struct MrShape {
@@ -176,9 +185,12 @@ struct MrShape {
     // step-2 reads of consecutive rows fall on different banks
     static constexpr int P2 = N2 % 2 == 0 ? N2 + 1 : N2;
     static constexpr int XCH = 16 * N1 * P2;
-    // X passes: one complex line per column at pitch SP (= 16 mod 32, >= N)
+    // X passes: XP line pairs per tile, XTHREADS threads; one complex line per
+    // pair at pitch SP (= 16 mod 32, >= N)
+    static constexpr int XP = PF_MR_XP;
+    static constexpr int XTHREADS = mr_x_threads(N1, N2);
     static constexpr int SP = N + ((16 - N % 32) % 32 + 32) % 32;
-    static constexpr int XLDS = XCH > 16 * SP ? XCH : 16 * SP;
+    static constexpr int XLDS = XP * N1 * P2 > XP * SP ? XP * N1 * P2 : XP * SP;
     // C2C pass with a line side: line-major tile copy at pitch SPZ (= PF_MR_SPZ_RES
     // mod 32, >= N), written and read by lanes along the columns
     static constexpr int SPZ = N + ((PF_MR_SPZ_RES - N % 32) % 32 + 32) % 32;
@@ -330,7 +342,7 @@ __device__ __forceinline__ void mr_c2c_body(const MrC2C &t) {
     }
 }
 
-// ---- X passes: 16 pairs of real lines per tile ---------------------------------
+// ---- X passes: PF_MR_XP pairs of real lines per tile ----------------------------
 struct MrX {
     const void *in;
     void *out;
@@ -344,7 +356,7 @@ __device__ __forceinline__ MrX mr_x_args(const PassArgs &a, const void *inp, voi
     t.in = inp;
     t.out = outp;
     t.tw = reinterpret_cast<const cx<float> *>(a.tw);
-    t.g0 = tile * 32;
+    t.g0 = tile * (2 * PF_MR_XP);
     t.lines = a.lines;
     t.ld_real = a.ld_real;
     t.ny = a.ny;
@@ -356,11 +368,11 @@ __device__ __forceinline__ MrX mr_x_args(const PassArgs &a, const void *inp, voi
     return t;
 }
 
-// row offset (workspace, column block 0) of the 32 lines of the tile: line
-// g = z ny + y starts at row z zrows + y0 + y
+// row offset (workspace, column block 0) of the 2 PF_MR_XP lines of the tile:
+// line g = z ny + y starts at row z zrows + y0 + y
 __device__ __forceinline__ void mr_rowoff(const MrX &t, long long *rowoff) {
     const int tid = threadIdx.x;
-    if (tid < 32) {
+    if (tid < 2 * PF_MR_XP) {
         const long long g = t.g0 + tid;
         const long long z = g / t.ny;
         const long long y = g - z * t.ny;
@@ -373,13 +385,13 @@ template <int N1, int N2>
 __device__ __forceinline__ void mr_r2c_body(const MrX &t) {
     using S = MrShape<N1, N2>;
     constexpr int N = S::N;
-    __shared__ long long rowoff[32];
+    __shared__ long long rowoff[2 * PF_MR_XP];
     cx<float> *lds = reinterpret_cast<cx<float> *>(pf_smem);
     const int tid = threadIdx.x;
     mr_rowoff(t, rowoff);
     const float *__restrict__ in = reinterpret_cast<const float *>(t.in);
     cx<float> *__restrict__ out = reinterpret_cast<cx<float> *>(t.out);
-    if (tid < 16 * N2) {  // step 1, item (c, q): lanes along the points of the lines
+    if (tid < S::XP * N2) {  // step 1, item (c, q): lanes along the points of the lines
         const int c = tid / N2, q = tid - c * N2;
         const long long ga = t.g0 + 2 * c;
         cx<float> x[N1];
@@ -404,22 +416,22 @@ __device__ __forceinline__ void mr_r2c_body(const MrX &t) {
     __syncthreads();
     cx<float> y[N2];
     const int c2 = tid / N1, k1 = tid - c2 * N1;
-    if (tid < 16 * N1) {  // step 2, item (c, k1)
+    if (tid < S::XP * N1) {  // step 2, item (c, k1)
 #pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) y[n2] = lds[(c2 * N1 + k1) * S::P2 + n2];
         DftMR<N2, -1>::run(y);
     }
     __syncthreads();  // the exchange tile is read before the spectra overwrite it
-    if (tid < 16 * N1) {
+    if (tid < S::XP * N1) {
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) lds[c2 * S::SP + k1 + N1 * k2] = y[k2];
     }
     __syncthreads();
     // split Z = A + i B into the half spectra of the two lines, row by row:
     // mode (kb, cc, kk), lanes along the 16 modes of a row
-    const int total = t.nkb * 256;
-    for (int f = tid; f < total; f += S::THREADS) {
-        const int kk = f & 15, cc = (f >> 4) & 15, kb = f >> 8;
+    const int total = t.nkb * 16 * S::XP;
+    for (int f = tid; f < total; f += S::XTHREADS) {
+        const int kk = f & 15, cc = (f >> 4) & (S::XP - 1), kb = f / (16 * S::XP);
         const int k = kb * 16 + kk;
         const long long ga = t.g0 + 2 * cc;
         if (k < t.nxh && ga < t.lines) {
@@ -438,7 +450,7 @@ __device__ __forceinline__ void mr_c2r_body(const MrX &t) {
     using S = MrShape<N1, N2>;
     constexpr int N = S::N;
     constexpr int EH = 4;  // rows in flight per thread before the LDS writes
-    __shared__ long long rowoff[32];
+    __shared__ long long rowoff[2 * PF_MR_XP];
     cx<float> *lds = reinterpret_cast<cx<float> *>(pf_smem);
     const int tid = threadIdx.x;
     mr_rowoff(t, rowoff);
@@ -447,14 +459,14 @@ __device__ __forceinline__ void mr_c2r_body(const MrX &t) {
     float *__restrict__ out = reinterpret_cast<float *>(t.out);
     // Z = A + i B on the whole line: modes k < nxh from the rows, the rest by
     // Hermitian symmetry; the imaginary parts of modes 0 and N / 2 are dropped
-    const int total = t.nkb * 256;
-    for (int f1 = tid; f1 < total; f1 += EH * S::THREADS) {
+    const int total = t.nkb * 16 * S::XP;
+    for (int f1 = tid; f1 < total; f1 += EH * S::XTHREADS) {
         cx<float> ra[EH], rb[EH];
 #pragma unroll
         for (int i = 0; i < EH; ++i) {
             ra[i] = rb[i] = make_float2(0.f, 0.f);
-            const int f = f1 + i * S::THREADS;
-            const int kk = f & 15, cc = (f >> 4) & 15, kb = f >> 8;
+            const int f = f1 + i * S::XTHREADS;
+            const int kk = f & 15, cc = (f >> 4) & (S::XP - 1), kb = f / (16 * S::XP);
             const int k = kb * 16 + kk;
             const long long ga = t.g0 + 2 * cc;
             if (f < total && k < t.nxh && ga < t.lines) {
@@ -465,8 +477,8 @@ __device__ __forceinline__ void mr_c2r_body(const MrX &t) {
         }
 #pragma unroll
         for (int i = 0; i < EH; ++i) {
-            const int f = f1 + i * S::THREADS;
-            const int kk = f & 15, cc = (f >> 4) & 15, kb = f >> 8;
+            const int f = f1 + i * S::XTHREADS;
+            const int kk = f & 15, cc = (f >> 4) & (S::XP - 1), kb = f / (16 * S::XP);
             const int k = kb * 16 + kk;
             if (f < total && k < t.nxh) {
                 const cx<float> A = ra[i], B = rb[i];
@@ -483,7 +495,7 @@ __device__ __forceinline__ void mr_c2r_body(const MrX &t) {
     __syncthreads();
     const int c = tid / N2, q = tid - c * N2;
     cx<float> x[N1];
-    if (tid < 16 * N2) {  // step 1, item (c, q)
+    if (tid < S::XP * N2) {  // step 1, item (c, q)
 #pragma unroll
         for (int m = 0; m < N1; ++m) x[m] = lds[c * S::SP + q + N2 * m];
         DftMR<N1, 1>::run(x);
@@ -495,12 +507,12 @@ __device__ __forceinline__ void mr_c2r_body(const MrX &t) {
         }
     }
     __syncthreads();  // the lines are read before the exchange tile overwrites them
-    if (tid < 16 * N2) {
+    if (tid < S::XP * N2) {
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) lds[(c * N1 + k1) * S::P2 + q] = x[k1];
     }
     __syncthreads();
-    if (tid < 16 * N1) {  // step 2, item (c, k1): real parts to line 2c, imaginary to 2c + 1
+    if (tid < S::XP * N1) {  // step 2, item (c, k1): real parts to line 2c, imaginary to 2c + 1
         const int c2 = tid / N1, k1 = tid - c2 * N1;
         cx<float> y[N2];
 #pragma unroll
@@ -554,7 +566,7 @@ __global__ __launch_bounds__(mr_c2c_threads(N1, N2)) void k_mr_c2c(MrArgs m) {
 }
 
 template <int N1, int N2, int FWD>
-__global__ __launch_bounds__(mr_threads(N1, N2)) void k_mr_x(MrArgs m) {
+__global__ __launch_bounds__(mr_x_threads(N1, N2)) void k_mr_x(MrArgs m) {
     const long long blk = blockIdx.x;
     MrX t;
     if (m.b.count == 0) {
@@ -596,7 +608,7 @@ __global__ __launch_bounds__(mr_threads(N1, N2)) void k_mr_x(MrArgs m) {
 // 2 forward X (real to half spectra), 3 backward X
 template <int N1, int N2>
 const void *mr_kernel_of(int what) {
-    static_assert(MrShape<N1, N2>::XLDS * 8 + 32 * 8 <= 65536 && MrShape<N1, N2>::CLDS * 8 <= 65536,
+    static_assert(MrShape<N1, N2>::XLDS * 8 + 2 * PF_MR_XP * 8 <= 65536 && MrShape<N1, N2>::CLDS * 8 <= 65536,
                   "tile within the default dynamic LDS limit");
     switch (what) {
         case 0: return reinterpret_cast<const void *>(&k_mr_c2c<N1, N2, -1>);

@@ -51,8 +51,10 @@ bool mr_supported(int n, int prec) {
 int mr_threads_of(int n, int xpass) {
     int a = 0, b = 0;
     if (!mr_factors(n, &a, &b)) return 0;
-    return xpass ? mr_threads(a, b) : mr_c2c_threads(a, b);
+    return xpass ? mr_x_threads(a, b) : mr_c2c_threads(a, b);
 }
+
+int mr_x_pairs() { return PF_MR_XP; }
 
 size_t mr_lds_bytes(int n, int xpass) {
     // the kernels' own tile constants, so that host and device sizes agree

@@ -209,10 +209,11 @@ hipError_t p2_fused_launch(const FusedArgs &f, int fwd, int nx, int ny, unsigned
 
 // Compile-time mixed-radix passes, FP32 (kernels_mr.hip): the C2C column pass
 // (PASS_C2C_MR, 16 columns per tile, a.tc_log2 = 4) and the X passes
-// (PASS_R2C_MR / PASS_C2R_MR, 16 line pairs per tile) of a length n the table
+// (PASS_R2C_MR / PASS_C2R_MR, mr_x_pairs() line pairs per tile) of a length n the table
 // holds; one tile per workgroup.  a.tw: W_n^m, m < n (forward sign).
 bool mr_supported(int n, int prec);
 int mr_threads_of(int n, int xpass);  // threads per workgroup of the C2C (xpass 0) or X kernel
+int mr_x_pairs();                     // line pairs per X tile (a power of two)
 size_t mr_lds_bytes(int n, int xpass);
 hipError_t mr_launch(const PassDesc &d, hipStream_t s);
 hipError_t mr_launch_batch(const BatchLaunch &L, hipStream_t s);
