@@ -387,17 +387,20 @@ int pf_spectral_step(pf_plan *p, const void *in, void *spec, void *out, int adjo
 /*
  * Many independent 3D transforms of different sizes run together (the same
  * method per transform, Sec. 2; the paper's "any grid dimensions", Sec. 3.1).
- * Each transform uses the generic kernels (runtime mixed-radix plans).  A
- * fused pass is one kernel launch per distinct block size among the
- * transforms' passes, over the tiles of every transform of that size (a
- * device table maps each workgroup to its transform), so a direction takes
- * at most three launches per block size whatever the count (block sizes are
- * powers of two up to 512).
+ * An axis whose length has a compile-time mixed-radix kernel (the 7-smooth
+ * lengths 48 .. 320 but 256, and 360, 480; FP32) runs that kernel; every
+ * other axis runs the runtime-radix kernels (the power-of-two kernels, whose
+ * persistent grids are sized per transform, are not used in a batch).  A
+ * fused pass is one kernel launch per group of transforms that share a
+ * kernel -- the runtime-radix passes grouped by block size, the mixed-radix
+ * passes by length -- over the tiles of every transform of the group (a
+ * device table maps each workgroup to its transform).
  *
  * pf_tune: per axis (x, y, z) a radix order (0: radix 16 first, then 8, 4, 2,
  * 3, 5, 7; 1: 8, 4, 2, 3, 5, 7; 2: 4, 2, 3, 5, 7; 3: 3, 5, 7 first, then 16,
  * 8, 4, 2) and a tile width (0: the default, else at most that many line
- * pairs per X tile or columns per Y / Z tile).  Chosen per transform by the
+ * pairs per X tile or columns per Y / Z tile; below 16 it selects the
+ * runtime-radix kernel for that axis).  Chosen per transform by the
  * package's autotuner; NULL means defaults.
  */
 typedef struct pf_tune {
