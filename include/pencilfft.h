@@ -295,6 +295,21 @@ int pf_run_pass(pf_plan *p, int dir, int pass, const void *in, void *out, void *
 const char *pf_pass_name(const pf_plan *p, int dir, int pass);
 
 /*
+ * Layout of the workspace between the transform passes of direction dir:
+ * PF_WS_BLOCKED, the [nz][nkb][ny][B] rows above, or PF_WS_TRANSPOSED,
+ * complex [nz][nxh][ny] (mode kx of line (y, z) at [z][kx][y]: 128-byte rows
+ * of 16 lines at one mode).  The backward chain of an FP32 plain STRIDE1
+ * 1 x 1 plan with nx in {512, 1024, 2048} and ny a multiple of 16 up to 512
+ * uses the transposed form: its Z pass reads 16 adjacent Z-pencil lines per tile, its
+ * Y pass runs in place along contiguous lines, its X pass reads the rows of
+ * 16 lines (the same two transposes of Sec. 2, placed differently).  Returns
+ * PF_EINVAL for a NULL plan or a bad dir.
+ */
+#define PF_WS_BLOCKED 0
+#define PF_WS_TRANSPOSED 1
+int pf_workspace_layout(const pf_plan *p, int dir);
+
+/*
  * Kernel family that runs pass `pass` of direction `dir` (a short static
  * string, "" for an invalid plan / dir / pass): "c2c_generic", "r2c_generic",
  * "c2r_generic" (radix plan read at run time, Sec. 2's 1D transforms as a

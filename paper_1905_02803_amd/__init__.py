@@ -38,6 +38,7 @@ PF_PENCIL_X, PF_PENCIL_Y, PF_PENCIL_Z = 0, 1, 2
 PF_DIR_FORWARD, PF_DIR_BACKWARD = 0, 1
 PF_BATCH_SERIAL, PF_BATCH_FUSED, PF_BATCH_GRAPH, PF_BATCH_STREAMS = 0, 1, 2, 4
 PF_BATCH_NSTREAMS = 4
+PF_WS_BLOCKED, PF_WS_TRANSPOSED = 0, 1
 PF_PROBE_COPY, PF_PROBE_TILES, PF_PROBE_TILES_INPLACE = 0, 1, 2
 
 EXPORTED = (
@@ -46,7 +47,7 @@ EXPORTED = (
     "pf_run_pass", "pf_pass_name", "pf_pass_bytes", "pf_set_timing", "pf_get_timing", "pf_copy",
     "pf_batch_setup", "pf_batch_offset", "pf_batch_bytes", "pf_batch_set_mode", "pf_batch_ftran_r2c",
     "pf_batch_btran_c2r", "pf_batch_destroy", "pf_spectral_step", "pf_exec_noalloc", "pf_check_status",
-    "pf_probe", "pf_pass_kernel",
+    "pf_probe", "pf_pass_kernel", "pf_workspace_layout",
 )
 
 
@@ -119,6 +120,7 @@ def lib():
             "pf_run_pass": (i, [vp, i, i, vp, vp, vp]),
             "pf_pass_name": (ctypes.c_char_p, [vp, i, i]),
             "pf_pass_kernel": (ctypes.c_char_p, [vp, i, i]),
+            "pf_workspace_layout": (i, [vp, i]),
             "pf_pass_bytes": (ctypes.c_double, [vp, i, i]),
             "pf_set_timing": (i, [vp, i]),
             "pf_copy": (i, [vp, vp, sz, vp]),
@@ -230,6 +232,12 @@ def pf_pass_name(h, direction: int, pass_index: int) -> str:
 
 def pf_pass_kernel(h, direction: int, pass_index: int) -> str:
     return lib().pf_pass_kernel(h, direction, pass_index).decode()
+
+
+def pf_workspace_layout(h, direction: int) -> int:
+    r = lib().pf_workspace_layout(h, direction)
+    _raise(r if r < 0 else 0, "pf_workspace_layout")
+    return r
 
 
 def pf_pass_bytes(h, direction: int, pass_index: int) -> float:
@@ -394,6 +402,9 @@ class Plan:
 
     def pass_kernel(self, direction: int, index: int) -> str:
         return pf_pass_kernel(self.handle, direction, index)
+
+    def workspace_layout(self, direction: int) -> int:
+        return pf_workspace_layout(self.handle, direction)
 
     def pass_bytes(self, direction: int, index: int) -> float:
         return pf_pass_bytes(self.handle, direction, index)
@@ -595,6 +606,12 @@ def workspace_to_half_spectrum(ws, nx: int, ny: int, nz: int):
     nkb = (nxh + B - 1) // B
     w = ws[: nz * nkb * ny * B].reshape(nz, nkb, ny, B).permute(0, 2, 1, 3).reshape(nz, ny, nkb * B)
     return w[:, :, :nxh]
+
+
+def transposed_workspace_to_half_spectrum(ws, nx: int, ny: int, nz: int):
+    """View a transposed workspace (PF_WS_TRANSPOSED: [nz][nxh][ny]) as [nz][ny][nxh]; for tests."""
+    nxh = nx // 2 + 1
+    return ws[: nz * nxh * ny].reshape(nz, nxh, ny).permute(0, 2, 1)
 
 
 def half_spectrum_to_workspace(U, ws):

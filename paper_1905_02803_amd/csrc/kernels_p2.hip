@@ -1250,7 +1250,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
 
 // The backward X stage split like R2cP2 (loads of one tile's spectra, inverse
 // split, transform and stores of one tile).
-template <int M, int MT>
+template <int M, int MT, bool TR = false>
 struct C2rP2 {
     static constexpr int TC = 16;
     static constexpr int T = M / 16;
@@ -1305,6 +1305,28 @@ struct C2rP2 {
     // xk[2 i], xk[2 i + 1]: X[k] of the item's two lines; xm likewise X[M - k]
     __device__ __forceinline__ void load(cx<float> (&xk)[2 * NIT], cx<float> (&xm)[2 * NIT], float2 &xh, int t,
                                          int tv) const {
+        if constexpr (TR) {
+            // transposed rows: mode k of line g = z ny + y at z zrows + k kbrows + y
+            // (zrows = nxh nyp, kbrows = nyp: 128-byte rows of 16 lines at one
+            // mode).  The tile's 16 lines share a plane (ny is a multiple of 16).
+            // Item f: line l = f & 15 (lanes along the lines of a row), mode
+            // k = f >> 4 (k < M/2); it holds X[k] and X[M-k] of that line, and
+            // threads 0..15 hold X[M/2] of line tv.
+            const int g0 = 16 * t;
+            const int z0 = g0 / a.ny;
+            const int y0 = g0 - z0 * a.ny;
+            const cx<float> *tb = in + (long long)z0 * a.zrows + y0;
+            const long long ks = a.kbrows;
+#pragma unroll
+            for (int i = 0; i < 2 * NIT; ++i) {
+                const int f = tv + NT * i;
+                const int l = f & 15, k = f >> 4;
+                xk[i] = gld<streamed<LD_C2R>()>(tb + k * ks + l);
+                xm[i] = gld<streamed<LD_C2R>()>(tb + (M - k) * ks + l);
+            }
+            if (tv < 16) xh = gld<streamed<LD_C2R>()>(tb + (M / 2) * ks + tv);
+            return;
+        }
         const int g0 = 16 * t;
         const int z0 = g0 / a.ny;
         const int y0 = g0 - z0 * a.ny;
@@ -1350,6 +1372,19 @@ struct C2rP2 {
     // The caller synchronises before the transform reads the tile.
     __device__ __forceinline__ void split(const cx<float> (&pk)[2 * NIT], const cx<float> (&pm)[2 * NIT], float2 ph,
                                           int tv) const {
+        if constexpr (TR) {  // one line per item: its half of the slot of its line pair
+            float2 *b2 = reinterpret_cast<float2 *>(buf);
+#pragma unroll
+            for (int i = 0; i < 2 * NIT; ++i) {
+                const int f = tv + NT * i;
+                const int l = f & 15, k = f >> 4;
+                float2 Ak = pk[i], Am = pm[i];
+                if (k == 0) Ak.y = Am.y = 0.f;
+                const cx<float> w = spl[k];
+                b2[2 * p2_slot<TC>(k, l >> 1) + (l & 1)] = zb(Ak, Am, make_float2(w.x, -w.y));
+                if (k != 0) b2[2 * p2_slot<TC>(M - k, l >> 1) + (l & 1)] = zb(Am, Ak, make_float2(-w.x, -w.y));
+            }
+        } else {
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int f = tv + NT * i;
@@ -1365,6 +1400,7 @@ struct C2rP2 {
                 const float2 wm = make_float2(-w.x, -w.y);
                 buf[p2_slot<TC>(M - k, pr)] = pack2(zb(Am, Ak, wm), zb(Bm, Bk, wm));
             }
+        }
         }
         if (tv < 16) {
             const cx<float> w = spl[M / 2];
@@ -1436,9 +1472,9 @@ struct C2rP2 {
     }
 };
 
-template <int M, int MT>
+template <int M, int MT, bool TR = false>
 __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
-    typedef C2rP2<M, MT> K;
+    typedef C2rP2<M, MT, TR> K;
     float4 *buf = reinterpret_cast<float4 *>(pf_smem);
     K k(a, buf, reinterpret_cast<cx<float> *>(buf + M * K::CP));
     k.init_tables(threadIdx.x, K::NT);
@@ -1835,9 +1871,10 @@ size_t p2x_lds_bytes(int nx, int math) {
     return (size_t)M * 16 * sizeof(float2) + (size_t)(2 * M + 2) * sizeof(float2) + (math ? kMfmaTableBytes : 0);
 }
 
-static const void *p2x_pick(int nx, int fwd, int mt) {
+static const void *p2x_pick(int nx, int fwd, int mt, int tr = 0) {
 #define PF_X_PICK(NXV, MV)                                                                    \
     if (nx == NXV) {                                                                          \
+        if (tr) return !fwd && mt == 0 ? (const void *)&k_c2r_p2<MV, 0, true> : nullptr;     \
         if (mt == 0) return fwd ? (const void *)&k_r2c_p2<MV, 0> : (const void *)&k_c2r_p2<MV, 0>; \
         if (MV < 512) return nullptr;                                                         \
         if (mt == 1) return fwd ? (const void *)&k_r2c_p2<MV, MV < 512 ? 0 : 1>               \
@@ -1854,10 +1891,11 @@ static const void *p2x_pick(int nx, int fwd, int mt) {
 hipError_t p2x_prepare(int nx) {
     hipError_t e = hipSuccess;
     for (int fwd : {0, 1})
-        for (int mt = 0; mt < 3; ++mt) {
-        const void *k = p2x_pick(nx, fwd, mt);
+        for (int mt = 0; mt < 4; ++mt) {  // mt 3: the transposed-row backward kernel (plain)
+        const void *k = mt < 3 ? p2x_pick(nx, fwd, mt) : p2x_pick(nx, fwd, 0, 1);
         if (!k) continue;
-        hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, mt));
+        hipError_t r =
+            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, mt < 3 ? mt : 0));
         if (r != hipSuccess && e == hipSuccess) e = r;
         }
     return e;
@@ -1917,6 +1955,9 @@ static const void *p2_pick_io_dir(int inp, int outp) {
     if (inp == 1 && outp == 0) return p2_kernel<N, TC, DIR, 1, 0, MT>();
     if (inp == 0 && outp == 2) return p2_kernel<N, TC, DIR, 0, 2, MT>();
     if (inp == 2 && outp == 0) return p2_kernel<N, TC, DIR, 2, 0, MT>();
+    if constexpr (DIR > 0 && MT == 0) {  // lines in place: the backward Y pass on the transposed workspace
+        if (inp == 1 && outp == 1) return p2_kernel<N, TC, DIR, 1, 1, MT>();
+    }
     return nullptr;
 }
 
@@ -1963,7 +2004,7 @@ static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
 const void *p2_symbol(const PassDesc &d) {
     if (d.kind == PASS_C2C_P2 && d.prec == 1) return p2d_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
     if (d.kind == PASS_R2C_P2) return p2x_pick(2 * d.a.fft.n, 1, d.a.math);
-    if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0, d.a.math);
+    if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0, d.a.math, d.a.xtr);
     return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);
 }
 
@@ -2016,9 +2057,9 @@ bool p2_has_mfma(int n) { return n == 512 || n == 1024; }
 hipError_t p2_prepare(int n) {
     hipError_t e = hipSuccess;
     for (int dir : {-1, 1})
-        for (int io = 0; io < 25; ++io) {
-            const int mt = io / 5, k5 = io % 5;  // (inp, outp): (0,0) (0,1) (1,0) (0,2) (2,0)
-            const int inp = k5 == 2 ? 1 : k5 == 4 ? 2 : 0, outp = k5 == 1 ? 1 : k5 == 3 ? 2 : 0;
+        for (int io = 0; io < 30; ++io) {
+            const int mt = io / 6, k6 = io % 6;  // (inp, outp): (0,0) (0,1) (1,0) (0,2) (2,0) (1,1)
+            const int inp = k6 == 2 || k6 == 5 ? 1 : k6 == 4 ? 2 : 0, outp = k6 == 1 || k6 == 5 ? 1 : k6 == 3 ? 2 : 0;
             const void *k = p2_pick(n, dir, inp, outp, mt);
             if (!k) continue;
             hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2_lds_bytes(n, mt));

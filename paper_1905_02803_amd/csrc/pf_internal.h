@@ -120,6 +120,8 @@ struct PassArgs {
     int ny, nkb, b_log2, nxh;
     int y0;
     long long zrows, kbrows;
+    int xtr;  // backward power-of-two X pass: 1 = transposed rows, mode k of line (y, z) at
+              // z zrows + k kbrows + y (rows of 16 lines at one mode; ny a multiple of 16)
 };
 
 struct PassDesc {

@@ -158,6 +158,7 @@ int main() {
     CHECK(pf_run_pass(nullptr, 0, 0, nullptr, nullptr, nullptr) == PF_EINVAL);
     CHECK(pf_pass_name(nullptr, 0, 0) != nullptr);
     CHECK(pf_pass_kernel(nullptr, 0, 0) != nullptr && pf_pass_kernel(nullptr, 0, 0)[0] == 0);
+    CHECK(pf_workspace_layout(nullptr, PF_DIR_BACKWARD) == PF_EINVAL);
     CHECK(pf_pass_bytes(nullptr, 0, 0) == 0.0);
     CHECK(pf_set_timing(nullptr, 1) == PF_EINVAL);
     double ms;

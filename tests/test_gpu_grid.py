@@ -54,6 +54,7 @@ CASES = [
     ((128 // 4, 128 // 4, 128 // 4), (2, 3)),   # 6 tasks, uneven in every pencil
     ((16, 512, 36), (1, 8)),    # slab 1 x P, power-of-two Y
     ((9, 7, 15), (5, 2)),
+    ((50, 48, 60), (2, 3)),     # every axis on the compile-time mixed-radix kernels (FP32)
 ]
 
 
