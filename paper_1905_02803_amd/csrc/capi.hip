@@ -305,6 +305,11 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
 // ny nz elements apart) and is faster when concurrently resident tiles spread
 // over ky (order 1); the forward Z pass, which writes those lines, is faster
 // in order 0.
+// largest ny for which plans take the transposed backward chain (measured:
+// faster up to 512, slower at 1024)
+#ifndef PF_BWD_TR_MAX_NY
+#define PF_BWD_TR_MAX_NY 512
+#endif
 #ifndef PF_TILE_ORDER_FZ
 #define PF_TILE_ORDER_FZ 0
 #endif
@@ -1130,7 +1135,7 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     p->ws_bytes = p->w_bytes;
     p->bwd_tr = !o.no_bwd_tr && p->fast_x && l->stride1 && !p->share && !p->blocked && !p->fused &&
                 l->third == PF_THIRD_FFT && l->precision == PF_F32 && l->math == PF_PLAIN && ny % 16 == 0 &&
-                ny <= 512;
+                ny <= PF_BWD_TR_MAX_NY;
     if (p->share) {
         p->ws_bytes += (size_t)p->nxh * ny * nz * p->csize;
     } else if (p->blocked) {
