@@ -319,6 +319,11 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
 #ifndef PF_TILE_ORDER_Y
 #define PF_TILE_ORDER_Y 0
 #endif
+// mixed-radix Z passes: order 1 (ky fastest) measured within 1% of order 0 at
+// 480 x 360 x 250, 320^3 and on the 64-transform batch
+#ifndef PF_TILE_ORDER_MRZ
+#define PF_TILE_ORDER_MRZ 0
+#endif
 #ifndef PF_XCD_UROWS
 #define PF_XCD_UROWS 1
 #endif
@@ -693,6 +698,7 @@ void build_passes(pf_plan *p) {
         // walking column blocks first, so that neighbouring tiles (on one XCD)
         // share the cache lines the rows straddle
         z.a.tile_order = dir == 0 ? PF_TILE_ORDER_FZ : (p->lay.stride1 ? PF_TILE_ORDER_BZ : 0);
+        if (z.kind == pf::PASS_C2C_MR) z.a.tile_order = PF_TILE_ORDER_MRZ;
         z.blocks = c2c_grid(p, z);
 
         if (dir == 1 && p->bwd_tr) {

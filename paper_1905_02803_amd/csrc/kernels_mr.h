@@ -219,9 +219,11 @@ __device__ __forceinline__ long long mr_side_base(const Side &s, long long a, in
 // tile `tile` of the C2C pass a (16 columns per tile), reading inp, writing outp
 __device__ __forceinline__ MrC2C mr_c2c_args(const PassArgs &a, const void *inp, void *outp, long long tile) {
     MrC2C t;
-    const int CB = (int)a.CB;
-    const int ta = (int)tile / CB;
-    const int cb = (int)tile - ta * CB;
+    // tile order 1 walks the outer index fastest (neighbouring tiles then touch
+    // adjacent rows and lines of sides whose column blocks lie far apart)
+    const int CB = (int)a.CB, A = (int)a.A;
+    const int ta = a.tile_order ? (int)tile % A : (int)tile / CB;
+    const int cb = a.tile_order ? (int)tile / A : (int)tile - ta * CB;
     t.in = reinterpret_cast<const cx<float> *>(inp);
     t.out = reinterpret_cast<cx<float> *>(outp);
     t.tw = reinterpret_cast<const cx<float> *>(a.tw);
