@@ -44,6 +44,12 @@ def parse():
     ap.add_argument("--kt-summary", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
                     help="write the per-kernel summaries under profiles/ from a rocprofv3 kernel trace of this "
                          "benchmark (COMMAND: the rocprofv3 command that produced it), then exit")
+    ap.add_argument("--mfma-workload", action="store_true",
+                    help="run only the plain and matrix-core FP32 plans at the grid edge --n (one warm-up and "
+                         "--steps pairs each), for a rocprofv3 --pmc run with MFMA_COUNTERS, then exit")
+    ap.add_argument("--mfma-summary", nargs=2, metavar=("COUNTER_CSV", "COMMAND"),
+                    help="write profiles/counters_mfma_fft.txt from a rocprofv3 --pmc run of --mfma-workload, "
+                         "then exit")
     ap.add_argument("--sq-summary", nargs=2, metavar=("COUNTER_CSV", "COMMAND"),
                     help="write profiles/counters_sq_fft.txt from a rocprofv3 --pmc run of this benchmark with "
                          "the SQ instruction counters (COMMAND: the rocprofv3 command that produced it), then exit")
@@ -188,6 +194,73 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_W
                "SQ_INSTS_SALU", "SQ_BUSY_CYCLES", "SQ_ACTIVE_INST_VALU")
 # MI355X: 256 CUs of 4 SIMDs; without packed FP32 a wave64 VALU instruction holds its SIMD 4 cycles
 VALU_SIMDS, VALU_CYCLES_PER_INST, CLOCK_GHZ = 1024, 4, 2.4
+
+
+MFMA_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_MFMA", "SQ_VALU_MFMA_BUSY_CYCLES",
+                 "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def mfma_workload(n: int, steps: int) -> None:
+    """The plain, FP16x2 and BF16x2 plans at n^3: one warm-up pair and `steps` pairs each."""
+    import torch
+
+    import paper_1905_02803_amd as pf
+
+    u = torch.empty((n, n, n), device="cuda", dtype=torch.float32).uniform_(-1.0, 1.0)
+    for math_ in (pf.PF_PLAIN, pf.PF_MFMA_FP16X2, pf.PF_MFMA_BF16X2):
+        plan = pf.Plan(n, n, n, pf.Layout(math=math_))
+        U = plan.empty_complex()
+        r = plan.empty_real()
+        for _ in range(1 + steps):
+            plan.ftran(u, U)
+            plan.btran(U, r)
+        torch.cuda.synchronize()
+        plan.destroy()
+        print(f"bench: mfma workload, math {math_} done", file=sys.stderr, flush=True)
+
+
+def summarize_mfma(counter_csv: str, command: str) -> None:
+    """profiles/counters_mfma_fft.txt from a rocprofv3 --pmc run of --mfma-workload with MFMA_COUNTERS.
+
+    Per kernel, per-dispatch averages: MFMA instructions per wave, the fraction of the SIMDs' active cycles
+    the matrix cores were busy (rocprofv3's MfmaUtil: SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE of one
+    XCD x 1024 SIMDs); the counter CSV holds GRBM_GUI_ACTIVE summed over the 8 XCDs), VALU and LDS
+    instructions per wave, and the dispatch duration under counter collection.
+    """
+    import csv
+
+    disp = {}
+    for r in csv.DictReader(open(counter_csv)):
+        d = disp.setdefault(int(r["Dispatch_Id"]), {
+            "name": r["Kernel_Name"], "ms": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6, "c": {}})
+        d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    by = {}
+    for d in disp.values():
+        if "pf::k_" in d["name"] and "k_copy" not in d["name"]:
+            by.setdefault(d["name"], []).append(d)
+    lines = ["rocprofv3 matrix-core counters per dispatch, 1024^3 FP32 plans: plain (<.., 0>), FP16x2 (<.., 1>) "
+             "and BF16x2 (<.., 2>), MI355X",
+             f"command: {command}",
+             "counters: " + " ".join(MFMA_COUNTERS),
+             "mfma/wave, valu/wave, lds/wave: instructions per wave; mfma busy: SQ_VALU_MFMA_BUSY_CYCLES / "
+             f"(GRBM_GUI_ACTIVE / 8 XCDs x {VALU_SIMDS} SIMDs) in %; avg ms: duration under counter collection",
+             "",
+             f"{'kernel':60s} {'calls':>5s} {'avg ms':>7s} {'mfma/wave':>9s} {'mfma busy':>9s} {'valu/wave':>9s} "
+             f"{'lds/wave':>8s}"]
+    for name, ds in sorted(by.items(), key=lambda kv: kv[0]):
+        def avg(c):
+            return sum(d["c"].get(c, 0.0) for d in ds) / len(ds)
+        waves = avg("SQ_WAVES") or 1.0
+        gui = (avg("GRBM_GUI_ACTIVE") or 8.0) / 8.0  # one XCD's active cycles
+        busy = 100.0 * avg("SQ_VALU_MFMA_BUSY_CYCLES") / (gui * VALU_SIMDS)
+        n = name if len(name) <= 60 else name[:57] + "..."
+        lines.append(f"{n:60s} {len(ds):5d} {sum(d['ms'] for d in ds) / len(ds):7.3f} "
+                     f"{avg('SQ_INSTS_MFMA') / waves:9.1f} {busy:8.2f}% {avg('SQ_INSTS_VALU') / waves:9.1f} "
+                     f"{avg('SQ_INSTS_LDS') / waves:8.1f}")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "counters_mfma_fft.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote profiles/counters_mfma_fft.txt")
 
 
 def summarize_sq(counter_csv: str, command: str) -> None:
@@ -833,6 +906,12 @@ def main():
         return
     if args.sq_summary:
         summarize_sq(args.sq_summary[0], args.sq_summary[1])
+        return
+    if args.mfma_summary:
+        summarize_mfma(args.mfma_summary[0], args.mfma_summary[1])
+        return
+    if args.mfma_workload:
+        mfma_workload(args.n, args.steps)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "

@@ -141,3 +141,25 @@ def test_sq_summary_normalises_by_each_sections_grid(tmp_root):
     assert "k_fill" not in text  # the share-only leg is not summarised
     # the batch has no fixed grid: no per-element figure
     assert row("void pf::k_c2c_tile_b", "batched")[-4] == "-"
+
+
+def test_mfma_summary_per_wave_and_busy_fraction(tmp_root):
+    """MFMA instructions per wave and busy fraction against one XCD's active cycles (the CSV holds
+    GRBM_GUI_ACTIVE summed over 8 XCDs)."""
+    name = "void pf::k_c2c_p2<1024, 16, -1, 0, 0, 1>(pf::PassArgs)"
+    vals = {"SQ_WAVES": 2048.0, "SQ_INSTS_VALU": 2048.0 * 300.0, "SQ_INSTS_LDS": 2048.0 * 20.0,
+            "SQ_INSTS_MFMA": 2048.0 * 12.0, "SQ_VALU_MFMA_BUSY_CYCLES": 0.05 * 1024 * 1e6,
+            "SQ_BUSY_CYCLES": 1.0, "GRBM_GUI_ACTIVE": 8e6}
+    path = tmp_root / "mfma.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp",
+                               "End_Timestamp"])
+        w.writeheader()
+        for c, v in vals.items():
+            w.writerow({"Dispatch_Id": 1, "Kernel_Name": name, "Counter_Name": c, "Counter_Value": v,
+                        "Start_Timestamp": 0, "End_Timestamp": 2000000})
+    bench.summarize_mfma(str(path), "CMD")
+    text = (tmp_root / "profiles" / "counters_mfma_fft.txt").read_text()
+    row = next(line for line in text.splitlines() if line.startswith(name)).split()
+    assert row[-4] == "12.0" and row[-3] == "5.00%" and row[-2] == "300.0" and row[-1] == "20.0"
+    assert "command: CMD" in text
