@@ -504,7 +504,8 @@ void build_share_only(pf_plan *p) {
         x.a.ny = yl1;
         x.a.y0 = ys1;
         if (x.kind == pf::PASS_R2C_P2 || x.kind == pf::PASS_C2R_P2) {
-            const long long tiles = (x.a.lines + 15) / 16;
+            const long long tl = pf::p2x_tile_lines(x.prec);
+            const long long tiles = (x.a.lines + tl - 1) / tl;
             const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(x);
             x.blocks = (unsigned)std::min(tiles, resident);
         } else {
@@ -657,14 +658,15 @@ void build_passes(pf_plan *p) {
             x.lds = pf::mr_lds_bytes(p->nx, 1);
             x.blocks = (unsigned)((pairs + xp - 1) / xp);
         }
-        if (p->fast_x) {  // half-length complex transform, 16 lines per tile, persistent blocks
+        if (p->fast_x) {  // half-length complex transform, 16 (FP64: 8) lines per tile, persistent blocks
             x.kind = dir == 0 ? pf::PASS_R2C_P2 : pf::PASS_C2R_P2;
             x.a.fft = p->fxh;
-            x.a.math = pf::p2_has_mfma(p->nx / 2) ? p->lay.math : 0;
+            x.a.math = pf::p2_has_mfma(p->nx / 2) && p->lay.precision == PF_F32 ? p->lay.math : 0;
             x.a.tw = (const char *)p->tw_dev + p->tw_off[3];
             x.threads = (unsigned)pf::p2x_threads(p->nx);
-            x.lds = pf::p2x_lds_bytes(p->nx, x.a.math);
-            const long long tiles = (x.a.lines + 15) / 16;
+            x.lds = pf::p2x_lds_bytes(p->nx, x.a.math, x.prec);
+            const long long tl = pf::p2x_tile_lines(x.prec);
+            const long long tiles = (x.a.lines + tl - 1) / tl;
             const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(x);
             x.blocks = (unsigned)(tiles < resident ? tiles : resident);
         }
@@ -1047,17 +1049,22 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
         // [M-point stage table (M - 1)][pad][W_nx^k, k = 0 .. M], M = nx / 2
         const int M = nx / 2;
         factor_length(M, &p->fxh);
-        std::vector<float> t;
-        build_twiddles<float>(p->fxh, t);
-        t.resize(2 * (size_t)(2 * M + 1), 0.f);
-        const double two_pi = 6.283185307179586476925286766559;
-        for (int k = 0; k <= M; ++k) {
-            const double ang = two_pi * (double)k / (double)nx;
-            t[2 * (size_t)(M + k)] = (float)std::cos(ang);
-            t[2 * (size_t)(M + k) + 1] = (float)(-std::sin(ang));
-        }
-        const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
-        host.insert(host.end(), b, b + t.size() * sizeof(float));
+        auto split_table = [&](auto zero) {
+            typedef decltype(zero) R;
+            std::vector<R> t;
+            build_twiddles<R>(p->fxh, t);
+            t.resize(2 * (size_t)(2 * M + 1), zero);
+            const double two_pi = 6.283185307179586476925286766559;
+            for (int k = 0; k <= M; ++k) {
+                const double ang = two_pi * (double)k / (double)nx;
+                t[2 * (size_t)(M + k)] = (R)std::cos(ang);
+                t[2 * (size_t)(M + k) + 1] = (R)(-std::sin(ang));
+            }
+            const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
+            host.insert(host.end(), b, b + t.size() * sizeof(R));
+        };
+        if (l->precision == PF_F64) split_table(0.0);
+        else split_table(0.f);
         host.resize((host.size() + 255) & ~(size_t)255, 0);
     }
     // mixed-radix tables W_n^m, m < n (FP32 plain transforms; the Chebyshev and
@@ -1096,7 +1103,7 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     }
     const bool cheb_p2 = l->third == PF_THIRD_CHEB && !o.generic_only && pf::p2_supported(p->fz.n, l->precision);
     if (e == hipSuccess && cheb_p2) e = pf::p2_spec_prepare(p->fz.n);
-    if (e == hipSuccess && p->fast_x) e = pf::p2x_prepare(nx);
+    if (e == hipSuccess && p->fast_x) e = pf::p2x_prepare(nx, l->precision);
     if (e != hipSuccess) {
         (void)hipFree(p->tw_dev);
         delete p;

@@ -1493,6 +1493,239 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
     }
 }
 
+// ---- X stage for power-of-two nx, FP64 ------------------------------------
+// The FP32 X stage's method in double precision (Sec. 3.2): the real line x of
+// length nx = 2M is transformed as the complex line z[m] = x[2m] + i x[2m+1]
+// of length M and split into its M + 1 modes, X[k] = E[k] + W_nx^k O[k]; the
+// backward pass inverts the split and runs the inverse DFT_M.  A tile is 8
+// lines, each a column of the FP64 C2C kernel's LDS map (one 16-byte slot per
+// point, 8 per row); workspace rows hold 8 modes (128 bytes).  Twiddles as in
+// FP32: the M-point stage table (M - 1 entries, copied to LDS), then at offset
+// M the split table W_nx^k, k = 0 .. M, read from global memory (in LDS it
+// would cost a block per CU at nx = 512).
+
+// Row offset in the FP64 workspace of line g = z ny + y (8 modes per row).
+__device__ __forceinline__ long long xd_rowoff(const PassArgs &a, int g) {
+    const int z = g / a.ny;
+    const int y = g - z * a.ny;
+    return ((long long)z * a.zrows + a.y0 + y) << 3;
+}
+
+template <int M>
+__global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2d(PassArgs a) {
+    constexpr int TC = 8;  // lines per tile
+    constexpr int T = M / 16;
+    constexpr int NT = T * TC;
+    constexpr int S = p2_stages(M);
+    constexpr int RL = p2_radix(M, S - 1);
+    constexpr int NSL = p2_ns(M, S - 1);
+    constexpr int NKB = M / 8 + 1;  // column blocks of 8 modes for the M + 1 modes
+    typedef cx<double> cd;
+    __shared__ long long rowoff[TC];
+    cd *buf = reinterpret_cast<cd *>(pf_smem);  // M points x 8 lines
+    cd *twl = buf + M * TC;                     // the stage table; the split table stays in global memory
+    const cd *__restrict__ tw = reinterpret_cast<const cd *>(a.tw);
+    const cd *__restrict__ spl = tw + M;
+    for (int i = threadIdx.x; i < M - 1; i += NT) twl[i] = tw[i];
+    const double *__restrict__ in = reinterpret_cast<const double *>(a.in);
+    cd *__restrict__ out = reinterpret_cast<cd *>(a.out);
+    const int lines = (int)a.lines;
+    const int ntiles = (lines + TC - 1) / TC;
+    const long long kbstride = a.kbrows << 3;
+    auto slot = [](int p, int c) { return p2_slot<16>(p, c); };
+    // line l = tv / T of tile t, points q + T m (lanes along the line)
+    auto load = [&](cd(&d)[16], int t) {
+        const int tv = opaque_tid();
+        const int l = tv / T, q = tv % T;
+        const int g = TC * t + l;
+        if (g < lines) {
+            const double *pl = in + (long long)g * a.ld_real + 2 * q;
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+                d[m] = gld_d<streamed<LD_R2C>()>(reinterpret_cast<const double2 *>(pl + 2 * T * m));
+        }
+    };
+    int t = blockIdx.x;
+    cd p[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) p[m] = make_double2(0.0, 0.0);
+    if (t < ntiles) load(p, t);
+    __syncthreads();  // tables in LDS
+    for (; t < ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        const int c_in = tv / T, q_in = tv % T;
+        const int c_mid = tv % TC, q_mid = tv / TC;
+        cd v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = p[m];
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(p, tn);
+        if (tv < TC && TC * t + tv < lines) rowoff[tv] = xd_rowoff(a, TC * t + tv);
+        Dft<double, 16, -1>::run(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[slot(q_in * 16 + r, c_in)] = v[r];
+        __syncthreads();
+        if constexpr (S == 3) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) v[m] = buf[slot(q_mid + T * m, c_mid)];
+            __syncthreads();
+            p2_butterflies1<M, 16, 16, -1>(v, q_mid, twl + p2_twoff(M, 1));
+            const int k = q_mid & 15;
+            const int base = (q_mid - k) * 16 + k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[slot(base + r * 16, c_mid)] = v[r];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = buf[slot(q_mid + T * m, c_mid)];
+        __syncthreads();
+        p2_butterflies1<M, RL, NSL, -1>(v, q_mid, twl + p2_twoff(M, S - 1));
+#pragma unroll
+        for (int m = 0; m < 16; ++m) buf[slot(q_mid + T * m, c_mid)] = v[m];
+        __syncthreads();
+        // X[k] of line l from Z[k mod M] and Z[(M - k) mod M], k = 0 .. M
+        auto split = [&](int k, int l) {
+            const cd zk = buf[slot(k < M ? k : 0, l)];
+            const cd zm = buf[slot((M - k) & (M - 1), l)];
+            const cd E = make_double2(0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y));
+            const cd O = make_double2(0.5 * (zk.y + zm.y), 0.5 * (zm.x - zk.x));
+            return cadd(E, cmul(spl[k], O));
+        };
+        // item f = (column block kb, line l, mode j): 8 lanes store one 128-byte row;
+        // the items of k = 0 also store mode M, alone in the last column block
+        for (int f = tv; f < (NKB - 1) * 64; f += NT) {
+            const int kb = f >> 6, l = (f >> 3) & 7, j = f & 7;
+            if (TC * t + l >= lines) continue;
+            const int k = kb * 8 + j;
+            cd *row = out + rowoff[l];
+            gst_d<streamed<ST_R2C>()>(reinterpret_cast<double2 *>(row + kb * kbstride + j), split(k, l));
+            if (k == 0)
+                gst_d<streamed<ST_R2C>()>(reinterpret_cast<double2 *>(row + (NKB - 1) * kbstride), split(M, l));
+        }
+        __syncthreads();  // LDS tile and row offsets are reused by the next tile
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2d(PassArgs a) {
+    constexpr int TC = 8;
+    constexpr int T = M / 16;
+    constexpr int NT = T * TC;
+    constexpr int S = p2_stages(M);
+    constexpr int RL = p2_radix(M, S - 1);
+    constexpr int NSL = p2_ns(M, S - 1);
+    constexpr int NIT = M / 2 * TC / NT;  // (mode k < M/2, line) items per thread per tile
+    static_assert(NT % 64 == 0, "an item's line depends on tv only");
+    typedef cx<double> cd;
+    cd *buf = reinterpret_cast<cd *>(pf_smem);
+    cd *twl = buf + M * TC;  // the stage table; the split table stays in global memory
+    const cd *__restrict__ tw = reinterpret_cast<const cd *>(a.tw);
+    const cd *__restrict__ spl = tw + M;
+    for (int i = threadIdx.x; i < M - 1; i += NT) twl[i] = tw[i];
+    const cd *__restrict__ in = reinterpret_cast<const cd *>(a.in);
+    double *__restrict__ out = reinterpret_cast<double *>(a.out);
+    const int lines = (int)a.lines;
+    const int ntiles = (lines + TC - 1) / TC;
+    auto slot = [](int p, int c) { return p2_slot<16>(p, c); };
+    // item i: f = tv + NT i -> mode k = 8 (f >> 6) + (f & 7) < M/2 of line l =
+    // (f >> 3) & 7; it holds X[k] and X[M-k] (for k = 0 the partner is X[M], the
+    // first slot of the last column block), and threads 0..7 hold X[M/2] of line
+    // tv.  A wave reads whole 128-byte rows.
+    auto load = [&](cd(&xk)[NIT], cd(&xm)[NIT], cd &xh, int t, int tv) {
+        const int g0 = TC * t;
+        const int z0 = g0 / a.ny;
+        const int y0 = g0 - z0 * a.ny;
+        const cd *tb = in + (((long long)z0 * a.zrows + a.y0 + y0) << 3);
+        const long long zplane = a.zrows * 8;  // elements between z planes of the workspace
+        const long long kbs = a.kbrows * 8;    // elements between column blocks
+        auto rowrel = [&](int l) {
+            const int g = g0 + l;
+            const int z = g / a.ny;
+            const int y = g - z * a.ny;
+            return (long long)(z - z0) * zplane + (y - y0) * 8;
+        };
+        auto col = [&](int k) { return (long long)(k >> 3) * kbs + (k & 7); };
+        // lines past the end load the last line instead; their results are never stored
+        const int lmax = lines - 1 - g0;
+        const cd *r = tb + rowrel(min((tv >> 3) & 7, lmax));
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int f = tv + NT * i;
+            const int k = ((f >> 6) << 3) + (f & 7);
+            xk[i] = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(r + col(k)));
+            xm[i] = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(r + col(M - k)));
+        }
+        if (tv < TC) xh = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(tb + rowrel(min(tv, lmax)) + col(M / 2)));
+    };
+    // Zb[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) W_nx^-k
+    auto zb = [](cd Xk, cd Xm, cd w) {
+        const cd E = make_double2(Xk.x + Xm.x, Xk.y - Xm.y);
+        const cd O = cmul(make_double2(Xk.x - Xm.x, Xk.y + Xm.y), w);
+        return make_double2(E.x - O.y, E.y + O.x);
+    };
+
+    int t = blockIdx.x;
+    cd pk[NIT], pm[NIT], ph = make_double2(0.0, 0.0);
+    if (t < ntiles) load(pk, pm, ph, t, threadIdx.x);
+    __syncthreads();  // tables in LDS
+    for (; t < ntiles; t += gridDim.x) {
+        const int tv = opaque_tid();
+        // inverse split into the LDS tile; modes 0 and M contribute their real parts only
+        {
+            const int l = (tv >> 3) & 7;
+#pragma unroll
+            for (int i = 0; i < NIT; ++i) {
+                const int f = tv + NT * i;
+                const int k = ((f >> 6) << 3) + (f & 7);
+                cd Xk = pk[i], Xm = pm[i];
+                if (k == 0) Xk.y = Xm.y = 0.0;
+                const cd w = spl[k];
+                buf[slot(k, l)] = zb(Xk, Xm, make_double2(w.x, -w.y));
+                // Zb[M-k] uses W_nx^-(M-k) = -W_nx^k
+                if (k != 0) buf[slot(M - k, l)] = zb(Xm, Xk, make_double2(-w.x, -w.y));
+            }
+            if (tv < TC) {
+                const cd w = spl[M / 2];
+                buf[slot(M / 2, tv)] = zb(ph, ph, make_double2(w.x, -w.y));
+            }
+        }
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(pk, pm, ph, tn, tv);
+        __syncthreads();
+        const int c_mid = tv % TC, q_mid = tv / TC;
+        const int c_out = tv / T, q_out = tv % T;
+        cd v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = buf[slot(q_mid + T * m, c_mid)];
+        __syncthreads();
+        Dft<double, 16, 1>::run(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[slot(q_mid * 16 + r, c_mid)] = v[r];
+        __syncthreads();
+        if constexpr (S == 3) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) v[m] = buf[slot(q_mid + T * m, c_mid)];
+            __syncthreads();
+            p2_butterflies1<M, 16, 16, 1>(v, q_mid, twl + p2_twoff(M, 1));
+            const int k = q_mid & 15;
+            const int base = (q_mid - k) * 16 + k;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) buf[slot(base + r * 16, c_mid)] = v[r];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = buf[slot(q_out + T * m, c_out)];
+        p2_butterflies1<M, RL, NSL, 1>(v, q_out, twl + p2_twoff(M, S - 1));
+        const int g = TC * t + c_out;
+        if (g < lines) {
+            double *o = out + (long long)g * a.ld_real + 2 * q_out;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) gst_d<streamed<ST_C2R>()>(reinterpret_cast<double2 *>(o + 2 * T * m), v[m]);
+        }
+        __syncthreads();  // the next tile's split overwrites the LDS tile
+    }
+}
+
 // ---- fused X-Y pass: the slab form of the method (Sec. 4.3, Fig. 10) --------
 // The X and Y stages of one z plane need no data from other planes, so one
 // persistent kernel can run both, plane after plane, and the Y stage then
@@ -1862,13 +2095,24 @@ hipError_t p2_fused_launch(const FusedArgs &f, int fwd, int nx, int ny, unsigned
     return hipLaunchKernel(k, dim3(blocks), dim3(512), args, p2_fused_lds_bytes(nx, ny), s);
 }
 
-bool p2x_supported(int nx, int prec) { return prec == 0 && (nx == 512 || nx == 1024 || nx == 2048); }
+bool p2x_supported(int nx, int prec) {
+    return (prec == 0 && (nx == 512 || nx == 1024 || nx == 2048)) || (prec == 1 && (nx == 512 || nx == 1024));
+}
 
 int p2x_threads(int nx) { return nx / 2 / 16 * 8; }
 
-size_t p2x_lds_bytes(int nx, int math) {
+int p2x_tile_lines(int prec) { return prec == 1 ? 8 : 16; }
+
+size_t p2x_lds_bytes(int nx, int math, int prec) {
     const int M = nx / 2;
+    if (prec == 1) return (size_t)M * 8 * sizeof(double2) + (size_t)M * sizeof(double2);
     return (size_t)M * 16 * sizeof(float2) + (size_t)(2 * M + 2) * sizeof(float2) + (math ? kMfmaTableBytes : 0);
+}
+
+static const void *p2xd_pick(int nx, int fwd) {
+    if (nx == 512) return fwd ? (const void *)&k_r2c_p2d<256> : (const void *)&k_c2r_p2d<256>;
+    if (nx == 1024) return fwd ? (const void *)&k_r2c_p2d<512> : (const void *)&k_c2r_p2d<512>;
+    return nullptr;
 }
 
 static const void *p2x_pick(int nx, int fwd, int mt, int tr = 0) {
@@ -1888,14 +2132,24 @@ static const void *p2x_pick(int nx, int fwd, int mt, int tr = 0) {
     return nullptr;
 }
 
-hipError_t p2x_prepare(int nx) {
+hipError_t p2x_prepare(int nx, int prec) {
     hipError_t e = hipSuccess;
+    if (prec == 1) {
+        for (int fwd : {0, 1}) {
+            const void *k = p2xd_pick(nx, fwd);
+            if (!k) return hipErrorInvalidValue;
+            const hipError_t r =
+                hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, 0, 1));
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
     for (int fwd : {0, 1})
         for (int mt = 0; mt < 4; ++mt) {  // mt 3: the transposed-row backward kernel (plain)
         const void *k = mt < 3 ? p2x_pick(nx, fwd, mt) : p2x_pick(nx, fwd, 0, 1);
         if (!k) continue;
         hipError_t r =
-            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, mt < 3 ? mt : 0));
+            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, mt < 3 ? mt : 0, 0));
         if (r != hipSuccess && e == hipSuccess) e = r;
         }
     return e;
@@ -2003,8 +2257,9 @@ static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
 
 const void *p2_symbol(const PassDesc &d) {
     if (d.kind == PASS_C2C_P2 && d.prec == 1) return p2d_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
-    if (d.kind == PASS_R2C_P2) return p2x_pick(2 * d.a.fft.n, 1, d.a.math);
-    if (d.kind == PASS_C2R_P2) return p2x_pick(2 * d.a.fft.n, 0, d.a.math, d.a.xtr);
+    if (d.kind == PASS_R2C_P2) return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 1) : p2x_pick(2 * d.a.fft.n, 1, d.a.math);
+    if (d.kind == PASS_C2R_P2)
+        return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 0) : p2x_pick(2 * d.a.fft.n, 0, d.a.math, d.a.xtr);
     return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);
 }
 

@@ -242,11 +242,13 @@ hipError_t p2_launch(const PassDesc &d, hipStream_t s);
 hipError_t p2_spec_prepare(int n);
 int p2_spec_blocks_per_cu(int n, unsigned threads, size_t lds);
 hipError_t p2_spec_launch(const PassDesc &d, int adj, int nx, float scale, hipStream_t s);
-// Even power-of-two X stage, FP32 (fft.n of the pass is nx / 2).
+// Even power-of-two X stage (fft.n of the pass is nx / 2): FP32 for nx = 512 ..
+// 2048 (tiles of 16 lines), FP64 for nx = 512, 1024 (tiles of 8 lines).
 bool p2x_supported(int nx, int prec);
 int p2x_threads(int nx);
-size_t p2x_lds_bytes(int nx, int math);
-hipError_t p2x_prepare(int nx);
+int p2x_tile_lines(int prec);
+size_t p2x_lds_bytes(int nx, int math, int prec);
+hipError_t p2x_prepare(int nx, int prec);
 
 // LDS index with one pad slot every 16 complex elements (spreads the strided
 // Stockham writes over the banks).
