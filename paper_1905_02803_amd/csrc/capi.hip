@@ -732,11 +732,12 @@ void build_passes(pf_plan *p) {
             y2.a.out_s = yl;
             y2.a.tile_order = 0;
             y2.blocks = c2c_grid(p, y2);
-            // X: rows of W' hold 16 lines at one mode (its own kernel: the grid again)
+            // X: rows of W' hold 16 (FP64: 8) lines at one mode (its own kernel: the grid again)
             x.a.xtr = 1;
             x.a.zrows = (long long)p->nxh * p->ny;
             x.a.kbrows = p->ny;
-            const long long xtiles = (x.a.lines + 15) / 16;
+            const long long xtl = pf::p2x_tile_lines(x.prec);
+            const long long xtiles = (x.a.lines + xtl - 1) / xtl;
             const long long xres = (long long)p->ncu * pf::p2_blocks_per_cu(x);
             x.blocks = (unsigned)(xtiles < xres ? xtiles : xres);
             z = z2;
@@ -1146,8 +1147,10 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     p->blocked = !p->share && l->m1 * l->m2 > 1;
     p->w_bytes = ((size_t)p->nz * p->nkb * p->ny * p->B * p->csize + 255) & ~(size_t)255;
     p->ws_bytes = p->w_bytes;
+    // (ny a multiple of the X tile's lines: 16 FP32, 8 FP64, so that a row of the
+    // transposed workspace holds one tile's lines at one mode)
     p->bwd_tr = !o.no_bwd_tr && p->fast_x && l->stride1 && !p->share && !p->blocked && !p->fused &&
-                l->third == PF_THIRD_FFT && l->precision == PF_F32 && l->math == PF_PLAIN && ny % 16 == 0 &&
+                l->third == PF_THIRD_FFT && l->math == PF_PLAIN && ny % pf::p2x_tile_lines(l->precision) == 0 &&
                 ny <= PF_BWD_TR_MAX_NY;
     if (p->share) {
         p->ws_bytes += (size_t)p->nxh * ny * nz * p->csize;

@@ -1606,7 +1606,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2d(PassArgs a) {
     }
 }
 
-template <int M>
+template <int M, bool TR = false>
 __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2d(PassArgs a) {
     constexpr int TC = 8;
     constexpr int T = M / 16;
@@ -1627,12 +1627,40 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2d(PassArgs a) {
     const int lines = (int)a.lines;
     const int ntiles = (lines + TC - 1) / TC;
     auto slot = [](int p, int c) { return p2_slot<16>(p, c); };
-    // item i: f = tv + NT i -> mode k = 8 (f >> 6) + (f & 7) < M/2 of line l =
-    // (f >> 3) & 7; it holds X[k] and X[M-k] (for k = 0 the partner is X[M], the
-    // first slot of the last column block), and threads 0..7 hold X[M/2] of line
-    // tv.  A wave reads whole 128-byte rows.
+    // item i: f = tv + NT i -> mode k < M/2 of line l; it holds X[k] and X[M-k]
+    // (for k = 0 the partner is X[M], the first slot of the last column
+    // block), and threads 0..7 hold X[M/2] of line tv.  A wave reads whole
+    // 128-byte rows.  Blocked rows (8 modes of one line): k = 8 (f >> 6) +
+    // (f & 7), l = (f >> 3) & 7.  Transposed rows (TR: mode k of line g = z ny
+    // + y at z zrows + k kbrows + y, zrows = nxh ny, kbrows = ny, so one row
+    // holds the tile's 8 lines at one mode; ny is a multiple of 8): l = f & 7,
+    // k = f >> 3.
+    auto item = [](int f, int &k, int &l) {
+        if constexpr (TR) {
+            l = f & 7;
+            k = f >> 3;
+        } else {
+            l = (f >> 3) & 7;
+            k = ((f >> 6) << 3) + (f & 7);
+        }
+    };
     auto load = [&](cd(&xk)[NIT], cd(&xm)[NIT], cd &xh, int t, int tv) {
         const int g0 = TC * t;
+        if constexpr (TR) {
+            const int z0 = g0 / a.ny;
+            const int y0 = g0 - z0 * a.ny;
+            const cd *tb = in + (long long)z0 * a.zrows + y0;
+            const long long ks = a.kbrows;
+#pragma unroll
+            for (int i = 0; i < NIT; ++i) {
+                int k, l;
+                item(tv + NT * i, k, l);
+                xk[i] = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(tb + k * ks + l));
+                xm[i] = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(tb + (M - k) * ks + l));
+            }
+            if (tv < TC) xh = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(tb + (M / 2) * ks + tv));
+            return;
+        }
         const int z0 = g0 / a.ny;
         const int y0 = g0 - z0 * a.ny;
         const cd *tb = in + (((long long)z0 * a.zrows + a.y0 + y0) << 3);
@@ -1650,8 +1678,8 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2d(PassArgs a) {
         const cd *r = tb + rowrel(min((tv >> 3) & 7, lmax));
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
-            const int f = tv + NT * i;
-            const int k = ((f >> 6) << 3) + (f & 7);
+            int k, l;
+            item(tv + NT * i, k, l);
             xk[i] = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(r + col(k)));
             xm[i] = gld_d<streamed<LD_C2R>()>(reinterpret_cast<const double2 *>(r + col(M - k)));
         }
@@ -1672,11 +1700,10 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2d(PassArgs a) {
         const int tv = opaque_tid();
         // inverse split into the LDS tile; modes 0 and M contribute their real parts only
         {
-            const int l = (tv >> 3) & 7;
 #pragma unroll
             for (int i = 0; i < NIT; ++i) {
-                const int f = tv + NT * i;
-                const int k = ((f >> 6) << 3) + (f & 7);
+                int k, l;
+                item(tv + NT * i, k, l);
                 cd Xk = pk[i], Xm = pm[i];
                 if (k == 0) Xk.y = Xm.y = 0.0;
                 const cd w = spl[k];
@@ -2109,9 +2136,13 @@ size_t p2x_lds_bytes(int nx, int math, int prec) {
     return (size_t)M * 16 * sizeof(float2) + (size_t)(2 * M + 2) * sizeof(float2) + (math ? kMfmaTableBytes : 0);
 }
 
-static const void *p2xd_pick(int nx, int fwd) {
-    if (nx == 512) return fwd ? (const void *)&k_r2c_p2d<256> : (const void *)&k_c2r_p2d<256>;
-    if (nx == 1024) return fwd ? (const void *)&k_r2c_p2d<512> : (const void *)&k_c2r_p2d<512>;
+static const void *p2xd_pick(int nx, int fwd, int tr = 0) {
+    if (nx == 512)
+        return fwd ? (tr ? nullptr : (const void *)&k_r2c_p2d<256>)
+                   : (tr ? (const void *)&k_c2r_p2d<256, true> : (const void *)&k_c2r_p2d<256>);
+    if (nx == 1024)
+        return fwd ? (tr ? nullptr : (const void *)&k_r2c_p2d<512>)
+                   : (tr ? (const void *)&k_c2r_p2d<512, true> : (const void *)&k_c2r_p2d<512>);
     return nullptr;
 }
 
@@ -2135,8 +2166,8 @@ static const void *p2x_pick(int nx, int fwd, int mt, int tr = 0) {
 hipError_t p2x_prepare(int nx, int prec) {
     hipError_t e = hipSuccess;
     if (prec == 1) {
-        for (int fwd : {0, 1}) {
-            const void *k = p2xd_pick(nx, fwd);
+        for (int v : {0, 1, 2}) {  // backward, forward, backward on transposed rows
+            const void *k = p2xd_pick(nx, v == 1, v == 2);
             if (!k) return hipErrorInvalidValue;
             const hipError_t r =
                 hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, 0, 1));
@@ -2174,6 +2205,8 @@ static const void *p2d_pick_dir(int inp, int outp) {
     if (inp == 0 && outp == 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 0, 0>);
     if (inp == 0 && outp == 1) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 0, 1>);
     if (inp == 1 && outp == 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 1, 0>);
+    // lines on both sides: the backward Y pass of the transposed chain
+    if (inp == 1 && outp == 1 && DIR > 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 1, 1>);
     return nullptr;
 }
 
@@ -2188,9 +2221,12 @@ static const void *p2d_pick(int n, int dir, int inp, int outp) {
 
 hipError_t p2d_prepare(int n) {
     for (int dir : {-1, 1})
-        for (int io = 0; io < 3; ++io) {
-            const void *k = p2d_pick(n, dir, io == 2 ? 1 : 0, io == 1 ? 1 : 0);
-            if (!k) return hipErrorInvalidValue;
+        for (int io = 0; io < 4; ++io) {  // (inp, outp): (0,0) (0,1) (1,0) (1,1)
+            const void *k = p2d_pick(n, dir, io >= 2 ? 1 : 0, io & 1);
+            if (!k) {
+                if (io == 3 && dir < 0) continue;
+                return hipErrorInvalidValue;
+            }
             const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2d_lds_bytes(n));
             if (e != hipSuccess) return e;
         }
@@ -2259,7 +2295,7 @@ const void *p2_symbol(const PassDesc &d) {
     if (d.kind == PASS_C2C_P2 && d.prec == 1) return p2d_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
     if (d.kind == PASS_R2C_P2) return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 1) : p2x_pick(2 * d.a.fft.n, 1, d.a.math);
     if (d.kind == PASS_C2R_P2)
-        return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 0) : p2x_pick(2 * d.a.fft.n, 0, d.a.math, d.a.xtr);
+        return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 0, d.a.xtr) : p2x_pick(2 * d.a.fft.n, 0, d.a.math, d.a.xtr);
     return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);
 }
 

@@ -130,8 +130,9 @@ def test_maximum_lengths_match_oracle(shape, prec, stride1):
                                    (5, 7, 512), (40, 24, 1024), (6, 32, 512), (3, 48, 1024)], ids=ids)
 def test_each_pass_matches_oracle_stage(shape, prec):
     """Every kernel alone against the oracle's own stage (forward X, Y, Z; backward Z, Y, X).
-    The backward intermediate is read in the layout the plan reports (FP32 plans with a
-    power-of-two X pass and ny a multiple of 16 up to 512 use the transposed one)."""
+    The backward intermediate is read in the layout the plan reports (plans with a
+    power-of-two X pass and ny up to 512, a multiple of 16 (FP32) or 8 (FP64), use the
+    transposed one)."""
     nz, ny, nx = shape
     print(f"case shape={shape} prec={prec}", flush=True)
     tol = TOL[prec]
@@ -158,7 +159,8 @@ def test_each_pass_matches_oracle_stage(shape, prec):
         assert rel(out.cpu().numpy(), oracle.to_stride1(A)) < tol
         # backward stages on an arbitrary half spectrum
         layout = plan.workspace_layout(pf.PF_DIR_BACKWARD)
-        transposed = prec == pf.PF_F32 and nx in (512, 1024, 2048) and ny % 16 == 0 and ny <= 512
+        transposed = ny <= 512 and ((prec == pf.PF_F32 and nx in (512, 1024, 2048) and ny % 16 == 0) or
+                                    (prec == pf.PF_F64 and nx in (512, 1024) and ny % 8 == 0))
         assert layout == (pf.PF_WS_TRANSPOSED if transposed else pf.PF_WS_BLOCKED)
         view = pf.transposed_workspace_to_half_spectrum if transposed else pf.workspace_to_half_spectrum
         V = synth.complex_half(400 + nx, (nz, ny, nx // 2 + 1)).astype(np_cplx(prec))

@@ -2,8 +2,9 @@
 line of half the length, its DFT and the split into nx / 2 + 1 modes
 (Sec. 3.2), eight lines per tile.  Checked against the oracle's X stage alone
 and the whole transform, on tile-ragged line counts (one line, fewer lines
-than a tile, more tiles than the resident grid), in place, and for the
-processor-grid block layout of Table 1."""
+than a tile, more tiles than the resident grid) and in place.  With ny a
+multiple of 8 the backward X pass reads the transposed workspace [nz][nxh][ny]
+(rows of the tile's 8 lines at one mode)."""
 import numpy as np
 import pytest
 
@@ -40,7 +41,13 @@ def test_f64_power_of_two_x_stage_matches_oracle(shape):
         torch.cuda.synchronize()
         assert rel(pf.workspace_to_half_spectrum(ws, nx, ny, nz).cpu().numpy(), oracle.stage_x_r2c(u)) < TOL
         ws.zero_()
-        pf.half_spectrum_to_workspace(torch.from_numpy(V).cuda(), ws)
+        Vd = torch.from_numpy(V).cuda()
+        if plan.workspace_layout(pf.PF_DIR_BACKWARD) == pf.PF_WS_TRANSPOSED:  # [nz][nxh][ny]
+            assert ny % 8 == 0 and ny <= 512
+            ws[: V.size].copy_(Vd.permute(0, 2, 1).reshape(-1))
+        else:
+            assert ny % 8 or ny > 512
+            pf.half_spectrum_to_workspace(Vd, ws)
         r = plan.empty_real()
         plan.run_pass(pf.PF_DIR_BACKWARD, 2, ws, r)
         torch.cuda.synchronize()
