@@ -102,8 +102,9 @@ def section_starts(names):
     s0 = first(lambda k: "k_r2c_p2<256" in k, b0)
     h0 = first(lambda k: "k_fill" in k, s0)
     o0 = first(lambda k: "k_r2c_p2<256" in k, h0)
-    # the FP64 512^3 plan runs between the share-only leg and the other grids
-    f0 = first(lambda k: "k_c2c_p2d" in k or "<double" in k, h0)
+    # the FP64 512^3 plan (its FP64 kernels: k_*_p2d, or a runtime-radix <double, ...>) runs
+    # between the share-only leg and the other grids
+    f0 = first(lambda k: "_p2d<" in k or "<double" in k, h0)
     # the fused comparison at 2048 x 512 x 512 (its X kernel k_r2c_p2<1024, ...>) runs last
     c0 = first(lambda k: "k_r2c_p2<1024" in k, o0)
     return b0, s0, h0, min(f0, o0), o0, c0

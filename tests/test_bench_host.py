@@ -45,6 +45,9 @@ def test_trace_summary_splits_the_workloads(tmp_root):
              ("void pf::k_spec_p2<512, 16, 0>(pf::PassArgs, int, float)", 0.23),
              ("pf::k_fill(pf::FillArgs)", 0.09),                            # the share-only leg begins
              (KERNELS[0], 0.28),
+             ("void pf::k_r2c_p2d<256>(pf::PassArgs)", 0.41),               # the FP64 plan begins
+             ("void pf::k_c2c_p2d<512, -1, 0, 0>(pf::PassArgs)", 0.44),
+             ("void pf::k_c2r_p2d<256, true>(pf::PassArgs)", 0.48),
              ("void pf::k_r2c_p2<256, 0>(pf::PassArgs)", 0.4),              # the other grids begin
              ("void pf::k_mr_x<20, 24, 1>(pf::MrArgs)", 0.1),
              ("void pf::k_r2c_p2<1024, 0>(pf::PassArgs)", 0.9),             # the fused comparison begins
@@ -66,7 +69,10 @@ def test_trace_summary_splits_the_workloads(tmp_root):
     other = (prof / "kernels_fft_512cubed_480x360x250.txt").read_text()
     assert "k_r2c_p2<256" in other and "k_mr_x<20, 24, 1>" in other and "k_fill" not in other
     assert "k_xy_fused" not in other and "k_r2c_p2<1024" not in other
-    assert "k_mr_x" not in share
+    assert "k_mr_x" not in share and "p2d" not in share
+    f64 = (prof / "kernels_fft_512cubed_f64.txt").read_text()
+    assert "k_r2c_p2d<256>" in f64 and "k_c2r_p2d<256, true>" in f64 and "k_r2c_p2<256" not in f64
+    assert "p2d" not in other
     fused = (prof / "kernels_fft_2048x512x512_fused.txt").read_text()
     assert "k_r2c_p2<1024" in fused and "k_xy_fused<1024, 512, 1>" in fused and "k_mr_x" not in fused
 
