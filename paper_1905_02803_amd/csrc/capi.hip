@@ -41,6 +41,7 @@ struct PassTiming {
 struct PlanOpts {
     bool generic_only = false;
     bool no_mr = false;  // keep the runtime-radix kernels where a compile-time mixed-radix one exists
+    bool no_spec_sr = false;  // fused spectral step by the even extension even where the split form exists
     bool no_bwd_tr = false;  // backward chain on W (no transposed workspace)
     bool external_ws = false;
     int radix_order[3] = {0, 0, 0};
@@ -63,6 +64,8 @@ struct pf_plan {
     // offset of its table W_n^m, m < n, in tw_dev
     bool mr[3];
     size_t tw_mr[3];
+    size_t tw_dct;  // split type-I DCT of the fused spectral step: [L-point][M-point stage tables][W_4M^k]
+    bool spec_sr;
     FftSpec fxh;   // nx / 2 plan of the even power-of-two X stage
     bool fast_x;
     void *ws;          // the workspace: W, then (m1 m2 > 1) the global-array buffer
@@ -778,6 +781,13 @@ void build_passes(pf_plan *p) {
             const long long tiles = f.a.A * f.a.CB;
             const long long resident = (long long)p->ncu * pf::p2_spec_blocks_per_cu(fz.n, f.threads, f.lds);
             f.blocks = (unsigned)(tiles < resident ? tiles : resident);
+            if (p->spec_sr) {  // the split type-I DCT: one tile per workgroup
+                f.a.math = 5;
+                f.a.tw = (const char *)p->tw_dev + p->tw_dct;
+                f.threads = pf::p2_spec_sr_threads(p->nz);
+                f.lds = pf::p2_spec_sr_lds_bytes(p->nz);
+                f.blocks = (unsigned)tiles;
+            }
             p->spec = f;
             p->spec_fused = true;
         }
@@ -1084,6 +1094,32 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
             t[2 * (size_t)m] = (float)std::cos(ang);
             t[2 * (size_t)m + 1] = (float)(-std::sin(ang));
         }
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
+        host.insert(host.end(), b, b + t.size() * sizeof(float));
+        host.resize((host.size() + 255) & ~(size_t)255, 0);
+    }
+    // the split type-I DCT of the fused spectral step (FP32, nz = L + 1 = 257)
+    p->spec_sr = !o.no_spec_sr && !o.generic_only && l->third == PF_THIRD_CHEB && l->precision == PF_F32 &&
+                 pf::p2_spec_sr_supported(nz);
+    p->tw_dct = 0;
+    if (p->spec_sr) {
+        const int L = nz - 1, M = L / 2;
+        FftSpec fl, fm;
+        factor_length(L, &fl);
+        factor_length(M, &fm);
+        std::vector<float> tl, tm;
+        build_twiddles<float>(fl, tl);
+        build_twiddles<float>(fm, tm);
+        std::vector<float> t(2 * (size_t)(L + 2 * M), 0.f);
+        std::copy(tl.begin(), tl.begin() + 2 * (L - 1), t.begin());
+        std::copy(tm.begin(), tm.begin() + 2 * (M - 1), t.begin() + 2 * L);
+        const double two_pi = 6.283185307179586476925286766559;
+        for (int k = 0; k < M; ++k) {  // W_{4M}^k
+            const double ang = two_pi * (double)k / (double)(4 * M);
+            t[2 * (size_t)(L + M + k)] = (float)std::cos(ang);
+            t[2 * (size_t)(L + M + k) + 1] = (float)(-std::sin(ang));
+        }
+        p->tw_dct = host.size();
         const unsigned char *b = reinterpret_cast<const unsigned char *>(t.data());
         host.insert(host.end(), b, b + t.size() * sizeof(float));
         host.resize((host.size() + 255) & ~(size_t)255, 0);

@@ -18,6 +18,7 @@
 // (whole lines) lanes run along points.  Middle stages always run along
 // columns.  The LDS tile uses a swizzle that keeps every one of these access
 // patterns free of bank conflicts for N = 1024.
+#include <type_traits>
 #include <vector>
 
 #include "fft_device.h"
@@ -1011,6 +1012,205 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_spec_p2(PassArgs a, int nx,
             }
         }
         __syncthreads();  // the next tile's stage 0 overwrites the LDS tile
+    }
+}
+
+// The same z part with the type-I DCT split once (split radix), for nz = 257
+// (L = nz - 1 = 256, M = L / 2).  For a column x_0 .. x_L:
+//  * the even outputs Y_{2m}, m = 0 .. M, are the L-point DFT of the even
+//    sequence a_n = x_n + x_{L-n}, n < L (a_0 = x_0 + x_L);
+//  * the odd outputs Y_{2m+1}, m < M, are the type-III DCT
+//    B_m = sum_{k<M} X_k cos(pi k (2m+1) / (2M)) of X_0 = c_0, X_k = 2 c_k,
+//    c_k = x_k - x_{L-k}; it is one M-point DFT, v = DFT_M(V) of V_0 = c_0,
+//    V_k = W_{4M}^k (c_k + i c_{M-k}), read out as B_{2j} = v_j and
+//    B_{2j+1} = v_{M-1-j} (the transpose of the DFT-based type-II DCT, which
+//    holds for complex data because each step is complex-linear).
+// That is 1.5 L points of DFT per column where the even extension takes 2 L,
+// with no running sum (the half-length form with one carries FP32 rounding
+// across the column).  The L-point DFTs run on the first L/16 x 8 threads
+// (group L), the M-point ones on the next M/16 x 8 (group M), side by side,
+// with the barriers at the top level; each transform stages the tile's L + 1
+// rows in LDS once, and the two DFT exchanges then reuse that space.  One
+// tile (ky line, 16 kx columns) per workgroup.  The multiplier, the adjoint's
+// weights and the arguments are those of k_spec_p2; a.tw holds the L-point
+// stage table, the M-point stage table (each padded to L and M entries) and
+// W_{4M}^k, k < M.
+template <int L, int ADJ>
+__global__ __launch_bounds__(L / 16 * 8 + L / 32 * 8) void k_spec_sr(PassArgs a, int nx, float scale) {
+    static_assert(L == 256, "two-stage DFTs of L and L / 2 points");
+    constexpr int TC = 16, CP = TC / 2;
+    constexpr int M = L / 2;
+    constexpr int TL = L / 16, TM = M / 16;
+    constexpr int NL = TL * CP, NT = NL + TM * CP;
+    constexpr int NLOAD = ((L + 1) * CP + NT - 1) / NT;  // staging loads per thread
+    static_assert(NL % 64 == 0 && NT % CP == 0, "groups are whole waves; a thread's column pair is fixed");
+    float4 *stg = reinterpret_cast<float4 *>(pf_smem);  // rows 0 .. L of the tile, [row][pair]
+    float4 *bufL = stg;                                 // the DFT exchanges reuse the staging area
+    float4 *bufM = stg + L * CP;
+    cx<float> *twL = reinterpret_cast<cx<float> *>(stg + (L + M) * CP);
+    const cx<float> *twM = twL + L;
+    const cx<float> *w4 = twL + L + M;
+    const int tid = threadIdx.x;
+    const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
+    for (int i = tid; i < L + 2 * M; i += NT) twL[i] = tw[i];
+    cx<float> *__restrict__ ws = reinterpret_cast<cx<float> *>(a.out);
+    const int ny = (int)a.A;
+    const int CB = (int)a.CB;
+    const int t = blockIdx.x;
+    const int ta = t / CB, cb = t - ta * CB;
+    const int ncol = min(TC, a.C - cb * TC);
+    const Side &sd = a.in_s;
+    // workspace address of the tile's column pair p, row 0
+    auto colbase = [&](int p) -> long long {
+        return (long long)ta * sd.sa + (long long)(cb / sd.cpb) * sd.sblk + (long long)(cb % sd.cpb) * TC * sd.sc +
+               (long long)(2 * p) * sd.sc;
+    };
+    {  // stage rows 0 .. L (element f: row f / 8, pair f % 8 = tid % 8)
+        const int lp = tid % CP;
+        const long long b = colbase(lp);
+        const bool live = 2 * lp < ncol;
+        float4 xr[NLOAD];
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            const int row = tid / CP + i * (NT / CP);
+            xr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (live && row <= L)
+                xr[i] = gld<streamed<LD_C2C_ROWS>()>(reinterpret_cast<const float4 *>(ws + b + (long long)row * sd.sp));
+        }
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            const int row = tid / CP + i * (NT / CP);
+            if (row <= L) stg[row * CP + lp] = xr[i];
+        }
+    }
+    __syncthreads();
+
+    const bool gl = tid < NL;  // wave-uniform
+    const int tg = gl ? tid : tid - NL;
+    const int cp = tg % CP, q = tg / CP;
+    cx<float> v0[16], v1[16];
+    auto sub = [](float4 u, float4 v) { return make_float4(u.x - v.x, u.y - v.y, u.z - v.z, u.w - v.w); };
+    // staged row r as the transform reads it: the adjoint's first transform divides
+    // rows by w(z) (1 at z = 0 and L, 2 inside); applied here rather than when the
+    // rows are staged, which lets the compiler issue every staging load before the
+    // first wait
+    auto rd = [&](int r, auto first) {
+        float4 x = stg[r * CP + cp];
+        if constexpr (ADJ && decltype(first)::value) {
+            const float w = (r == 0 || r == L) ? 1.f : 0.5f;
+            x = make_float4(x.x * w, x.y * w, x.z * w, x.w * w);
+        }
+        return x;
+    };
+    // the type-I DCT of the staged rows; group L ends with Y_{2k} at k = q + TL m in
+    // (v0[m], v1[m]), group M with v_j at j = q + TM m
+    auto dct = [&](auto first) {
+        if (gl) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int n = q + TL * m;
+                const float4 u = rd(n, first), w = rd(L - n, first);  // n = 0 pairs with row L
+                v0[m] = make_float2(u.x + w.x, u.y + w.y);
+                v1[m] = make_float2(u.z + w.z, u.w + w.w);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int k = q + TM * m;
+                const float4 ck = sub(rd(k, first), rd(L - k, first));
+                if (k == 0) {
+                    v0[m] = make_float2(ck.x, ck.y);
+                    v1[m] = make_float2(ck.z, ck.w);
+                } else {
+                    const float4 cm = sub(rd(M - k, first), rd(M + k, first));
+                    const cx<float> w = w4[k];
+                    v0[m] = cmul(w, make_float2(ck.x - cm.y, ck.y + cm.x));
+                    v1[m] = cmul(w, make_float2(ck.z - cm.w, ck.w + cm.z));
+                }
+            }
+        }
+        __syncthreads();  // the DFT exchanges overwrite the staged rows
+        Dft<float, 16, -1>::run(v0);
+        Dft<float, 16, -1>::run(v1);
+        float4 *buf = gl ? bufL : bufM;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[p2_slot<TC>(q * 16 + r, cp)] = pack2(v0[r], v1[r]);
+        __syncthreads();
+        if (gl) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const float4 x = bufL[p2_slot<TC>(q + TL * m, cp)];
+                v0[m] = make_float2(x.x, x.y);
+                v1[m] = make_float2(x.z, x.w);
+            }
+            p2_butterflies2<L, L / 16, 16, -1>(v0, v1, q, twL + p2_twoff(L, 1));
+        } else {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const float4 x = bufM[p2_slot<TC>(q + TM * m, cp)];
+                v0[m] = make_float2(x.x, x.y);
+                v1[m] = make_float2(x.z, x.w);
+            }
+            p2_butterflies2<M, M / 16, 16, -1>(v0, v1, q, twM + p2_twoff(M, 1));
+        }
+    };
+    // output row of register m: group L holds Y_{2k} (k = q + TL m, kept for k <= M),
+    // group M holds B_{2j} = Y_{4j+1} (j < M/2) or B_{2(M-1-j)+1} = Y_{2L-4j-1}
+    auto out_row = [&](int m) {
+        if (gl) {
+            const int k = q + TL * m;
+            return k <= M ? 2 * k : -1;
+        }
+        const int j = q + TM * m;
+        return j < M / 2 ? 4 * j + 1 : 2 * L - 4 * j - 1;
+    };
+
+    dct(std::true_type());
+    {  // product with m = i mu (conj(m) when ADJ), mu = 0 at k = 0
+        const float two_pi = 6.283185307179586f;
+        const float kyf = two_pi / (float)ny, kxf = two_pi / (float)nx, kzf = two_pi / (float)(2 * L);
+        const float sg = ADJ ? -1.f : 1.f;
+        const int kx0 = cb * TC + 2 * cp;
+        const int kys = 2 * ta <= ny ? ta : ta - ny;
+        const float kyr = kyf * (float)kys;
+        const float kx0r = kxf * (float)kx0, kx1r = kxf * (float)(kx0 + 1);
+        const float r0 = kx0r * kx0r + kyr * kyr, r1 = kx1r * kx1r + kyr * kyr;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int k = out_row(m);
+            const float kzr = kzf * (float)(k < 0 ? 0 : k);
+            const float kz2 = kzr * kzr;
+            // 1 / |k|^2 by the hardware reciprocal (1 ulp), as in k_spec_p2
+            const float k20 = r0 + kz2, k21 = r1 + kz2;
+            const float mu0 = k20 > 0.f ? sg * (-scale * kx0r) * __builtin_amdgcn_rcpf(k20) : 0.f;
+            const float mu1 = sg * (-scale * kx1r) * __builtin_amdgcn_rcpf(k21);  // kx0 + 1 > 0
+            v0[m] = make_float2(-mu0 * v0[m].y, mu0 * v0[m].x);
+            v1[m] = make_float2(-mu1 * v1[m].y, mu1 * v1[m].x);
+        }
+    }
+    __syncthreads();  // every wave has read the DFT exchanges before the rows are staged again
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int row = out_row(m);
+        if (row >= 0) stg[row * CP + cp] = pack2(v0[m], v1[m]);
+    }
+    __syncthreads();
+    // the product is an even sequence again: its first nz points are the backward type-I DCT
+    dct(std::false_type());
+    if (2 * cp < ncol) {
+        const long long b = colbase(cp);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int row = out_row(m);
+            if (row >= 0) {
+                float4 x = pack2(v0[m], v1[m]);
+                if constexpr (ADJ) {
+                    const float w = (row == 0 || row == L) ? 1.f : 2.f;
+                    x = make_float4(x.x * w, x.y * w, x.z * w, x.w * w);
+                }
+                gst<streamed<ST_C2C_ROWS>()>(reinterpret_cast<float4 *>(ws + b + (long long)row * sd.sp), x);
+            }
+        }
     }
 }
 
@@ -2335,8 +2535,20 @@ int p2_spec_blocks_per_cu(int n, unsigned threads, size_t lds) {
     return nb > 0 ? nb : 1;
 }
 
+#ifndef PF_SPEC_SR
+#define PF_SPEC_SR 1  // 0: the fused spectral step keeps the even extension at nz = 257 too
+#endif
+bool p2_spec_sr_supported(int nz) { return PF_SPEC_SR && nz == 257; }
+unsigned p2_spec_sr_threads(int nz) { return nz == 257 ? 256 / 16 * 8 + 256 / 32 * 8 : 0; }
+size_t p2_spec_sr_lds_bytes(int nz) {
+    const int L = nz - 1, M = L / 2;
+    return (size_t)(L + M) * 8 * sizeof(float4) + (size_t)(L + 2 * M) * sizeof(float2);
+}
+
 hipError_t p2_spec_launch(const PassDesc &d, int adj, int nx, float scale, hipStream_t s) {
-    const void *k = spec_pick(d.a.fft.n, adj);
+    const void *k = d.a.math == 5 && d.a.cheb == 257
+                        ? (adj ? (const void *)&k_spec_sr<256, 1> : (const void *)&k_spec_sr<256, 0>)
+                        : spec_pick(d.a.fft.n, adj);
     if (!k) return hipErrorInvalidDeviceFunction;
     PassArgs a = d.a;
     void *args[] = {&a, &nx, &scale};

@@ -108,7 +108,8 @@ struct PassArgs {
     int inp, outp;  // power-of-two C2C pass, kind of side: 1 lines, 0 aligned rows, 2 unaligned rows
     int math;       // power-of-two passes: 0 plain, 1 / 2 middle radix-16 stage on MFMA (FP16 / BF16 hi+lo),
                     // 3 (C2C pass) no transform: the reorder alone, 4 (C2C pass) type-I DCT by the
-                    // even extension (lines of cheb = fft.n / 2 + 1 points)
+                    // even extension (lines of cheb = fft.n / 2 + 1 points), 5 (fused spectral
+                    // step) type-I DCT split once
     int tile_order; // power-of-two C2C pass: 0 tile t = (t / CB, t % CB), 1 tile t = (t % A, t / A)
     int xcd;        // power-of-two C2C pass: 1 to give each XCD runs of consecutive tiles
     int cheb;       // C2C pass: > 0 = lines of cheb points, transformed as their even
@@ -242,6 +243,11 @@ hipError_t p2_launch(const PassDesc &d, hipStream_t s);
 hipError_t p2_spec_prepare(int n);
 int p2_spec_blocks_per_cu(int n, unsigned threads, size_t lds);
 hipError_t p2_spec_launch(const PassDesc &d, int adj, int nx, float scale, hipStream_t s);
+// the same step with the type-I DCT split once (d.a.math = 5; nz = 257): one
+// tile per workgroup, twiddles [L-point table][M-point table][W_4M^k]
+bool p2_spec_sr_supported(int nz);
+unsigned p2_spec_sr_threads(int nz);
+size_t p2_spec_sr_lds_bytes(int nz);
 // Even power-of-two X stage (fft.n of the pass is nx / 2): FP32 for nx = 512 ..
 // 2048 (tiles of 16 lines), FP64 for nx = 512, 1024 (tiles of 8 lines).
 bool p2x_supported(int nx, int prec);
