@@ -8,8 +8,10 @@ Sec. 3.1) and the differentiable spectral step built on it.
 * Its hand-written adjoint satisfies <L u, g> = <u, L^T g> to rounding, equals
   the transpose of the explicitly assembled matrix on a tiny grid, and passes
   torch.autograd.gradcheck (finite differences) on the 16 x 16 x 17 grid.
-* The fused FP32 form (power-of-two extension) matches the oracle for the step
-  and the adjoint, and satisfies the dot-product identity.
+* The fused FP32 form (power-of-two extension; at nz = 257 the split-radix
+  DCT) matches the oracle for the step and the adjoint, satisfies the
+  dot-product identity, and reproduces the analytic mode (odd and last
+  Gauss-Lobatto modes, q0 = 131 and 256, at nz = 257).
 """
 import numpy as np
 import pytest
@@ -113,8 +115,10 @@ def test_spectral_step_fp32(shape):
 
 
 @pytest.mark.parametrize("prec", [pf.PF_F64, pf.PF_F32])
-@pytest.mark.parametrize("shape,k0,q0", [((17, 8, 16), 3, 5), ((17, 8, 16), 1, 0), ((129, 6, 20), 4, 37)],
-                         ids=["17x8x16-k3-q5", "17x8x16-k1-q0", "129x6x20-k4-q37"])
+@pytest.mark.parametrize("shape,k0,q0", [((17, 8, 16), 3, 5), ((17, 8, 16), 1, 0), ((129, 6, 20), 4, 37),
+                                         ((257, 4, 40), 5, 131), ((257, 4, 40), 19, 256)],
+                         ids=["17x8x16-k3-q5", "17x8x16-k1-q0", "129x6x20-k4-q37", "257x4x40-k5-q131",
+                              "257x4x40-k19-q256"])
 def test_spectral_step_closed_form(shape, k0, q0, prec):
     """An analytic pin of the step, independent of the oracle: a cosine in x times
     a Gauss-Lobatto cosine in z is one mode of the transform (the latter is an
