@@ -155,8 +155,9 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
             *table(rows[h0:f0])],
         "kernels_fft_512cubed_f64.txt": [
             "rocprofv3 kernel-trace statistics, FP64 R2C+C2R at 512^3, STRIDE1, out-of-place", *head,
-            f"{pairs} pairs (k_c2c_p2d: the FP64 power-of-two Y / Z kernel; k_r2c_x / k_c2r_x <double>: the X "
-            "passes), then one forward for the oracle comparison", *table(rows[f0:o0])],
+            f"{pairs} pairs (k_c2c_p2d: the FP64 power-of-two Y / Z kernel; k_r2c_p2d / k_c2r_p2d: the X passes, "
+            "the backward one <.., true> reading the transposed workspace), then one forward for the oracle "
+            "comparison", *table(rows[f0:o0])],
         "kernels_fft_512cubed_480x360x250.txt": [
             "rocprofv3 kernel-trace statistics, FP32 R2C+C2R at 512^3 (power-of-two kernels) and "
             "480 x 360 x 250 (mixed-radix kernels), STRIDE1, out-of-place", *head,
@@ -181,8 +182,8 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
             "(type-I DCT along z)", *head,
             f"L u, L^T g and autograd forward + backward ({pairs} each), then {pairs} forward + backward "
             "transform pairs",
-            "k_spec_p2<512, 16, ADJ>: the fused z pass (DCT, product, inverse DCT); k_c2c_p2<512, .., 4>: the "
-            "DCT Z passes", *table(rows[s0:h0])],
+            "k_spec_sr<256, ADJ>: the fused z pass (split-radix DCT, product, inverse DCT); "
+            "k_c2c_p2<512, .., 4>: the DCT Z passes (even extension)", *table(rows[s0:h0])],
     }
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     for name, lines in files.items():
