@@ -8,8 +8,8 @@
   Also the two matrix-core precision variants at their stated bounds
   (FP16 x 2: 1e-6, BF16 x 2: 1e-5).
 * 512^3 and 480 x 360 x 250 FP32 random fields: the same checks.
-* 32^3 FP64, uniform[-1, 1] from seed 1: forward, backward and round trip at
-  1e-12.
+* 32^3 FP64, uniform[-1, 1] from seed 1, and the 512^3 FP64 benchmark grid
+  (a random field): forward, backward and round trip at 1e-12.
 * 2048^3 FP32 (eight times the benchmark's grid): round trip and Parseval,
   which hold at any size, reduced on the device.
 * 1024^3 plane wave: every output of the forward transform and of the C2R of
@@ -134,6 +134,29 @@ def test_32_cubed_f64_matches_oracle():
         vd = plan.btran(torch.from_numpy(oracle.to_stride1(V)).cuda())
         torch.cuda.synchronize()
         assert rel(vd.cpu().numpy(), oracle.c2r3d(V, 32)) < 1e-12
+
+
+@pytest.mark.timeout(600)
+def test_512_cubed_f64_matches_oracle():
+    """The FP64 benchmark grid, in the plan bench.py times (FP64 power-of-two X kernels,
+    the transposed backward chain): forward against the oracle, the backward of an
+    arbitrary half spectrum against the oracle's staged C2R, and the round trip, at 1e-12."""
+    n = 512
+    print("case 512^3 FP64", flush=True)
+    u = synth.grf(3, (n, n, n)).astype(np.float64)
+    with pf.Plan(n, n, n, pf.Layout(precision=pf.PF_F64)) as plan:
+        assert plan.pass_kernel(pf.PF_DIR_FORWARD, 0) == "r2c_pow2"
+        assert plan.pass_kernel(pf.PF_DIR_BACKWARD, 2) == "c2r_pow2"
+        assert plan.workspace_layout(pf.PF_DIR_BACKWARD) == pf.PF_WS_TRANSPOSED
+        Ud = plan.ftran(torch.from_numpy(u).cuda())
+        assert rel(Ud.cpu().numpy(), oracle.to_stride1(oracle.r2c3d(u))) < 1e-12
+        back = plan.btran(Ud)
+        del Ud
+        assert rel(back.cpu().numpy() / u.size, u) < 1e-12
+        del back
+        V = synth.complex_half(6, (n, n, n // 2 + 1))
+        vd = plan.btran(torch.from_numpy(oracle.to_stride1(V)).cuda())
+        assert rel(vd.cpu().numpy(), oracle.c2r3d(V, n)) < 1e-12
 
 
 @pytest.mark.timeout(600)
