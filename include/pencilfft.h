@@ -304,7 +304,9 @@ const char *pf_pass_name(const pf_plan *p, int dir, int pass);
  * and ny up to 512 uses the transposed form: its Z pass reads adjacent
  * Z-pencil lines per tile, its Y pass runs in place along contiguous lines,
  * its X pass reads the rows of one tile's lines (the same two transposes of
- * Sec. 2, placed differently).  Returns PF_EINVAL for a NULL plan or a bad dir.
+ * Sec. 2, placed differently).  The forward chain of such an FP32 plan uses
+ * it too, mirrored: X writes the rows, Y runs along the lines, Z writes
+ * adjacent Z-pencil lines.  Returns PF_EINVAL for a NULL plan or a bad dir.
  */
 #define PF_WS_BLOCKED 0
 #define PF_WS_TRANSPOSED 1

@@ -43,6 +43,7 @@ struct PlanOpts {
     bool no_mr = false;  // keep the runtime-radix kernels where a compile-time mixed-radix one exists
     bool no_spec_sr = false;  // fused spectral step by the even extension even where the split form exists
     bool no_bwd_tr = false;  // backward chain on W (no transposed workspace)
+    bool no_fwd_tr = false;  // forward chain on W (no transposed workspace)
     bool external_ws = false;
     int radix_order[3] = {0, 0, 0};
     int tile[3] = {0, 0, 0};
@@ -80,7 +81,7 @@ struct pf_plan {
     // 5.21 -> 5.09 ms, 2048 x 512 x 512 5.57 -> 5.29 ms; at ny = 1024 (1024^3,
     // 9.83 -> 10.0 ms) the Y pass along 8 KB lines and the X pass's rows 8 KB
     // apart lose more than the Z pass gains, so W stays there.
-    bool bwd_tr;
+    bool bwd_tr, fwd_tr;
     bool own_ws;
     bool blocked;      // m1 m2 > 1: user arrays are the concatenated Table 1 blocks
     bool share;        // share-only: user arrays are rank (r1, r2)'s blocks
@@ -312,6 +313,10 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
 // faster up to 512, slower at 1024)
 #ifndef PF_BWD_TR_MAX_NY
 #define PF_BWD_TR_MAX_NY 512
+#endif
+// 1: plans that take the transposed backward chain take the forward one too (FP32)
+#ifndef PF_FWD_TR
+#define PF_FWD_TR 1
 #endif
 #ifndef PF_TILE_ORDER_FZ
 #define PF_TILE_ORDER_FZ 0
@@ -706,9 +711,10 @@ void build_passes(pf_plan *p) {
         if (z.kind == pf::PASS_C2C_MR) z.a.tile_order = PF_TILE_ORDER_MRZ;
         z.blocks = c2c_grid(p, z);
 
-        if (dir == 1 && p->bwd_tr) {
+        if ((dir == 1 && p->bwd_tr) || (dir == 0 && p->fwd_tr)) {
             // Z: 16 adjacent ky lines of one kx of the Z-pencil per tile (one
-            // contiguous run) -> rows (z, kx, ky block) of W'
+            // contiguous run) <-> rows (z, kx, ky block) of W' (backward: lines in,
+            // rows out; forward: rows in, lines out)
             PassDesc z2;
             set_c2c_common(z2, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], true, 2);
             const long long tcz = 1LL << z2.a.tc_log2;
@@ -718,8 +724,8 @@ void build_passes(pf_plan *p) {
             Side zi, zo;
             zi.sa = (long long)p->ny * p->nz, zi.sblk = 0, zi.sc = p->nz, zi.sp = 1, zi.cpb = z2.a.CB, zi.v8 = 0;
             zo.sa = p->ny, zo.sblk = 0, zo.sc = 1, zo.sp = (long long)p->nxh * p->ny, zo.cpb = z2.a.CB, zo.v8 = 0;
-            z2.a.in_s = zi;
-            z2.a.out_s = zo;
+            z2.a.in_s = dir == 1 ? zi : zo;
+            z2.a.out_s = dir == 1 ? zo : zi;
             z2.a.tile_order = 0;
             z2.blocks = c2c_grid(p, z2);
             // Y: in place along the contiguous ky lines of W', 16 adjacent kx per tile
@@ -1188,6 +1194,9 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     p->bwd_tr = !o.no_bwd_tr && p->fast_x && l->stride1 && !p->share && !p->blocked && !p->fused &&
                 l->third == PF_THIRD_FFT && l->math == PF_PLAIN && ny % pf::p2x_tile_lines(l->precision) == 0 &&
                 ny <= PF_BWD_TR_MAX_NY;
+    // the forward chain on the same transposed workspace (FP32: the X pass then
+    // writes rows of 16 lines at one mode)
+    p->fwd_tr = !o.no_fwd_tr && p->bwd_tr && l->precision == PF_F32 && PF_FWD_TR;
     if (p->share) {
         p->ws_bytes += (size_t)p->nxh * ny * nz * p->csize;
     } else if (p->blocked) {
@@ -1323,7 +1332,8 @@ const char *pf_pass_name(const pf_plan *p, int dir, int pass) {
 
 int pf_workspace_layout(const pf_plan *p, int dir) {
     if (!p || (dir != PF_DIR_FORWARD && dir != PF_DIR_BACKWARD)) return PF_EINVAL;
-    return dir == PF_DIR_BACKWARD && p->bwd_tr ? PF_WS_TRANSPOSED : PF_WS_BLOCKED;
+    return (dir == PF_DIR_BACKWARD && p->bwd_tr) || (dir == PF_DIR_FORWARD && p->fwd_tr) ? PF_WS_TRANSPOSED
+                                                                                           : PF_WS_BLOCKED;
 }
 
 const char *pf_pass_kernel(const pf_plan *p, int dir, int pass) {

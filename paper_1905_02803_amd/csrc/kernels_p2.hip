@@ -1240,7 +1240,7 @@ __device__ __forceinline__ long long x_rowoff(const PassArgs &a, int g) {
 // split and stores of one tile.  tv: the thread's index among the NT threads
 // of one tile; buf, rowoff: that tile's LDS work area; tables: twiddles (the
 // M-point stage table, then the split table at M), A operands at 2 M + 2.
-template <int M, int MT>
+template <int M, int MT, bool TR = false>
 struct R2cP2 {
     static constexpr int TC = 16;
     static constexpr int T = M / 16;
@@ -1396,6 +1396,29 @@ struct R2cP2 {
             xa = cadd(Ea, cmul(w, Oa));
             xb = cadd(Eb, cmul(w, Ob));
         };
+        if constexpr (TR) {
+            // transposed rows: mode k of line g = z ny + y at z zrows + k kbrows + y
+            // (zrows = nxh ny, kbrows = ny, ny a multiple of 16), so one row holds the
+            // tile's 16 lines at one mode.  Item f: line pair pr = f & 7 (lanes along
+            // the row), mode k = f >> 3 < M; the items of k = 0 also store mode M.
+            const int g0 = 16 * t;
+            const int z0 = g0 / a.ny;
+            const int y0 = g0 - z0 * a.ny;
+            cx<float> *tb = out + (long long)z0 * a.zrows + y0;
+            const int ks = (int)a.kbrows;
+            for (int f = tv; f < M * 8; f += NT) {
+                const int pr = f & 7, k = f >> 3;
+                float2 xa, xb;
+                split(k, pr, xa, xb);
+                gst<NTS>(reinterpret_cast<float4 *>(tb + (k * ks + 2 * pr)), pack2(xa, xb));
+                if (k == 0) {
+                    split(M, pr, xa, xb);
+                    gst<NTS>(reinterpret_cast<float4 *>(tb + (M * ks + 2 * pr)), pack2(xa, xb));
+                }
+            }
+            __syncthreads();  // the LDS tile is reused by the next tile
+            return;
+        }
         for (int f = tv; f < (NKB - 1) * 64; f += NT) {
             const int kb = f >> 6, pr = (f >> 3) & 7, kp = f & 7;
             const int ga = 16 * t + 2 * pr;
@@ -1420,9 +1443,9 @@ struct R2cP2 {
     }
 };
 
-template <int M, int MT>
+template <int M, int MT, bool TR = false>
 __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2(PassArgs a) {
-    typedef R2cP2<M, MT> K;
+    typedef R2cP2<M, MT, TR> K;
     __shared__ long long rowoff[16];
     float4 *buf = reinterpret_cast<float4 *>(pf_smem);
     K k(a, buf, reinterpret_cast<cx<float> *>(buf + M * K::CP), rowoff);
@@ -2349,7 +2372,8 @@ static const void *p2xd_pick(int nx, int fwd, int tr = 0) {
 static const void *p2x_pick(int nx, int fwd, int mt, int tr = 0) {
 #define PF_X_PICK(NXV, MV)                                                                    \
     if (nx == NXV) {                                                                          \
-        if (tr) return !fwd && mt == 0 ? (const void *)&k_c2r_p2<MV, 0, true> : nullptr;     \
+        if (tr && mt != 0) return nullptr;                                                    \
+        if (tr) return fwd ? (const void *)&k_r2c_p2<MV, 0, true> : (const void *)&k_c2r_p2<MV, 0, true>; \
         if (mt == 0) return fwd ? (const void *)&k_r2c_p2<MV, 0> : (const void *)&k_c2r_p2<MV, 0>; \
         if (MV < 512) return nullptr;                                                         \
         if (mt == 1) return fwd ? (const void *)&k_r2c_p2<MV, MV < 512 ? 0 : 1>               \
@@ -2376,7 +2400,7 @@ hipError_t p2x_prepare(int nx, int prec) {
         return hipSuccess;
     }
     for (int fwd : {0, 1})
-        for (int mt = 0; mt < 4; ++mt) {  // mt 3: the transposed-row backward kernel (plain)
+        for (int mt = 0; mt < 4; ++mt) {  // mt 3: the transposed-row kernels (plain)
         const void *k = mt < 3 ? p2x_pick(nx, fwd, mt) : p2x_pick(nx, fwd, 0, 1);
         if (!k) continue;
         hipError_t r =
@@ -2445,7 +2469,7 @@ static const void *p2_pick_io_dir(int inp, int outp) {
     if (inp == 1 && outp == 0) return p2_kernel<N, TC, DIR, 1, 0, MT>();
     if (inp == 0 && outp == 2) return p2_kernel<N, TC, DIR, 0, 2, MT>();
     if (inp == 2 && outp == 0) return p2_kernel<N, TC, DIR, 2, 0, MT>();
-    if constexpr (DIR > 0 && MT == 0) {  // lines in place: the backward Y pass on the transposed workspace
+    if constexpr (MT == 0) {  // lines in place: the Y passes on the transposed workspace
         if (inp == 1 && outp == 1) return p2_kernel<N, TC, DIR, 1, 1, MT>();
     }
     return nullptr;
@@ -2493,7 +2517,8 @@ static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
 
 const void *p2_symbol(const PassDesc &d) {
     if (d.kind == PASS_C2C_P2 && d.prec == 1) return p2d_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
-    if (d.kind == PASS_R2C_P2) return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 1) : p2x_pick(2 * d.a.fft.n, 1, d.a.math);
+    if (d.kind == PASS_R2C_P2)
+        return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 1) : p2x_pick(2 * d.a.fft.n, 1, d.a.math, d.a.xtr);
     if (d.kind == PASS_C2R_P2)
         return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 0, d.a.xtr) : p2x_pick(2 * d.a.fft.n, 0, d.a.math, d.a.xtr);
     return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);

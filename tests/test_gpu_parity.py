@@ -130,9 +130,9 @@ def test_maximum_lengths_match_oracle(shape, prec, stride1):
                                    (5, 7, 512), (40, 24, 1024), (6, 32, 512), (3, 48, 1024)], ids=ids)
 def test_each_pass_matches_oracle_stage(shape, prec):
     """Every kernel alone against the oracle's own stage (forward X, Y, Z; backward Z, Y, X).
-    The backward intermediate is read in the layout the plan reports (plans with a
-    power-of-two X pass and ny up to 512, a multiple of 16 (FP32) or 8 (FP64), use the
-    transposed one)."""
+    The intermediates are read in the layout the plan reports for each direction (plans
+    with a power-of-two X pass and ny up to 512, a multiple of 16 (FP32) or 8 (FP64), use
+    the transposed one backward, FP32 ones forward too)."""
     nz, ny, nx = shape
     print(f"case shape={shape} prec={prec}", flush=True)
     tol = TOL[prec]
@@ -143,15 +143,21 @@ def test_each_pass_matches_oracle_stage(shape, prec):
         ws = torch.zeros(nws, dtype=plan.complex_dtype, device="cuda")
         ws2 = torch.zeros_like(ws)
         ud = torch.from_numpy(u).cuda()
+        # forward intermediate: transposed for FP32 plans that take the transposed chains
+        ptr = nx in (512, 1024, 2048) and ny % 16 == 0 and ny <= 512
+        layout_f = plan.workspace_layout(pf.PF_DIR_FORWARD)
+        assert layout_f == (pf.PF_WS_TRANSPOSED if prec == pf.PF_F32 and ptr else pf.PF_WS_BLOCKED)
+        viewf = pf.transposed_workspace_to_half_spectrum if layout_f == pf.PF_WS_TRANSPOSED \
+            else pf.workspace_to_half_spectrum
         plan.run_pass(pf.PF_DIR_FORWARD, 0, ud, ws)
         torch.cuda.synchronize()
         A = oracle.stage_x_r2c(u)
-        got = pf.workspace_to_half_spectrum(ws, nx, ny, nz).cpu().numpy()
+        got = viewf(ws, nx, ny, nz).cpu().numpy()
         assert rel(got, A) < tol
         plan.run_pass(pf.PF_DIR_FORWARD, 1, ws, ws)
         torch.cuda.synchronize()
         A = oracle.stage_c2c(A, nx, "y", -1)
-        assert rel(pf.workspace_to_half_spectrum(ws, nx, ny, nz).cpu().numpy(), A) < tol
+        assert rel(viewf(ws, nx, ny, nz).cpu().numpy(), A) < tol
         out = plan.empty_complex()
         plan.run_pass(pf.PF_DIR_FORWARD, 2, ws, out)
         torch.cuda.synchronize()
