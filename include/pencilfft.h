@@ -297,16 +297,16 @@ const char *pf_pass_name(const pf_plan *p, int dir, int pass);
 /*
  * Layout of the workspace between the transform passes of direction dir:
  * PF_WS_BLOCKED, the [nz][nkb][ny][B] rows above, or PF_WS_TRANSPOSED,
- * complex [nz][nxh][ny] (mode kx of line (y, z) at [z][kx][y]: 128-byte rows
- * of 16 FP32 or 8 FP64 lines at one mode).  The backward chain of a plain
- * STRIDE1 1 x 1 plan with a power-of-two X pass (FP32: nx in {512, 1024,
- * 2048}, ny a multiple of 16; FP64: nx in {512, 1024}, ny a multiple of 8)
- * and ny up to 512 uses the transposed form: its Z pass reads adjacent
- * Z-pencil lines per tile, its Y pass runs in place along contiguous lines,
- * its X pass reads the rows of one tile's lines (the same two transposes of
- * Sec. 2, placed differently).  The forward chain of such an FP32 plan uses
- * it too, mirrored: X writes the rows, Y runs along the lines, Z writes
- * adjacent Z-pencil lines.  Returns PF_EINVAL for a NULL plan or a bad dir.
+ * complex [nz][nxh][ny] (mode kx of line (y, z) at [z][kx][y]: rows of 16
+ * lines at one mode, 128 bytes FP32, 256 bytes FP64).  Both chains of a plain STRIDE1 1 x 1 plan with
+ * a power-of-two X pass (FP32: nx in {512, 1024, 2048}; FP64: nx in {512,
+ * 1024}) and ny a multiple of 16 up to 512 use the transposed form: backward,
+ * the Z pass reads adjacent Z-pencil lines per tile, the Y pass runs in place
+ * along contiguous lines and the X pass reads the rows of one tile's 16
+ * lines; forward (FP64: at nx = 512), mirrored (X writes the rows, Y runs
+ * along the lines, Z writes adjacent Z-pencil lines): the same two transposes
+ * of Sec. 2, placed differently.  Returns PF_EINVAL for a NULL plan or a bad
+ * dir.
  */
 #define PF_WS_BLOCKED 0
 #define PF_WS_TRANSPOSED 1

@@ -314,7 +314,7 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
 #ifndef PF_BWD_TR_MAX_NY
 #define PF_BWD_TR_MAX_NY 512
 #endif
-// 1: plans that take the transposed backward chain take the forward one too (FP32)
+// 1: plans that take the transposed backward chain take the forward one too
 #ifndef PF_FWD_TR
 #define PF_FWD_TR 1
 #endif
@@ -512,7 +512,7 @@ void build_share_only(pf_plan *p) {
         x.a.ny = yl1;
         x.a.y0 = ys1;
         if (x.kind == pf::PASS_R2C_P2 || x.kind == pf::PASS_C2R_P2) {
-            const long long tl = pf::p2x_tile_lines(x.prec);
+            const long long tl = pf::p2x_tile_lines(x.prec, 0);
             const long long tiles = (x.a.lines + tl - 1) / tl;
             const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(x);
             x.blocks = (unsigned)std::min(tiles, resident);
@@ -671,9 +671,9 @@ void build_passes(pf_plan *p) {
             x.a.fft = p->fxh;
             x.a.math = pf::p2_has_mfma(p->nx / 2) && p->lay.precision == PF_F32 ? p->lay.math : 0;
             x.a.tw = (const char *)p->tw_dev + p->tw_off[3];
-            x.threads = (unsigned)pf::p2x_threads(p->nx);
-            x.lds = pf::p2x_lds_bytes(p->nx, x.a.math, x.prec);
-            const long long tl = pf::p2x_tile_lines(x.prec);
+            x.threads = (unsigned)pf::p2x_threads(p->nx, x.prec, 0);
+            x.lds = pf::p2x_lds_bytes(p->nx, x.a.math, x.prec, 0);
+            const long long tl = pf::p2x_tile_lines(x.prec, 0);
             const long long tiles = (x.a.lines + tl - 1) / tl;
             const long long resident = (long long)p->ncu * pf::p2_blocks_per_cu(x);
             x.blocks = (unsigned)(tiles < resident ? tiles : resident);
@@ -741,11 +741,14 @@ void build_passes(pf_plan *p) {
             y2.a.out_s = yl;
             y2.a.tile_order = 0;
             y2.blocks = c2c_grid(p, y2);
-            // X: rows of W' hold 16 (FP64: 8) lines at one mode (its own kernel: the grid again)
+            // X: rows of W' hold a tile's 16 lines at one mode (its own kernel, for FP64
+            // with 16-line tiles: the grid again)
             x.a.xtr = 1;
             x.a.zrows = (long long)p->nxh * p->ny;
             x.a.kbrows = p->ny;
-            const long long xtl = pf::p2x_tile_lines(x.prec);
+            x.threads = (unsigned)pf::p2x_threads(p->nx, x.prec, 1);
+            x.lds = pf::p2x_lds_bytes(p->nx, x.a.math, x.prec, 1);
+            const long long xtl = pf::p2x_tile_lines(x.prec, 1);
             const long long xtiles = (x.a.lines + xtl - 1) / xtl;
             const long long xres = (long long)p->ncu * pf::p2_blocks_per_cu(x);
             x.blocks = (unsigned)(xtiles < xres ? xtiles : xres);
@@ -1189,14 +1192,15 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     p->blocked = !p->share && l->m1 * l->m2 > 1;
     p->w_bytes = ((size_t)p->nz * p->nkb * p->ny * p->B * p->csize + 255) & ~(size_t)255;
     p->ws_bytes = p->w_bytes;
-    // (ny a multiple of the X tile's lines: 16 FP32, 8 FP64, so that a row of the
-    // transposed workspace holds one tile's lines at one mode)
+    // (ny a multiple of the X tile's 16 lines, so that a row of the transposed
+    // workspace holds one tile's lines at one mode)
     p->bwd_tr = !o.no_bwd_tr && p->fast_x && l->stride1 && !p->share && !p->blocked && !p->fused &&
-                l->third == PF_THIRD_FFT && l->math == PF_PLAIN && ny % pf::p2x_tile_lines(l->precision) == 0 &&
+                l->third == PF_THIRD_FFT && l->math == PF_PLAIN && ny % pf::p2x_tile_lines(l->precision, 1) == 0 &&
                 ny <= PF_BWD_TR_MAX_NY;
-    // the forward chain on the same transposed workspace (FP32: the X pass then
-    // writes rows of 16 lines at one mode)
-    p->fwd_tr = !o.no_fwd_tr && p->bwd_tr && l->precision == PF_F32 && PF_FWD_TR;
+    // the forward chain on the same transposed workspace (the X pass then writes
+    // rows of 16 lines at one mode); FP64 at nx = 512 only: at nx = 1024 its
+    // 16-line X tile needs 136 KB of LDS (one workgroup per CU) and measured slower
+    p->fwd_tr = !o.no_fwd_tr && p->bwd_tr && (l->precision == PF_F32 || nx <= 512) && PF_FWD_TR;
     if (p->share) {
         p->ws_bytes += (size_t)p->nxh * ny * nz * p->csize;
     } else if (p->blocked) {

@@ -1734,9 +1734,12 @@ __device__ __forceinline__ long long xd_rowoff(const PassArgs &a, int g) {
     return ((long long)z * a.zrows + a.y0 + y) << 3;
 }
 
-template <int M>
-__global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2d(PassArgs a) {
-    constexpr int TC = 8;  // lines per tile
+// TR: the spectra go to the transposed workspace (mode k of line g = z ny + y at
+// z zrows + k kbrows + y, zrows = nxh ny, kbrows = ny, ny a multiple of 16): a
+// tile is then 16 lines, so that one row holds 256 contiguous bytes per mode.
+template <int M, bool TR = false>
+__global__ __launch_bounds__(M / 16 * (TR ? 16 : 8)) void k_r2c_p2d(PassArgs a) {
+    constexpr int TC = TR ? 16 : 8;  // lines per tile
     constexpr int T = M / 16;
     constexpr int NT = T * TC;
     constexpr int S = p2_stages(M);
@@ -1755,7 +1758,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2d(PassArgs a) {
     const int lines = (int)a.lines;
     const int ntiles = (lines + TC - 1) / TC;
     const long long kbstride = a.kbrows << 3;
-    auto slot = [](int p, int c) { return p2_slot<16>(p, c); };
+    auto slot = [](int p, int c) { return p2_slot<2 * TC>(p, c); };
     // line l = tv / T of tile t, points q + T m (lanes along the line)
     auto load = [&](cd(&d)[16], int t) {
         const int tv = opaque_tid();
@@ -1783,7 +1786,7 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2d(PassArgs a) {
         for (int m = 0; m < 16; ++m) v[m] = p[m];
         const int tn = t + gridDim.x;
         if (tn < ntiles) load(p, tn);
-        if (tv < TC && TC * t + tv < lines) rowoff[tv] = xd_rowoff(a, TC * t + tv);
+        if (!TR && tv < TC && TC * t + tv < lines) rowoff[tv] = xd_rowoff(a, TC * t + tv);
         Dft<double, 16, -1>::run(v);
 #pragma unroll
         for (int r = 0; r < 16; ++r) buf[slot(q_in * 16 + r, c_in)] = v[r];
@@ -1814,6 +1817,22 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2d(PassArgs a) {
             const cd O = make_double2(0.5 * (zk.y + zm.y), 0.5 * (zm.x - zk.x));
             return cadd(E, cmul(spl[k], O));
         };
+        if constexpr (TR) {
+            // item f: line l = f & 15 (lanes along the row), mode k = f >> 4 < M; the
+            // items of k = 0 also store mode M
+            const int g0 = TC * t;
+            const int z0 = g0 / a.ny;
+            const int y0 = g0 - z0 * a.ny;
+            cd *tb = out + (long long)z0 * a.zrows + y0;
+            const int ks = (int)a.kbrows;
+            for (int f = tv; f < M * TC; f += NT) {
+                const int l = f & (TC - 1), k = f / TC;
+                gst_d<streamed<ST_R2C>()>(reinterpret_cast<double2 *>(tb + (k * ks + l)), split(k, l));
+                if (k == 0) gst_d<streamed<ST_R2C>()>(reinterpret_cast<double2 *>(tb + (M * ks + l)), split(M, l));
+            }
+            __syncthreads();  // the LDS tile is reused by the next tile
+            continue;
+        }
         // item f = (column block kb, line l, mode j): 8 lanes store one 128-byte row;
         // the items of k = 0 also store mode M, alone in the last column block
         for (int f = tv; f < (NKB - 1) * 64; f += NT) {
@@ -1830,8 +1849,8 @@ __global__ __launch_bounds__(M / 16 * 8) void k_r2c_p2d(PassArgs a) {
 }
 
 template <int M, bool TR = false>
-__global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2d(PassArgs a) {
-    constexpr int TC = 8;
+__global__ __launch_bounds__(M / 16 * (TR ? 16 : 8)) void k_c2r_p2d(PassArgs a) {
+    constexpr int TC = TR ? 16 : 8;  // lines per tile (TR: 256-byte transposed rows)
     constexpr int T = M / 16;
     constexpr int NT = T * TC;
     constexpr int S = p2_stages(M);
@@ -1849,19 +1868,19 @@ __global__ __launch_bounds__(M / 16 * 8) void k_c2r_p2d(PassArgs a) {
     double *__restrict__ out = reinterpret_cast<double *>(a.out);
     const int lines = (int)a.lines;
     const int ntiles = (lines + TC - 1) / TC;
-    auto slot = [](int p, int c) { return p2_slot<16>(p, c); };
+    auto slot = [](int p, int c) { return p2_slot<2 * TC>(p, c); };
     // item i: f = tv + NT i -> mode k < M/2 of line l; it holds X[k] and X[M-k]
     // (for k = 0 the partner is X[M], the first slot of the last column
-    // block), and threads 0..7 hold X[M/2] of line tv.  A wave reads whole
-    // 128-byte rows.  Blocked rows (8 modes of one line): k = 8 (f >> 6) +
-    // (f & 7), l = (f >> 3) & 7.  Transposed rows (TR: mode k of line g = z ny
-    // + y at z zrows + k kbrows + y, zrows = nxh ny, kbrows = ny, so one row
-    // holds the tile's 8 lines at one mode; ny is a multiple of 8): l = f & 7,
-    // k = f >> 3.
+    // block), and threads 0..TC-1 hold X[M/2] of line tv.  A wave reads whole
+    // rows.  Blocked rows (8 modes of one line): k = 8 (f >> 6) + (f & 7),
+    // l = (f >> 3) & 7.  Transposed rows (TR: mode k of line g = z ny + y at
+    // z zrows + k kbrows + y, zrows = nxh ny, kbrows = ny, so one 256-byte row
+    // holds the tile's 16 lines at one mode; ny is a multiple of 16): l = f & 15,
+    // k = f >> 4.
     auto item = [](int f, int &k, int &l) {
         if constexpr (TR) {
-            l = f & 7;
-            k = f >> 3;
+            l = f & (TC - 1);
+            k = f / TC;
         } else {
             l = (f >> 3) & 7;
             k = ((f >> 6) << 3) + (f & 7);
@@ -2349,22 +2368,22 @@ bool p2x_supported(int nx, int prec) {
     return (prec == 0 && (nx == 512 || nx == 1024 || nx == 2048)) || (prec == 1 && (nx == 512 || nx == 1024));
 }
 
-int p2x_threads(int nx) { return nx / 2 / 16 * 8; }
+int p2x_threads(int nx, int prec, int tr) { return nx / 2 / 16 * (prec == 1 && tr ? 16 : 8); }
 
-int p2x_tile_lines(int prec) { return prec == 1 ? 8 : 16; }
+int p2x_tile_lines(int prec, int tr) { return prec == 1 && !tr ? 8 : 16; }
 
-size_t p2x_lds_bytes(int nx, int math, int prec) {
+size_t p2x_lds_bytes(int nx, int math, int prec, int tr) {
     const int M = nx / 2;
-    if (prec == 1) return (size_t)M * 8 * sizeof(double2) + (size_t)M * sizeof(double2);
+    if (prec == 1) return (size_t)M * p2x_tile_lines(1, tr) * sizeof(double2) + (size_t)M * sizeof(double2);
     return (size_t)M * 16 * sizeof(float2) + (size_t)(2 * M + 2) * sizeof(float2) + (math ? kMfmaTableBytes : 0);
 }
 
 static const void *p2xd_pick(int nx, int fwd, int tr = 0) {
     if (nx == 512)
-        return fwd ? (tr ? nullptr : (const void *)&k_r2c_p2d<256>)
+        return fwd ? (tr ? (const void *)&k_r2c_p2d<256, true> : (const void *)&k_r2c_p2d<256>)
                    : (tr ? (const void *)&k_c2r_p2d<256, true> : (const void *)&k_c2r_p2d<256>);
     if (nx == 1024)
-        return fwd ? (tr ? nullptr : (const void *)&k_r2c_p2d<512>)
+        return fwd ? (tr ? (const void *)&k_r2c_p2d<512, true> : (const void *)&k_r2c_p2d<512>)
                    : (tr ? (const void *)&k_c2r_p2d<512, true> : (const void *)&k_c2r_p2d<512>);
     return nullptr;
 }
@@ -2390,11 +2409,11 @@ static const void *p2x_pick(int nx, int fwd, int mt, int tr = 0) {
 hipError_t p2x_prepare(int nx, int prec) {
     hipError_t e = hipSuccess;
     if (prec == 1) {
-        for (int v : {0, 1, 2}) {  // backward, forward, backward on transposed rows
-            const void *k = p2xd_pick(nx, v == 1, v == 2);
+        for (int v = 0; v < 4; ++v) {  // (forward, transposed rows) = (v & 1, v >> 1)
+            const void *k = p2xd_pick(nx, v & 1, v >> 1);
             if (!k) return hipErrorInvalidValue;
-            const hipError_t r =
-                hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, 0, 1));
+            const hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)p2x_lds_bytes(nx, 0, 1, v >> 1));
             if (r != hipSuccess) return r;
         }
         return hipSuccess;
@@ -2404,7 +2423,7 @@ hipError_t p2x_prepare(int nx, int prec) {
         const void *k = mt < 3 ? p2x_pick(nx, fwd, mt) : p2x_pick(nx, fwd, 0, 1);
         if (!k) continue;
         hipError_t r =
-            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, mt < 3 ? mt : 0, 0));
+            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2x_lds_bytes(nx, mt < 3 ? mt : 0, 0, 0));
         if (r != hipSuccess && e == hipSuccess) e = r;
         }
     return e;
@@ -2429,8 +2448,8 @@ static const void *p2d_pick_dir(int inp, int outp) {
     if (inp == 0 && outp == 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 0, 0>);
     if (inp == 0 && outp == 1) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 0, 1>);
     if (inp == 1 && outp == 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 1, 0>);
-    // lines on both sides: the backward Y pass of the transposed chain
-    if (inp == 1 && outp == 1 && DIR > 0) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 1, 1>);
+    // lines on both sides: the Y passes of the transposed chains
+    if (inp == 1 && outp == 1) return reinterpret_cast<const void *>(&k_c2c_p2d<N, DIR, 1, 1>);
     return nullptr;
 }
 
@@ -2447,10 +2466,7 @@ hipError_t p2d_prepare(int n) {
     for (int dir : {-1, 1})
         for (int io = 0; io < 4; ++io) {  // (inp, outp): (0,0) (0,1) (1,0) (1,1)
             const void *k = p2d_pick(n, dir, io >= 2 ? 1 : 0, io & 1);
-            if (!k) {
-                if (io == 3 && dir < 0) continue;
-                return hipErrorInvalidValue;
-            }
+            if (!k) return hipErrorInvalidValue;
             const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p2d_lds_bytes(n));
             if (e != hipSuccess) return e;
         }
@@ -2518,7 +2534,7 @@ static const void *p2_pick(int n, int dir, int inp, int outp, int mt) {
 const void *p2_symbol(const PassDesc &d) {
     if (d.kind == PASS_C2C_P2 && d.prec == 1) return p2d_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp);
     if (d.kind == PASS_R2C_P2)
-        return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 1) : p2x_pick(2 * d.a.fft.n, 1, d.a.math, d.a.xtr);
+        return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 1, d.a.xtr) : p2x_pick(2 * d.a.fft.n, 1, d.a.math, d.a.xtr);
     if (d.kind == PASS_C2R_P2)
         return d.prec == 1 ? p2xd_pick(2 * d.a.fft.n, 0, d.a.xtr) : p2x_pick(2 * d.a.fft.n, 0, d.a.math, d.a.xtr);
     return p2_pick(d.a.fft.n, d.dir, d.a.inp, d.a.outp, d.a.math);

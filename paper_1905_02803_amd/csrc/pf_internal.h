@@ -249,11 +249,13 @@ bool p2_spec_sr_supported(int nz);
 unsigned p2_spec_sr_threads(int nz);
 size_t p2_spec_sr_lds_bytes(int nz);
 // Even power-of-two X stage (fft.n of the pass is nx / 2): FP32 for nx = 512 ..
-// 2048 (tiles of 16 lines), FP64 for nx = 512, 1024 (tiles of 8 lines).
+// 2048 (tiles of 16 lines), FP64 for nx = 512, 1024 (tiles of 8 lines, 16 on
+// the transposed workspace).
+// (tr: the pass reads / writes the transposed workspace; FP64 tiles are then 16 lines)
 bool p2x_supported(int nx, int prec);
-int p2x_threads(int nx);
-int p2x_tile_lines(int prec);
-size_t p2x_lds_bytes(int nx, int math, int prec);
+int p2x_threads(int nx, int prec, int tr);
+int p2x_tile_lines(int prec, int tr);
+size_t p2x_lds_bytes(int nx, int math, int prec, int tr);
 hipError_t p2x_prepare(int nx, int prec);
 
 // LDS index with one pad slot every 16 complex elements (spreads the strided

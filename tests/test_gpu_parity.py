@@ -131,8 +131,8 @@ def test_maximum_lengths_match_oracle(shape, prec, stride1):
 def test_each_pass_matches_oracle_stage(shape, prec):
     """Every kernel alone against the oracle's own stage (forward X, Y, Z; backward Z, Y, X).
     The intermediates are read in the layout the plan reports for each direction (plans
-    with a power-of-two X pass and ny up to 512, a multiple of 16 (FP32) or 8 (FP64), use
-    the transposed one backward, FP32 ones forward too)."""
+    with a power-of-two X pass and ny a multiple of 16 up to 512 use the transposed one;
+    forward, FP64 plans only at nx = 512)."""
     nz, ny, nx = shape
     print(f"case shape={shape} prec={prec}", flush=True)
     tol = TOL[prec]
@@ -143,10 +143,12 @@ def test_each_pass_matches_oracle_stage(shape, prec):
         ws = torch.zeros(nws, dtype=plan.complex_dtype, device="cuda")
         ws2 = torch.zeros_like(ws)
         ud = torch.from_numpy(u).cuda()
-        # forward intermediate: transposed for FP32 plans that take the transposed chains
-        ptr = nx in (512, 1024, 2048) and ny % 16 == 0 and ny <= 512
+        # the intermediates are transposed for plans that take the transposed chains
+        # (the forward one for FP64 at nx = 512 only)
+        transposed = ny % 16 == 0 and ny <= 512 and nx in ((512, 1024, 2048) if prec == pf.PF_F32 else (512, 1024))
         layout_f = plan.workspace_layout(pf.PF_DIR_FORWARD)
-        assert layout_f == (pf.PF_WS_TRANSPOSED if prec == pf.PF_F32 and ptr else pf.PF_WS_BLOCKED)
+        ftr = transposed and (prec == pf.PF_F32 or nx == 512)
+        assert layout_f == (pf.PF_WS_TRANSPOSED if ftr else pf.PF_WS_BLOCKED)
         viewf = pf.transposed_workspace_to_half_spectrum if layout_f == pf.PF_WS_TRANSPOSED \
             else pf.workspace_to_half_spectrum
         plan.run_pass(pf.PF_DIR_FORWARD, 0, ud, ws)
@@ -165,8 +167,6 @@ def test_each_pass_matches_oracle_stage(shape, prec):
         assert rel(out.cpu().numpy(), oracle.to_stride1(A)) < tol
         # backward stages on an arbitrary half spectrum
         layout = plan.workspace_layout(pf.PF_DIR_BACKWARD)
-        transposed = ny <= 512 and ((prec == pf.PF_F32 and nx in (512, 1024, 2048) and ny % 16 == 0) or
-                                    (prec == pf.PF_F64 and nx in (512, 1024) and ny % 8 == 0))
         assert layout == (pf.PF_WS_TRANSPOSED if transposed else pf.PF_WS_BLOCKED)
         view = pf.transposed_workspace_to_half_spectrum if transposed else pf.workspace_to_half_spectrum
         V = synth.complex_half(400 + nx, (nz, ny, nx // 2 + 1)).astype(np_cplx(prec))

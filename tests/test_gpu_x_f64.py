@@ -3,8 +3,9 @@ line of half the length, its DFT and the split into nx / 2 + 1 modes
 (Sec. 3.2), eight lines per tile.  Checked against the oracle's X stage alone
 and the whole transform, on tile-ragged line counts (one line, fewer lines
 than a tile, more tiles than the resident grid) and in place.  With ny a
-multiple of 8 the backward X pass reads the transposed workspace [nz][nxh][ny]
-(rows of the tile's 8 lines at one mode)."""
+multiple of 16 up to 512 the backward X pass (and at nx = 512 the forward one)
+uses the transposed workspace [nz][nxh][ny] with 16-line tiles (one 256-byte
+row per mode)."""
 import numpy as np
 import pytest
 
@@ -23,7 +24,8 @@ def rel(a, b):
     return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
 
 
-SHAPES = [(1, 1, 512), (3, 5, 512), (2, 7, 1024), (9, 8, 512), (4, 300, 512), (35, 40, 1024)]
+SHAPES = [(1, 1, 512), (3, 5, 512), (2, 7, 1024), (9, 8, 512), (4, 300, 512), (35, 40, 1024),
+          (5, 16, 512), (3, 32, 1024), (2, 512, 512)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda v: "x".join(map(str, v[::-1])))
@@ -35,18 +37,23 @@ def test_f64_power_of_two_x_stage_matches_oracle(shape):
     with pf.Plan(nx, ny, nz, pf.Layout(precision=pf.PF_F64, stride1=1)) as plan:
         assert plan.pass_kernel(pf.PF_DIR_FORWARD, 0) == "r2c_pow2"
         assert plan.pass_kernel(pf.PF_DIR_BACKWARD, 2) == "c2r_pow2"
-        # the X stage alone, both directions
+        # the X stage alone, both directions; with ny a multiple of 16 up to 512 the
+        # intermediates are the transposed workspace [nz][nxh][ny] (16-line tiles):
+        # backward always, forward at nx = 512
+        transposed = ny % 16 == 0 and ny <= 512
+        ftr = transposed and nx == 512
+        assert plan.workspace_layout(pf.PF_DIR_FORWARD) == (pf.PF_WS_TRANSPOSED if ftr else pf.PF_WS_BLOCKED)
+        assert plan.workspace_layout(pf.PF_DIR_BACKWARD) == (pf.PF_WS_TRANSPOSED if transposed else pf.PF_WS_BLOCKED)
+        viewf = pf.transposed_workspace_to_half_spectrum if ftr else pf.workspace_to_half_spectrum
         ws = torch.zeros(plan.workspace_bytes // 16, dtype=torch.complex128, device="cuda")
         plan.run_pass(pf.PF_DIR_FORWARD, 0, torch.from_numpy(u).cuda(), ws)
         torch.cuda.synchronize()
-        assert rel(pf.workspace_to_half_spectrum(ws, nx, ny, nz).cpu().numpy(), oracle.stage_x_r2c(u)) < TOL
+        assert rel(viewf(ws, nx, ny, nz).cpu().numpy(), oracle.stage_x_r2c(u)) < TOL
         ws.zero_()
         Vd = torch.from_numpy(V).cuda()
-        if plan.workspace_layout(pf.PF_DIR_BACKWARD) == pf.PF_WS_TRANSPOSED:  # [nz][nxh][ny]
-            assert ny % 8 == 0 and ny <= 512
+        if transposed:
             ws[: V.size].copy_(Vd.permute(0, 2, 1).reshape(-1))
         else:
-            assert ny % 8 or ny > 512
             pf.half_spectrum_to_workspace(Vd, ws)
         r = plan.empty_real()
         plan.run_pass(pf.PF_DIR_BACKWARD, 2, ws, r)
