@@ -156,8 +156,8 @@ def summarize_trace(trace_csv: str, command: str, steps: int, warmup: int) -> No
         "kernels_fft_512cubed_f64.txt": [
             "rocprofv3 kernel-trace statistics, FP64 R2C+C2R at 512^3, STRIDE1, out-of-place", *head,
             f"{pairs} pairs (k_c2c_p2d: the FP64 power-of-two Y / Z kernel; k_r2c_p2d / k_c2r_p2d: the X passes, "
-            "the backward one <.., true> reading the transposed workspace), then one forward for the oracle "
-            "comparison", *table(rows[f0:o0])],
+            "<.., true> on the transposed workspace), then one forward for the oracle comparison",
+            *table(rows[f0:o0])],
         "kernels_fft_512cubed_480x360x250.txt": [
             "rocprofv3 kernel-trace statistics, FP32 R2C+C2R at 512^3 (power-of-two kernels) and "
             "480 x 360 x 250 (mixed-radix kernels), STRIDE1, out-of-place", *head,
