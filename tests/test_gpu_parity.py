@@ -206,7 +206,7 @@ def test_repeat_runs_are_bitwise_identical(shape):
 
 
 @pytest.mark.parametrize("prec", [pf.PF_F32, pf.PF_F64])
-@pytest.mark.parametrize("shape", [(24, 20, 36), (9, 7, 15)], ids=ids)
+@pytest.mark.parametrize("shape", [(24, 20, 36), (9, 7, 15), (4, 32, 512)], ids=ids)
 def test_inplace_matches_out_of_place(shape, prec):
     nz, ny, nx = shape
     u = synth.uniform(8, shape).astype(np_real(prec))
