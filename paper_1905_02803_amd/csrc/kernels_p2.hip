@@ -1721,8 +1721,9 @@ __global__ __launch_bounds__(M / 16 * 8, 2) void k_c2r_p2(PassArgs a) {
 // length nx = 2M is transformed as the complex line z[m] = x[2m] + i x[2m+1]
 // of length M and split into its M + 1 modes, X[k] = E[k] + W_nx^k O[k]; the
 // backward pass inverts the split and runs the inverse DFT_M.  A tile is 8
-// lines, each a column of the FP64 C2C kernel's LDS map (one 16-byte slot per
-// point, 8 per row); workspace rows hold 8 modes (128 bytes).  Twiddles as in
+// lines (16 on the transposed workspace), each a column of the FP64 C2C
+// kernel's LDS map (one 16-byte slot per point and line); workspace rows hold
+// 8 modes (128 bytes).  Twiddles as in
 // FP32: the M-point stage table (M - 1 entries, copied to LDS), then at offset
 // M the split table W_nx^k, k = 0 .. M, read from global memory (in LDS it
 // would cost a block per CU at nx = 512).
@@ -1748,7 +1749,7 @@ __global__ __launch_bounds__(M / 16 * (TR ? 16 : 8)) void k_r2c_p2d(PassArgs a) 
     constexpr int NKB = M / 8 + 1;  // column blocks of 8 modes for the M + 1 modes
     typedef cx<double> cd;
     __shared__ long long rowoff[TC];
-    cd *buf = reinterpret_cast<cd *>(pf_smem);  // M points x 8 lines
+    cd *buf = reinterpret_cast<cd *>(pf_smem);  // M points x TC lines
     cd *twl = buf + M * TC;                     // the stage table; the split table stays in global memory
     const cd *__restrict__ tw = reinterpret_cast<const cd *>(a.tw);
     const cd *__restrict__ spl = tw + M;
