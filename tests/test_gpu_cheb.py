@@ -78,7 +78,7 @@ def test_spectral_step_matches_oracle(shape, stride1):
     assert rel(got, ref) < 1e-12
 
 
-FUSED = [(129, 6, 20), (257, 8, 12), (513, 5, 36), (1025, 3, 16), (2049, 2, 6)]
+FUSED = [(129, 6, 20), (257, 8, 12), (257, 5, 36), (513, 5, 36), (1025, 3, 16), (2049, 2, 6)]
 UNFUSED = [(17, 16, 16), (33, 24, 20), (65, 10, 12)]  # other extension lengths: Z, product, Z as three passes
 
 
