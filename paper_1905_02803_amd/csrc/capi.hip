@@ -318,6 +318,10 @@ void set_c2c_common(PassDesc &d, const pf_plan *p, const FftSpec &fs, size_t two
 #ifndef PF_FWD_TR
 #define PF_FWD_TR 1
 #endif
+// 1: Chebyshev plans with the split spectral kernel take the transposed chains
+#ifndef PF_CHEB_TR
+#define PF_CHEB_TR 1
+#endif
 #ifndef PF_TILE_ORDER_FZ
 #define PF_TILE_ORDER_FZ 0
 #endif
@@ -716,7 +720,9 @@ void build_passes(pf_plan *p) {
             // contiguous run) <-> rows (z, kx, ky block) of W' (backward: lines in,
             // rows out; forward: rows in, lines out)
             PassDesc z2;
-            set_c2c_common(z2, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], true, 2);
+            set_c2c_common(z2, p, fz, p->tw_off[2], sgn, p->B, p->opt.tile[2], !cheb, 2);
+            if (cheb) z2.a.cheb = p->nz;
+            if (cheb && z2.kind == pf::PASS_C2C_P2) z2.a.math = 4;  // the even extension, as above
             const long long tcz = 1LL << z2.a.tc_log2;
             z2.a.A = p->nxh;
             z2.a.CB = (p->ny + tcz - 1) / tcz;
@@ -780,9 +786,11 @@ void build_passes(pf_plan *p) {
         p->npass[dir] = 3;
         if (p->blocked) add_remaps(p, dir);
         if (dir == 0 && cheb && z.kind == pf::PASS_C2C_P2 && p->lay.precision == PF_F32 && !p->blocked && !p->share) {
-            // fused spectral step: the forward Z pass's tiles, W on both sides
+            // fused spectral step: the forward Z pass's tiles, W on both sides (on the
+            // transposed workspace: its rows of 16 ky at one kx, and a.xtr = 1)
             PassDesc f = z;
-            f.a.in_s = f.a.out_s = wsz;
+            f.a.in_s = f.a.out_s = p->fwd_tr ? z.a.in_s : wsz;
+            f.a.xtr = p->fwd_tr ? 1 : 0;
             f.a.inp = f.a.outp = 0;
             f.a.tile_order = 0;
             f.a.xcd = 0;
@@ -1194,9 +1202,11 @@ static int plan_create(int nx, int ny, int nz, const pf_layout *l, const PlanOpt
     p->ws_bytes = p->w_bytes;
     // (ny a multiple of the X tile's 16 lines, so that a row of the transposed
     // workspace holds one tile's lines at one mode)
+    // (Chebyshev plans where the fused spectral step has the split DCT, whose
+    // kernel also runs on the transposed rows)
     p->bwd_tr = !o.no_bwd_tr && p->fast_x && l->stride1 && !p->share && !p->blocked && !p->fused &&
-                l->third == PF_THIRD_FFT && l->math == PF_PLAIN && ny % pf::p2x_tile_lines(l->precision, 1) == 0 &&
-                ny <= PF_BWD_TR_MAX_NY;
+                (l->third == PF_THIRD_FFT || (l->third == PF_THIRD_CHEB && p->spec_sr && PF_CHEB_TR)) &&
+                l->math == PF_PLAIN && ny % pf::p2x_tile_lines(l->precision, 1) == 0 && ny <= PF_BWD_TR_MAX_NY;
     // the forward chain on the same transposed workspace (the X pass then writes
     // rows of 16 lines at one mode); FP64 at nx = 512 only: at nx = 1024 its
     // 16-line X tile needs 136 KB of LDS (one workgroup per CU) and measured slower

@@ -1032,7 +1032,8 @@ __global__ __launch_bounds__(N / 16 * TC / 2) void k_spec_p2(PassArgs a, int nx,
 // with the barriers at the top level; each transform stages the tile's L + 1
 // rows in LDS once, and the two DFT exchanges then reuse that space.  One
 // tile (ky line, 16 kx columns) per workgroup.  The multiplier, the adjoint's
-// weights and the arguments are those of k_spec_p2; a.tw holds the L-point
+// weights and the arguments are those of k_spec_p2 (with a.xtr set, the tile
+// is 16 adjacent ky at one kx of the transposed workspace); a.tw holds the L-point
 // stage table, the M-point stage table (each padded to L and M entries) and
 // W_{4M}^k, k < M.
 template <int L, int ADJ>
@@ -1054,7 +1055,10 @@ __global__ __launch_bounds__(L / 16 * 8 + L / 32 * 8) void k_spec_sr(PassArgs a,
     const cx<float> *__restrict__ tw = reinterpret_cast<const cx<float> *>(a.tw);
     for (int i = tid; i < L + 2 * M; i += NT) twL[i] = tw[i];
     cx<float> *__restrict__ ws = reinterpret_cast<cx<float> *>(a.out);
-    const int ny = (int)a.A;
+    // a.xtr: the tile is 16 adjacent ky at one kx (rows of the transposed
+    // workspace: A = nxh lines of kx, C = ny) instead of 16 kx at one ky
+    const bool tr = a.xtr != 0;
+    const int ny = tr ? a.C : (int)a.A;
     const int CB = (int)a.CB;
     const int t = blockIdx.x;
     const int ta = t / CB, cb = t - ta * CB;
@@ -1170,11 +1174,12 @@ __global__ __launch_bounds__(L / 16 * 8 + L / 32 * 8) void k_spec_sr(PassArgs a,
         const float two_pi = 6.283185307179586f;
         const float kyf = two_pi / (float)ny, kxf = two_pi / (float)nx, kzf = two_pi / (float)(2 * L);
         const float sg = ADJ ? -1.f : 1.f;
-        const int kx0 = cb * TC + 2 * cp;
-        const int kys = 2 * ta <= ny ? ta : ta - ny;
-        const float kyr = kyf * (float)kys;
-        const float kx0r = kxf * (float)kx0, kx1r = kxf * (float)(kx0 + 1);
-        const float r0 = kx0r * kx0r + kyr * kyr, r1 = kx1r * kx1r + kyr * kyr;
+        auto sky = [ny](int k) { return 2 * k <= ny ? k : k - ny; };  // ky in -ny/2 .. ny/2
+        const int c0 = cb * TC + 2 * cp;  // the pair's first column
+        // (kx', ky') of the pair's two columns
+        const float kx0r = kxf * (float)(tr ? ta : c0), kx1r = kxf * (float)(tr ? ta : c0 + 1);
+        const float ky0r = kyf * (float)sky(tr ? c0 : ta), ky1r = kyf * (float)sky(tr ? c0 + 1 : ta);
+        const float r0 = kx0r * kx0r + ky0r * ky0r, r1 = kx1r * kx1r + ky1r * ky1r;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int k = out_row(m);
@@ -1183,7 +1188,7 @@ __global__ __launch_bounds__(L / 16 * 8 + L / 32 * 8) void k_spec_sr(PassArgs a,
             // 1 / |k|^2 by the hardware reciprocal (1 ulp), as in k_spec_p2
             const float k20 = r0 + kz2, k21 = r1 + kz2;
             const float mu0 = k20 > 0.f ? sg * (-scale * kx0r) * __builtin_amdgcn_rcpf(k20) : 0.f;
-            const float mu1 = sg * (-scale * kx1r) * __builtin_amdgcn_rcpf(k21);  // kx0 + 1 > 0
+            const float mu1 = k21 > 0.f ? sg * (-scale * kx1r) * __builtin_amdgcn_rcpf(k21) : 0.f;
             v0[m] = make_float2(-mu0 * v0[m].y, mu0 * v0[m].x);
             v1[m] = make_float2(-mu1 * v1[m].y, mu1 * v1[m].x);
         }
