@@ -1537,20 +1537,24 @@ struct C2rP2 {
             // transposed rows: mode k of line g = z ny + y at z zrows + k kbrows + y
             // (zrows = nxh nyp, kbrows = nyp: 128-byte rows of 16 lines at one
             // mode).  The tile's 16 lines share a plane (ny is a multiple of 16).
-            // Item f: line l = f & 15 (lanes along the lines of a row), mode
-            // k = f >> 4 (k < M/2); it holds X[k] and X[M-k] of that line, and
-            // threads 0..15 hold X[M/2] of line tv.
+            // Item f: line pair pr = f & 7 (8 lanes of 16 bytes along a row), mode
+            // k = f >> 3 (k < M/2); it holds X[k] and X[M-k] of both lines, as the
+            // blocked items do, and threads 0..15 hold X[M/2] of line tv.
             const int g0 = 16 * t;
             const int z0 = g0 / a.ny;
             const int y0 = g0 - z0 * a.ny;
             const cx<float> *tb = in + (long long)z0 * a.zrows + y0;
             const long long ks = a.kbrows;
 #pragma unroll
-            for (int i = 0; i < 2 * NIT; ++i) {
+            for (int i = 0; i < NIT; ++i) {
                 const int f = tv + NT * i;
-                const int l = f & 15, k = f >> 4;
-                xk[i] = gld<streamed<LD_C2R>()>(tb + k * ks + l);
-                xm[i] = gld<streamed<LD_C2R>()>(tb + (M - k) * ks + l);
+                const int pr = f & 7, k = f >> 3;
+                const float4 u = gld<streamed<LD_C2R>()>(reinterpret_cast<const float4 *>(tb + k * ks + 2 * pr));
+                const float4 w = gld<streamed<LD_C2R>()>(reinterpret_cast<const float4 *>(tb + (M - k) * ks + 2 * pr));
+                xk[2 * i] = make_float2(u.x, u.y);
+                xk[2 * i + 1] = make_float2(u.z, u.w);
+                xm[2 * i] = make_float2(w.x, w.y);
+                xm[2 * i + 1] = make_float2(w.z, w.w);
             }
             if (tv < 16) xh = gld<streamed<LD_C2R>()>(tb + (M / 2) * ks + tv);
             return;
@@ -1600,23 +1604,13 @@ struct C2rP2 {
     // The caller synchronises before the transform reads the tile.
     __device__ __forceinline__ void split(const cx<float> (&pk)[2 * NIT], const cx<float> (&pm)[2 * NIT], float2 ph,
                                           int tv) const {
-        if constexpr (TR) {  // one line per item: its half of the slot of its line pair
-            float2 *b2 = reinterpret_cast<float2 *>(buf);
-#pragma unroll
-            for (int i = 0; i < 2 * NIT; ++i) {
-                const int f = tv + NT * i;
-                const int l = f & 15, k = f >> 4;
-                float2 Ak = pk[i], Am = pm[i];
-                if (k == 0) Ak.y = Am.y = 0.f;
-                const cx<float> w = spl[k];
-                b2[2 * p2_slot<TC>(k, l >> 1) + (l & 1)] = zb(Ak, Am, make_float2(w.x, -w.y));
-                if (k != 0) b2[2 * p2_slot<TC>(M - k, l >> 1) + (l & 1)] = zb(Am, Ak, make_float2(-w.x, -w.y));
-            }
-        } else {
+        {
 #pragma unroll
         for (int i = 0; i < NIT; ++i) {
             const int f = tv + NT * i;
-            const int k = ((f >> 7) << 4) + (f & 15), pr = (f >> 4) & 7;
+            // the item's mode and line pair (blocked or transposed rows, as in load())
+            const int k = TR ? f >> 3 : ((f >> 7) << 4) + (f & 15);
+            const int pr = TR ? f & 7 : (f >> 4) & 7;
             float2 Ak = pk[2 * i], Bk = pk[2 * i + 1];
             float2 Am = pm[2 * i], Bm = pm[2 * i + 1];
             if (k == 0) Ak.y = Bk.y = Am.y = Bm.y = 0.f;
