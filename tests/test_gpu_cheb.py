@@ -80,7 +80,8 @@ def test_spectral_step_matches_oracle(shape, stride1):
     assert rel(got, ref) < 1e-12
 
 
-FUSED = [(129, 6, 20), (257, 8, 12), (257, 5, 36), (257, 32, 512), (513, 5, 36), (1025, 3, 16), (2049, 2, 6)]
+FUSED = [(129, 6, 20), (257, 8, 12), (257, 5, 36), (257, 32, 512), (257, 16, 1024), (257, 16, 2048), (513, 5, 36),
+         (1025, 3, 16), (2049, 2, 6)]
 UNFUSED = [(17, 16, 16), (33, 24, 20), (65, 10, 12)]  # other extension lengths: Z, product, Z as three passes
 
 
