@@ -45,7 +45,7 @@ SHAPES = [
     (40, 24, 1024),
     # transposed workspace (STRIDE1, ny a multiple of 16 up to 512): both chains in FP32,
     # FP64 backward (and forward at nx = 512); tiles of 16 lines cross z planes at ny = 16
-    (4, 48, 512), (5, 32, 1024), (3, 16, 2048), (2, 512, 512),
+    (4, 48, 512), (5, 32, 1024), (3, 16, 2048), (2, 512, 512), (1, 16, 512), (7, 64, 1024),
     (1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 5, 3), (3, 1, 4),
 ]
 
