@@ -417,6 +417,18 @@ def COPY_BYTES(n: int) -> int:
     return 4 * n ** 3
 
 
+def forward_errors(pairs):
+    """Part of the CPU-baseline leg: relative L2 error of GPU forward outputs (STRIDE1 Z-pencils) against
+    the FP64 oracle's forward transform of the same real inputs; pairs: {name: (input, output)}."""
+    import oracle
+
+    errs = {}
+    for name, (u, got) in pairs.items():
+        ref = oracle.to_stride1(oracle.r2c3d(u))
+        errs[name] = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+    return errs
+
+
 def cpu_baseline(n: int, u=None, forward_outputs=None):
     """The oracle, untuned, on one forward+backward pair of an n^3 GRF (the benchmark's own input if given).
 
@@ -551,6 +563,9 @@ def other_grid_timings(pf, args, dev, stream):
                                "alg_GBps": plan.pass_bytes(d, i) / (pms * 1e-3) / 1e9})
         plan.set_timing(False)
         rec["passes"] = passes
+        # the intermediate between the passes of each direction: blocked rows or the transposed workspace
+        rec["workspace_layout"] = {dn: ("transposed" if plan.workspace_layout(d) == pf.PF_WS_TRANSPOSED else "blocked")
+                                   for d, dn in ((pf.PF_DIR_FORWARD, "fwd"), (pf.PF_DIR_BACKWARD, "bwd"))}
         out[f"{nx}x{ny}x{nz}"] = rec
         plan.destroy()
     return out
@@ -671,14 +686,10 @@ def f64_timing(pf, args, dev, stream, n=512, check=True):
            "frac_of_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "passes": passes}
     rt = (torch.linalg.vector_norm(r / N - u) / torch.linalg.vector_norm(u)).item()
     out["round_trip_rel_l2"] = rt
-    if check:
-        import oracle
-
+    if check:  # host copies of the input and forward output, compared in the CPU-baseline leg
         plan.ftran(u, U)
         torch.cuda.synchronize()
-        ref = oracle.to_stride1(oracle.r2c3d(u.cpu().numpy()))
-        got = U.cpu().numpy()
-        out["rel_l2_fwd_vs_fp64_oracle"] = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+        out["_check"] = {"512^3": (u.cpu().numpy(), U.cpu().numpy())}
     plan.destroy()
     return out
 
@@ -787,18 +798,12 @@ def batch_timing(pf, args, dev, stream, count=64, seed=4, check=True):
             out["modes"][f"{tname}_{mname}"] = {"ms_per_pair": ms, "gflops": flops / (ms * 1e-3) / 1e9,
                                                 "alg_GBps": nbytes / (ms * 1e-3) / 1e9,
                                                 "transforms_per_s": count / (ms * 1e-3)}
-        if check and tname == "default":
-            import oracle
-
+        if check and tname == "default":  # host copies of a sample, compared in the CPU-baseline leg
             b.set_mode(pf.PF_BATCH_FUSED)
             b.ftran(R, C)
             torch.cuda.synchronize()
-            errs = {}
-            for i in sorted(set([0, 1, 2, int(max(range(count), key=lambda j: Ns[j]))])):
-                ref = oracle.to_stride1(oracle.r2c3d(b.view(R, 0, i).cpu().numpy()))
-                got = b.view(C, 1, i).cpu().numpy()
-                errs["x".join(map(str, dims[i]))] = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
-            out["rel_l2_fwd_vs_fp64_oracle"] = errs
+            out["_check"] = {"x".join(map(str, dims[i])): (b.view(R, 0, i).cpu().numpy(), b.view(C, 1, i).cpu().numpy())
+                             for i in sorted(set([0, 1, 2, int(max(range(count), key=lambda j: Ns[j]))]))}
         b.destroy()
     return out
 
@@ -1048,9 +1053,14 @@ def main():
 
     cpu = None
     errs = {}
-    if not args.no_cpu_baseline:
+    f64_check, batch_check = f64.pop("_check", None), batched.pop("_check", None)
+    if not args.no_cpu_baseline:  # the CPU-baseline leg: the oracle's timing and every oracle comparison
         cpu, errs = cpu_baseline(min(args.cpu_n, n), u_host, fwd_host)
-    del u_host, fwd_host
+        if f64_check:
+            f64["rel_l2_fwd_vs_fp64_oracle"] = forward_errors(f64_check)["512^3"]
+        if batch_check:
+            batched["rel_l2_fwd_vs_fp64_oracle"] = forward_errors(batch_check)
+    del u_host, fwd_host, f64_check, batch_check
     for name in mfma:
         mfma[name]["rel_l2_fwd_vs_fp64_oracle"] = errs.get(name)
 
