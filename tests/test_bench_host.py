@@ -169,3 +169,15 @@ def test_mfma_summary_per_wave_and_busy_fraction(tmp_root):
     row = next(line for line in text.splitlines() if line.startswith(name)).split()
     assert row[-4] == "12.0" and row[-3] == "5.00%" and row[-2] == "300.0" and row[-1] == "20.0"
     assert "command: CMD" in text
+
+
+def test_more_than_one_gpu_is_refused():
+    """One GPU only: --gpus N > 1 exits with status 2 and says so, before touching a GPU."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
